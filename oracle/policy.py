@@ -1,0 +1,179 @@
+"""Oracle of the shared population policy and of the PPO learner.
+
+TEST INFRASTRUCTURE: see the package docstring.
+
+The paper trains every population agent with one shared actor-critic network
+(Sec. 4 "Experimental details": all population agents share the weights of
+the policy and value networks; PPO, Table 2) and masks invalid actions to
+probability zero (Sec. 3 "Action masking").  The network here is the one the
+synthetic workload names: d_in -> H -> H -> (A logits, 1 value), ReLU.
+Weights are the bf16-rounded values of the float32 inputs; the arithmetic
+is float64 throughout, with no blocking or fusion.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+
+def bf16_round(x) -> np.ndarray:
+    """Round float32 values to the nearest bfloat16 (ties to even), as float32."""
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).reshape(a.shape)
+
+
+def bf16_weights(w: dict) -> dict:
+    """The values the network computes with: bf16 matrices, float32 biases."""
+    out = {}
+    for k, v in w.items():
+        out[k] = bf16_round(v).astype(np.float64) if k.startswith("W") else np.asarray(v, np.float64)
+    return out
+
+
+def unpack_mask(mask_words: np.ndarray, A: int) -> np.ndarray:
+    """Bit a of word a // 32 says whether action a is allowed."""
+    m = np.asarray(mask_words, dtype=np.uint32)
+    a = np.arange(A)
+    return ((m[:, a // 32] >> (a % 32).astype(np.uint32)) & 1).astype(bool)
+
+
+def mlp(obs: np.ndarray, w: dict):
+    """Logits [M, A] and values [M] of the two-hidden-layer ReLU network."""
+    x = np.asarray(obs, dtype=np.float64)
+    h1 = np.maximum(x @ w["W1"] + w["b1"], 0.0)
+    h2 = np.maximum(h1 @ w["W2"] + w["b2"], 0.0)
+    out = h2 @ w["W3"] + w["b3"]
+    return out[:, :-1], out[:, -1]
+
+
+def masked_log_softmax(logits: np.ndarray, allowed: np.ndarray) -> np.ndarray:
+    """log pi(a) over the allowed actions; -inf for masked ones."""
+    z = np.where(allowed, logits, -np.inf)
+    zmax = z.max(axis=1, keepdims=True)
+    lse = zmax + np.log(np.exp(z - zmax).sum(axis=1, keepdims=True))
+    return z - lse
+
+
+def entropy(logp: np.ndarray) -> np.ndarray:
+    finite = np.isfinite(logp)
+    safe = np.where(finite, logp, 0.0)
+    return -(np.exp(safe) * safe * finite).sum(axis=1)
+
+
+def sample_inverse_cdf(logp: np.ndarray, u: np.ndarray):
+    """Action = the first index whose cumulative probability exceeds u.
+    Also returns the distance of u from the nearest cumulative boundary, so
+    a test can tell a decision that rounding could flip from one it cannot."""
+    p = np.exp(logp)
+    cdf = np.cumsum(p, axis=1)
+    M, A = p.shape
+    act = np.empty(M, np.int64)
+    margin = np.empty(M)
+    for m in range(M):
+        uu = u[m] * cdf[m, -1]
+        idx = int(np.searchsorted(cdf[m], uu, side="right"))
+        idx = min(idx, A - 1)
+        while p[m, idx] == 0.0 and idx > 0:  # never land on a masked action
+            idx -= 1
+        act[m] = idx
+        lo = cdf[m, idx - 1] if idx > 0 else 0.0
+        margin[m] = min(abs(uu - lo), abs(cdf[m, idx] - uu))
+    return act, margin
+
+
+def uniform_from_word(w: np.ndarray) -> np.ndarray:
+    """u = (top 24 bits + 1/2) / 2^24, exactly representable in float32."""
+    top = (np.asarray(w, dtype=np.uint64) >> np.uint64(40)).astype(np.float64)
+    return (top + 0.5) / 16777216.0
+
+
+def policy_forward(obs, mask_words, w_f32: dict, u: np.ndarray):
+    """Sampled actions, their log-probabilities, values and entropies."""
+    w = bf16_weights(w_f32)
+    A = w["W3"].shape[1] - 1
+    logits, value = mlp(obs, w)
+    logp = masked_log_softmax(logits, unpack_mask(mask_words, A))
+    act, margin = sample_inverse_cdf(logp, u)
+    return dict(logits=logits, value=value, logp_all=logp, act=act,
+                logp=logp[np.arange(len(act)), act], entropy=entropy(logp), margin=margin)
+
+
+# ---------------------------------------------------------------------------
+# PPO (Schulman et al. 2017) as configured in Table 2: clipped surrogate,
+# clipped value loss with coefficient c_v, entropy bonus c_e, GAE(gamma, lambda).
+# ---------------------------------------------------------------------------
+def gae(rew, val, done, last_val, gamma: float, lam: float):
+    """Generalised advantage estimation, reverse over time.
+    rew, val, done: [T, M]; done[t] = 1 when step t ended an episode;
+    last_val: [M], the value of the state after the last step."""
+    rew = np.asarray(rew, np.float64)
+    val = np.asarray(val, np.float64)
+    done = np.asarray(done, np.float64)
+    T = rew.shape[0]
+    adv = np.zeros_like(rew)
+    nxt_adv = np.zeros(rew.shape[1])
+    nxt_val = np.asarray(last_val, np.float64)
+    for t in range(T - 1, -1, -1):
+        nonterm = 1.0 - done[t]
+        delta = rew[t] + gamma * nxt_val * nonterm - val[t]
+        nxt_adv = delta + gamma * lam * nonterm * nxt_adv
+        adv[t] = nxt_adv
+        nxt_val = val[t]
+    return adv, adv + val
+
+
+def ppo_loss_torch(params: dict, obs, allowed, act, logp_old, val_old, adv, ret, hp: dict):
+    """PPO minibatch loss in float64 torch ops; returns (loss, terms).
+
+    Advantages are normalised over the minibatch (population standard
+    deviation, + 1e-8).  loss = mean(-min(rho A, clip(rho) A))
+                              + c_v mean(1/2 max((V-R)^2, (Vclip-R)^2))
+                              - c_e mean(H)."""
+    x = torch.as_tensor(np.asarray(obs, np.float64))
+    h1 = torch.relu(x @ params["W1"] + params["b1"])
+    h2 = torch.relu(h1 @ params["W2"] + params["b2"])
+    out = h2 @ params["W3"] + params["b3"]
+    logits, v = out[:, :-1], out[:, -1]
+    allowed_t = torch.as_tensor(allowed)
+    z = logits.masked_fill(~allowed_t, float("-inf"))
+    logp_all = torch.log_softmax(z, dim=1)
+    p = torch.exp(logp_all)
+    ent = -(p * logp_all.masked_fill(~allowed_t, 0.0)).sum(dim=1)
+    a = torch.as_tensor(np.asarray(act, np.int64))
+    logp = logp_all.gather(1, a[:, None])[:, 0]
+    A = torch.as_tensor(np.asarray(adv, np.float64))
+    A = (A - A.mean()) / (torch.sqrt(((A - A.mean()) ** 2).mean()) + 1e-8)
+    ratio = torch.exp(logp - torch.as_tensor(np.asarray(logp_old, np.float64)))
+    eps = hp["clip"]
+    pg = -torch.minimum(ratio * A, torch.clamp(ratio, 1.0 - eps, 1.0 + eps) * A).mean()
+    vo = torch.as_tensor(np.asarray(val_old, np.float64))
+    R = torch.as_tensor(np.asarray(ret, np.float64))
+    v_clip = vo + torch.clamp(v - vo, -hp["vclip"], hp["vclip"])
+    vl = 0.5 * torch.maximum((v - R) ** 2, (v_clip - R) ** 2).mean()
+    en = ent.mean()
+    loss = pg + hp["vf_coef"] * vl - hp["ent_coef"] * en
+    return loss, dict(pg=pg, vf=vl, ent=en)
+
+
+def ppo_grads(w_f32: dict, obs, mask_words, act, logp_old, val_old, adv, ret, hp: dict):
+    """Float64 loss and autograd gradients with respect to the bf16 weights."""
+    w = bf16_weights(w_f32)
+    A = w["W3"].shape[1] - 1
+    params = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in w.items()}
+    loss, terms = ppo_loss_torch(params, obs, unpack_mask(mask_words, A), act, logp_old, val_old, adv,
+                                 ret, hp)
+    loss.backward()
+    return (float(loss.detach()), {k: float(v.detach()) for k, v in terms.items()},
+            {k: params[k].grad.numpy().copy() for k in params})
+
+
+def adam_step(w, g, m, v, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba 2015) with bias correction; returns new (w, m, v)."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return w - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -1,0 +1,24 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+@pytest.fixture(scope="session")
+def gpu_lib():
+    """The GPU library, loaded from the in-tree build.  Fails loudly when the
+    HIP extension is missing: there is no CPU fallback."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test collected without a visible GPU")
+    from paper_2410_22165_amd import binding
+    return binding.lib()
