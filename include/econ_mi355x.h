@@ -1,0 +1,182 @@
+/*
+ * econ_mi355x.h -- C ABI of the gfx950 (MI355X) batched-economy library.
+ *
+ * The library advances E independent EconoJax economies (Ponse et al.,
+ * "EconoJax: A Fast & Scalable Economic Simulation in JAX", AAMAS 2025), each
+ * with n_e population agents and one government agent, and runs the shared
+ * population policy network and its PPO learner on the GPU.
+ *
+ * Conventions (all entry points):
+ *   - Every call returns an int: EJ_OK (0) or a negative EJ_E* code.  No C++
+ *     exception crosses the ABI.  ej_strerror() names a code;
+ *     ej_last_hip_error() returns the hipError_t behind the last EJ_EHIP of
+ *     the calling thread.
+ *   - Arrays named d_* are DEVICE pointers owned by the caller; the library
+ *     never frees them and never keeps them beyond the call.  Arrays named h_*
+ *     are host pointers.  State and scratch owned by a handle live inside it
+ *     and are freed by the matching destroy call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously on it; only calls documented as
+ *     synchronous (get/set state, status) wait for it.
+ *   - Per-agent arrays use "rows": the agents of economy e are rows
+ *     row0[e] .. row0[e] + n_e - 1, with row0 the prefix sum of the
+ *     populations (economy-major, agent-minor).  M = total rows.
+ *   - Handles are not thread-safe; calls on one handle must be serialised.
+ */
+#ifndef ECON_MI355X_H
+#define ECON_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EJ_OK 0
+#define EJ_EINVAL (-1)       /* bad argument or configuration */
+#define EJ_ENOMEM (-2)       /* device or host allocation failed */
+#define EJ_EHIP (-3)         /* a HIP runtime call failed; see ej_last_hip_error() */
+#define EJ_EUNSUPPORTED (-4) /* configuration outside the limits below */
+
+#define EJ_MAX_N 1024 /* agents per economy */
+#define EJ_MAX_R 8    /* resource types */
+#define EJ_MAX_P 128  /* price levels */
+#define EJ_MAX_K 16   /* tax brackets */
+#define EJ_MAX_X 32   /* order lifetime in steps */
+#define EJ_GOV_LEVELS 21 /* tax levels 0 %, 5 %, ..., 100 % */
+
+/* Observation feature-group scales (float multipliers applied before the
+ * bf16 rounding of the population observation). */
+typedef struct ej_obs_scales {
+    float coin, labor, orders, res, skill, rate, phase, price, count;
+} ej_obs_scales;
+
+/* Economy parameters.  Sec. 3 of the paper ("Population Agents",
+ * "Government Agent", "Setting tax rates") and Table 2 define them.
+ *   E            number of economies
+ *   N            largest population (every n_e <= N <= EJ_MAX_N)
+ *   R, P         resource types, price levels (prices[0..P-1], strictly increasing)
+ *   X            order lifetime: an order takes part in X clearings (Table 2: 30)
+ *   max_orders   live-order limit per agent (Table 2: 15)
+ *   P_tax, K     tax period in steps (Table 2: 100); number of brackets
+ *                (K = 0 disables taxes: the free market); cutoffs[0..K-2]
+ *   T            episode length (Table 2: 1000); economies reset automatically
+ *   R_kappa, R_d crafting needs R_kappa units of each of R_d types
+ *   kappa_c      crafting pays (SC * kappa_c) coin, SC the crafting skill
+ *   start_coin   coin at reset (Table 2: 15)
+ *   labor_*      labor per action in units of 1/20 (Table 2: 20, 20, 1)
+ *   allow_noop   NOOP allowed (Table 2: true)
+ *   eta, omega   utility curvature (Eq. (1), 0.27) and equality weight (Eq. (4), 1)
+ *   seed         key of the counter-based generator for skills, gathering
+ *                luck and order tie keys */
+typedef struct ej_env_config {
+    int32_t E, N, R, P, X, max_orders, P_tax, K, T;
+    int32_t R_kappa, R_d, kappa_c, start_coin;
+    int32_t labor_gather, labor_craft, labor_trade;
+    int32_t allow_noop;
+    int32_t reserved0;
+    double eta, omega;
+    uint64_t seed;
+    int32_t prices[EJ_MAX_P];
+    int32_t cutoffs[EJ_MAX_K];
+    ej_obs_scales scales;
+} ej_env_config;
+
+/* Sizes derived from a configuration (filled by ej_env_dims). */
+typedef struct ej_env_dims_t {
+    int64_t M;          /* total agent rows */
+    int32_t A;          /* population actions: 2 + R + 2 R P (Sec. 5 counts 30 and 86) */
+    int32_t mask_words; /* ceil(A / 32) uint32 words of action-mask bits per row */
+    int32_t D;          /* population observation features: 7 + 7 R + K */
+    int32_t D_stride;   /* bf16 elements per observation row (D rounded up to 8) */
+    int32_t D_gov;      /* government observation floats: 3 (3 + R) + K + 1 + 4 R */
+    int32_t K;          /* government action entries per economy */
+} ej_env_dims_t;
+
+typedef struct ej_env ej_env;
+
+/* Host-side view of the state of every economy, in a representation-neutral
+ * form (every pointer is a HOST array supplied by the caller):
+ *   t[E], ep[E]                    step within the episode, episode index
+ *   rates[E * K]                   current tax levels (0..20)
+ *   coin_inv, coin_esc, labor, snap, sc  [M]  coin in inventory / escrow,
+ *                                  labor (1/20 units), coin at the start of the
+ *                                  tax period, crafting skill (Q16.16)
+ *   res_inv, res_esc, sg           [R * M]  resources in inventory / escrow,
+ *                                  gathering skill (Q16.16), resource-major
+ *   orders                         [X * M]  live order of each (slot, row):
+ *                                  -1, or side + 2 (r + R p); side 0 = buy.
+ *                                  Slot s holds the order placed at the step
+ *                                  t0 with t0 mod X == s. */
+typedef struct ej_state_view {
+    int32_t *t, *ep, *rates;
+    int32_t *coin_inv, *coin_esc, *labor, *snap, *sc;
+    int32_t *res_inv, *res_esc, *sg;
+    int32_t *orders;
+} ej_state_view;
+
+const char* ej_strerror(int code);
+int ej_last_hip_error(void);
+
+/* Validates `cfg`, allocates the device state of E economies and places
+ * them at the reset state of episode 0 (synchronously).  h_n_per_env (host,
+ * [E], nullable) gives uneven populations; NULL means n_e = N for all.
+ * Errors: EJ_EINVAL (inconsistent values), EJ_EUNSUPPORTED (limits above,
+ * or R*2*P*X > 8192 order-book buckets), EJ_ENOMEM, EJ_EHIP. */
+int ej_env_create(const ej_env_config* cfg, const int32_t* h_n_per_env, ej_env** out);
+int ej_env_destroy(ej_env* env);
+int ej_env_dims(const ej_env* env, ej_env_dims_t* out);
+/* Row offsets row0[0..E] (host copy owned by the handle, valid until destroy). */
+const int32_t* ej_env_row_offsets(const ej_env* env);
+
+/* Resets every economy to step 0 of `episode`: coin = start_coin, empty
+ * inventories, escrow and book; skills drawn from Pareto(alpha = 4, x_m = 1)
+ * clipped to 5 (Sec. 4 "Experimental details" initialises skills with a
+ * Pareto distribution), keyed (seed, economy, episode, agent). */
+int ej_env_reset(ej_env* env, int32_t episode, void* stream);
+
+/* One step of every economy (Sec. 3; Eqs. (1)-(5)):
+ *   d_act     [M] int32 population actions: 0 NOOP, 1..R gather r-1, R+1 craft,
+ *             R+2 + r P + p buy (r, p), R+2 + R P + r P + p sell (r, p).
+ *             Actions outside the step-start action mask become NOOP (no labor)
+ *             and are counted (ej_env_status).
+ *   d_gov     [E * K] int32 government levels 0..20, read at the first step of a
+ *             tax period (t mod P_tax == 0); out-of-range levels keep the old rate.
+ *   d_rew     [M] float  u(t+1) - u(t) (Eq. (1), Eq. (2)), difference in fp64
+ *   d_gov_rew [E] float  change of Eq * Prod (Eqs. (3)-(5))
+ *   d_done    [M] uint8  1 when the step ended the episode (the economy then
+ *             restarts at the next episode before the call returns)
+ *   d_obs     [M * D_stride] bf16 bits, nullable: the observation after the step
+ *   d_mask    [M * mask_words] uint32, nullable: the action mask after the step
+ * One workgroup per economy; all inputs are read before any state changes. */
+int ej_env_step(ej_env* env, const int32_t* d_act, const int32_t* d_gov, float* d_rew, float* d_gov_rew,
+                uint8_t* d_done, uint16_t* d_obs, uint32_t* d_mask, void* stream);
+
+/* Observation of the current state.  d_obs / d_mask as in ej_env_step (both
+ * required); d_gov_obs [E * D_gov] float, nullable: per-feature mean, std and
+ * lower median over the population of (coin, period income, labor, each
+ * resource inventory), the tax levels, the period phase and the market
+ * statistics (best bid, best ask, #bids, #asks per resource).  Sec. 3
+ * "Action masking" and the Fig. 1 caption (government sees population
+ * statistics); Appendix A (market statistics). */
+int ej_env_observe(ej_env* env, uint16_t* d_obs, uint32_t* d_mask, float* d_gov_obs, void* stream);
+
+/* Synthetic workload actions for the current step of every economy: uniform
+ * over the A population actions, keyed (act_seed, economy, episode, step,
+ * agent), and uniform government levels over 0..20. */
+int ej_env_random_actions(ej_env* env, uint64_t act_seed, int32_t* d_act, int32_t* d_gov, void* stream);
+
+/* Synchronous copies of the whole state to / from host arrays (checkpoint
+ * and resume; parity checks).  set_state requires a state reachable by the
+ * rules: orders with t - X < t0 < t and an uncrossed book per resource. */
+int ej_env_get_state(ej_env* env, const ej_state_view* h_view, void* stream);
+int ej_env_set_state(ej_env* env, const ej_state_view* h_view, void* stream);
+
+/* Synchronous: number of population actions and government levels rejected
+ * since create (summed over economies). */
+int ej_env_status(ej_env* env, int64_t* h_invalid_actions, int64_t* h_invalid_gov, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ECON_MI355X_H */

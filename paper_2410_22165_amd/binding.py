@@ -1,0 +1,240 @@
+"""ctypes binding of libecon_mi355x.so (argument marshalling only).
+
+Every step of the path runs in the library's HIP kernels; this module turns
+torch tensors into device pointers and HIP streams, and raises on any error
+code.  It loads the in-tree build and fails loudly when it is missing: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libecon_mi355x.so")
+
+EJ_MAX_P, EJ_MAX_K = 128, 16
+
+
+class EjObsScales(C.Structure):
+    _fields_ = [(n, C.c_float) for n in ("coin", "labor", "orders", "res", "skill", "rate", "phase", "price",
+                                          "count")]
+
+
+class EjEnvConfig(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("E", "N", "R", "P", "X", "max_orders", "P_tax", "K", "T", "R_kappa",
+                                          "R_d", "kappa_c", "start_coin", "labor_gather", "labor_craft",
+                                          "labor_trade", "allow_noop", "reserved0")] + [
+        ("eta", C.c_double), ("omega", C.c_double), ("seed", C.c_uint64),
+        ("prices", C.c_int32 * EJ_MAX_P), ("cutoffs", C.c_int32 * EJ_MAX_K), ("scales", EjObsScales)]
+
+
+class EjEnvDims(C.Structure):
+    _fields_ = [("M", C.c_int64), ("A", C.c_int32), ("mask_words", C.c_int32), ("D", C.c_int32),
+                ("D_stride", C.c_int32), ("D_gov", C.c_int32), ("K", C.c_int32)]
+
+
+_STATE_FIELDS = ("t", "ep", "rates", "coin_inv", "coin_esc", "labor", "snap", "sc", "res_inv", "res_esc", "sg",
+                 "orders")
+
+
+class EjStateView(C.Structure):
+    _fields_ = [(n, C.POINTER(C.c_int32)) for n in _STATE_FIELDS]
+
+
+class EconError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (in-tree build).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise EconError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+    L.ej_strerror.argtypes = [C.c_int]
+    L.ej_strerror.restype = C.c_char_p
+    L.ej_last_hip_error.restype = C.c_int
+    L.ej_env_create.argtypes = [C.POINTER(EjEnvConfig), C.POINTER(i32), C.POINTER(vp)]
+    L.ej_env_destroy.argtypes = [vp]
+    L.ej_env_dims.argtypes = [vp, C.POINTER(EjEnvDims)]
+    L.ej_env_row_offsets.argtypes = [vp]
+    L.ej_env_row_offsets.restype = C.POINTER(i32)
+    L.ej_env_reset.argtypes = [vp, i32, vp]
+    L.ej_env_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.ej_env_observe.argtypes = [vp, vp, vp, vp, vp]
+    L.ej_env_random_actions.argtypes = [vp, u64, vp, vp, vp]
+    L.ej_env_get_state.argtypes = [vp, C.POINTER(EjStateView), vp]
+    L.ej_env_set_state.argtypes = [vp, C.POINTER(EjStateView), vp]
+    L.ej_env_status.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), vp]
+    _declare_learner(L)
+    _lib = L
+    return L
+
+
+def _declare_learner(L):
+    """Signatures of the policy / learner entry points (present once built)."""
+    vp, i32, i64, u64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_float
+    table = {
+        "ej_policy_forward": [vp, vp, vp, i64, u64, u64, vp, vp, vp, vp, vp, vp],
+        "ej_gae": [vp, vp, vp, vp, i32, i64, f32, f32, vp, vp, vp],
+        "ej_ppo_backward": [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i64, i64, vp, vp, vp, vp],
+        "ej_adam": [vp, vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp],
+        "ej_mlp_sync_weights": [vp, vp, vp],
+    }
+    for name, args in table.items():
+        fn = getattr(L, name, None)
+        if fn is not None:
+            fn.argtypes = args
+
+
+def check(rc: int, what: str = ""):
+    if rc != 0:
+        msg = lib().ej_strerror(rc).decode()
+        hip = lib().ej_last_hip_error()
+        raise EconError(f"{what}: {msg} (code {rc}, hip error {hip})")
+
+
+def ptr(t) -> int | None:
+    """Device pointer of a torch tensor (None passes NULL)."""
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def stream_ptr(stream=None) -> int | None:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def make_env_config(cfg: dict, scales: dict) -> EjEnvConfig:
+    c = EjEnvConfig()
+    for n in ("E", "N", "R", "P", "X", "max_orders", "P_tax", "K", "T", "R_kappa", "R_d", "kappa_c",
+              "start_coin", "labor_gather", "labor_craft", "labor_trade", "allow_noop"):
+        setattr(c, n, int(cfg[n]))
+    c.eta, c.omega, c.seed = float(cfg["eta"]), float(cfg["omega"]), int(cfg.get("seed", 0))
+    for i, v in enumerate(cfg["prices"]):
+        c.prices[i] = int(v)
+    for i, v in enumerate(cfg["cutoffs"]):
+        c.cutoffs[i] = int(v)
+    c.scales = EjObsScales(**{k: float(v) for k, v in scales.items()})
+    return c
+
+
+class Env:
+    """A batch of E economies on the GPU (thin owner of an ej_env handle)."""
+
+    def __init__(self, cfg: dict, scales: dict, n_per_env=None):
+        import torch
+        self.cfg = dict(cfg)
+        self._c = make_env_config(cfg, scales)
+        h = C.c_void_p()
+        arr = None
+        if n_per_env is not None:
+            arr = np.ascontiguousarray(n_per_env, dtype=np.int32)
+            check(lib().ej_env_create(C.byref(self._c), arr.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(h)),
+                  "ej_env_create")
+        else:
+            check(lib().ej_env_create(C.byref(self._c), None, C.byref(h)), "ej_env_create")
+        self._h = h
+        d = EjEnvDims()
+        check(lib().ej_env_dims(h, C.byref(d)), "ej_env_dims")
+        self.M, self.A, self.W, self.D, self.Ds, self.Dg, self.K = (int(d.M), d.A, d.mask_words, d.D, d.D_stride,
+                                                                      d.D_gov, d.K)
+        self.E = int(cfg["E"])
+        ro = lib().ej_env_row_offsets(h)
+        self.row_offsets = np.array([ro[i] for i in range(self.E + 1)], np.int64)
+        self.device = torch.device("cuda")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ej_env_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- buffers ----
+    def buffers(self):
+        import torch
+        dev = self.device
+        return dict(
+            act=torch.zeros(self.M, dtype=torch.int32, device=dev),
+            gov=torch.zeros(max(self.E * self.K, 1), dtype=torch.int32, device=dev),
+            rew=torch.zeros(self.M, dtype=torch.float32, device=dev),
+            gov_rew=torch.zeros(self.E, dtype=torch.float32, device=dev),
+            done=torch.zeros(self.M, dtype=torch.uint8, device=dev),
+            obs=torch.zeros((self.M, self.Ds), dtype=torch.int16, device=dev),
+            mask=torch.zeros((self.M, self.W), dtype=torch.int32, device=dev),
+            gov_obs=torch.zeros((self.E, self.Dg), dtype=torch.float32, device=dev),
+        )
+
+    # ---- entry points ----
+    def reset(self, episode: int = 0, stream=None):
+        check(lib().ej_env_reset(self._h, episode, stream_ptr(stream)), "ej_env_reset")
+
+    def step(self, act, gov, rew, gov_rew, done, obs=None, mask=None, stream=None):
+        check(lib().ej_env_step(self._h, ptr(act), ptr(gov), ptr(rew), ptr(gov_rew), ptr(done), ptr(obs), ptr(mask),
+                                stream_ptr(stream)), "ej_env_step")
+
+    def observe(self, obs, mask, gov_obs=None, stream=None):
+        check(lib().ej_env_observe(self._h, ptr(obs), ptr(mask), ptr(gov_obs), stream_ptr(stream)), "ej_env_observe")
+
+    def random_actions(self, act_seed: int, act, gov, stream=None):
+        check(lib().ej_env_random_actions(self._h, act_seed, ptr(act), ptr(gov), stream_ptr(stream)),
+              "ej_env_random_actions")
+
+    def status(self, stream=None):
+        a, g = C.c_int64(), C.c_int64()
+        check(lib().ej_env_status(self._h, C.byref(a), C.byref(g), stream_ptr(stream)), "ej_env_status")
+        return a.value, g.value
+
+    def _view(self, arrays):
+        v = EjStateView()
+        for n in _STATE_FIELDS:
+            setattr(v, n, arrays[n].ctypes.data_as(C.POINTER(C.c_int32)))
+        return v
+
+    def get_state(self, stream=None) -> dict:
+        E, M, R, X, K = self.E, self.M, self.cfg["R"], self.cfg["X"], self.K
+        a = dict(t=np.zeros(E, np.int32), ep=np.zeros(E, np.int32), rates=np.zeros((E, max(K, 1)), np.int32))
+        for n in ("coin_inv", "coin_esc", "labor", "snap", "sc"):
+            a[n] = np.zeros(M, np.int32)
+        for n in ("res_inv", "res_esc", "sg"):
+            a[n] = np.zeros((R, M), np.int32)
+        a["orders"] = np.zeros((X, M), np.int32)
+        v = self._view(a)
+        check(lib().ej_env_get_state(self._h, C.byref(v), stream_ptr(stream)), "ej_env_get_state")
+        a["rates"] = a["rates"][:, :K]
+        return a
+
+    def set_state(self, st: dict, stream=None):
+        E, K = self.E, self.K
+        a = {n: np.ascontiguousarray(st[n], dtype=np.int32) for n in _STATE_FIELDS}
+        if K == 0:
+            a["rates"] = np.zeros((E, 1), np.int32)
+        v = self._view(a)
+        check(lib().ej_env_set_state(self._h, C.byref(v), stream_ptr(stream)), "ej_env_set_state")
+
+    def env_state(self, st: dict, e: int) -> dict:
+        """The state of economy e in the oracle's per-economy layout."""
+        lo, hi = int(self.row_offsets[e]), int(self.row_offsets[e + 1])
+        out = dict(t=int(st["t"][e]), ep=int(st["ep"][e]), rates=st["rates"][e].copy())
+        for n in ("coin_inv", "coin_esc", "labor", "snap", "sc"):
+            out[n] = st[n][lo:hi].copy()
+        for n in ("res_inv", "res_esc", "sg", "orders"):
+            out[n] = st[n][:, lo:hi].copy()
+        out["n_active"] = (out["orders"] >= 0).sum(axis=0).astype(np.int32)
+        return out

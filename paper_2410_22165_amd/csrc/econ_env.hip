@@ -1,0 +1,1419 @@
+// econ_env.hip -- gfx950 kernels of the EconoJax economy step and the
+// economy half of the C ABI (ej_env_*).
+//
+// One workgroup owns one economy for the whole step.  Agent state is SoA in
+// HBM (field-major, each economy's agents contiguous and 64-byte aligned) and
+// lives in registers during the step; the order book of the economy is
+// rebuilt every step in LDS as a histogram over (resource, side, price,
+// age) buckets laid out in matching-priority order, so that exclusive scans
+// give every live order its global priority rank without sorting.
+//
+// Paper passages implemented (Ponse et al., EconoJax, AAMAS 2025):
+//   Sec. 3 "Population Agents": gathering, crafting, trading with escrow,
+//     matching priority (price, then age, then random), optional NOOP;
+//   Eq. (1)-(2): isoelastic utility minus labor, reward = utility change;
+//   Sec. 3 "Government Agent", Eqs. (3)-(5): social welfare Eq * Prod;
+//   Sec. 3 "Setting tax rates": marginal bracket tax on the period's
+//     earnings, uniform redistribution;
+//   Sec. 3 "Action masking"; Appendix A: trade price of the later order.
+#include <algorithm>
+#include <climits>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "econ_common.h"
+
+namespace econ {
+
+static thread_local int g_last_hip = 0;
+void set_last_hip_error(hipError_t e) { g_last_hip = (int)e; }
+
+// ---------------------------------------------------------------------------
+// parameters and state handed to every kernel (by value)
+// ---------------------------------------------------------------------------
+struct EnvParams {
+    int32_t N, R, P, X, max_orders, P_tax, K, T;
+    int32_t R_kappa, R_d, kappa_c, start_coin;
+    int32_t labor_gather, labor_craft, labor_trade, allow_noop;
+    int32_t A, W, D, Ds, Dg, HB;
+    double eta, omega;
+    uint64_t seed;
+    int64_t Ntot;  // stride between two state fields
+    int32_t prices[EJ_MAX_P];
+    int32_t cutoffs[EJ_MAX_K];
+    ej_obs_scales sc;
+};
+
+struct EnvState {
+    int32_t* field;          // [NF][Ntot]
+    int32_t* env_t;          // [E]
+    int32_t* env_ep;         // [E]
+    int32_t* env_rates;      // [E][K]
+    const int32_t* env_n;    // [E]
+    const int32_t* env_off;  // [E]   first state slot of the economy
+    const int32_t* env_row;  // [E+1] first row of the economy
+    int64_t* invalid;        // [E][2] rejected population actions / government levels
+};
+
+// state field indices
+__host__ __device__ inline int F_COIN_INV() { return 0; }
+__host__ __device__ inline int F_COIN_ESC() { return 1; }
+__host__ __device__ inline int F_LABOR() { return 2; }
+__host__ __device__ inline int F_SNAP() { return 3; }
+__host__ __device__ inline int F_SC() { return 4; }
+__host__ __device__ inline int F_RES_INV(int R, int r) { return 5 + r + 0 * R; }
+__host__ __device__ inline int F_RES_ESC(int R, int r) { return 5 + R + r; }
+__host__ __device__ inline int F_SG(int R, int r) { return 5 + 2 * R + r; }
+__host__ __device__ inline int F_SLOT(int R, int s) { return 5 + 3 * R + s; }
+__host__ __device__ inline int n_fields(int R, int X) { return 5 + 3 * R + X; }
+
+// packed order slot: valid | side | r (6) | p (8) | placement rank (16)
+__host__ __device__ inline uint32_t slot_pack(int side, int r, int p, int rank)
+{
+    return 0x80000000u | ((uint32_t)side << 30) | ((uint32_t)r << 24) | ((uint32_t)p << 16) | (uint32_t)rank;
+}
+__host__ __device__ inline bool slot_valid(uint32_t s) { return (s >> 31) != 0; }
+__host__ __device__ inline int slot_side(uint32_t s) { return (int)((s >> 30) & 1u); }
+__host__ __device__ inline int slot_r(uint32_t s) { return (int)((s >> 24) & 63u); }
+__host__ __device__ inline int slot_p(uint32_t s) { return (int)((s >> 16) & 255u); }
+__host__ __device__ inline int slot_rank(uint32_t s) { return (int)(s & 0xffffu); }
+
+// Pareto(4) skill in Q16.16 from one 64-bit word: x = U^(-1/4), U in (0, 1], x <= 5
+__host__ __device__ inline int32_t skill_q16(uint64_t w)
+{
+    double u = (double)((w >> 11) + 1) * (1.0 / 9007199254740992.0);
+    double x = 1.0 / sqrt(sqrt(u));
+    x = x > 5.0 ? 5.0 : x;
+    return (int32_t)(x * 65536.0 + 0.5);
+}
+
+// ---------------------------------------------------------------------------
+// per-agent registers
+// ---------------------------------------------------------------------------
+template <int RM, int XM>
+struct Agent {
+    int32_t coin_inv, coin_esc, labor, snap, sc;
+    int32_t res_inv[RM], res_esc[RM], sg[RM];
+    uint32_t slot[XM];
+};
+
+template <int RM>
+__device__ inline int32_t rget(const int32_t (&a)[RM], int r)
+{
+    int32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < RM; ++j)
+        if (j == r) v = a[j];
+    return v;
+}
+template <int RM>
+__device__ inline void radd(int32_t (&a)[RM], int r, int32_t d)
+{
+#pragma unroll
+    for (int j = 0; j < RM; ++j)
+        if (j == r) a[j] += d;
+}
+
+template <int RM, int XM>
+__device__ inline int n_active(const Agent<RM, XM>& ag, int X)
+{
+    int c = 0;
+#pragma unroll
+    for (int s = 0; s < XM; ++s)
+        if (s < X && slot_valid(ag.slot[s])) ++c;
+    return c;
+}
+
+template <int RM, int XM>
+__device__ inline void load_agent(const EnvParams& P, const EnvState& S, int64_t g, Agent<RM, XM>& ag)
+{
+    const int32_t* f = S.field;
+    const int64_t st = P.Ntot;
+    ag.coin_inv = f[F_COIN_INV() * st + g];
+    ag.coin_esc = f[F_COIN_ESC() * st + g];
+    ag.labor = f[F_LABOR() * st + g];
+    ag.snap = f[F_SNAP() * st + g];
+    ag.sc = f[F_SC() * st + g];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        if (r < P.R) {
+            ag.res_inv[r] = f[F_RES_INV(P.R, r) * st + g];
+            ag.res_esc[r] = f[F_RES_ESC(P.R, r) * st + g];
+            ag.sg[r] = f[F_SG(P.R, r) * st + g];
+        } else {
+            ag.res_inv[r] = 0;
+            ag.res_esc[r] = 0;
+            ag.sg[r] = 0;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < XM; ++s) ag.slot[s] = s < P.X ? (uint32_t)f[F_SLOT(P.R, s) * st + g] : 0u;
+}
+
+template <int RM, int XM>
+__device__ inline void store_agent(const EnvParams& P, const EnvState& S, int64_t g, const Agent<RM, XM>& ag)
+{
+    int32_t* f = S.field;
+    const int64_t st = P.Ntot;
+    f[F_COIN_INV() * st + g] = ag.coin_inv;
+    f[F_COIN_ESC() * st + g] = ag.coin_esc;
+    f[F_LABOR() * st + g] = ag.labor;
+    f[F_SNAP() * st + g] = ag.snap;
+    f[F_SC() * st + g] = ag.sc;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        if (r < P.R) {
+            f[F_RES_INV(P.R, r) * st + g] = ag.res_inv[r];
+            f[F_RES_ESC(P.R, r) * st + g] = ag.res_esc[r];
+            f[F_SG(P.R, r) * st + g] = ag.sg[r];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < XM; ++s)
+        if (s < P.X) f[F_SLOT(P.R, s) * st + g] = (int32_t)ag.slot[s];
+}
+
+// reset state of one agent at episode `ep` of economy e
+template <int RM, int XM>
+__device__ inline void reset_agent(const EnvParams& P, int e, int ep, int i, Agent<RM, XM>& ag)
+{
+    ag.coin_inv = P.start_coin;
+    ag.coin_esc = 0;
+    ag.labor = 0;
+    ag.snap = P.start_coin;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        ag.res_inv[r] = 0;
+        ag.res_esc[r] = 0;
+    }
+#pragma unroll
+    for (int s = 0; s < XM; ++s) ag.slot[s] = 0u;
+    // skill words s = 0..R-1 gathering, s = R crafting; four words per draw
+    u64x4 w = philox(P.seed, PURPOSE_SKILL, (uint64_t)e, (uint64_t)ep, (uint64_t)i, 0);
+#pragma unroll
+    for (int s = 0; s <= RM; ++s) {
+        if (s > P.R) break;
+        if (s > 0 && (s & 3) == 0) w = philox(P.seed, PURPOSE_SKILL, (uint64_t)e, (uint64_t)ep, (uint64_t)i, (uint64_t)(s >> 2));
+        int32_t q = skill_q16(word_of(w, s & 3));
+        if (s < P.R) {
+#pragma unroll
+            for (int r = 0; r < RM; ++r)
+                if (r == s) ag.sg[r] = q;
+        } else {
+            ag.sc = q;
+        }
+    }
+}
+
+// Eq. (1)
+__device__ inline double utility(int64_t coin, int32_t labor_q, double eta)
+{
+    const double one_m = 1.0 - eta;
+    return (pow((double)coin, one_m) - 1.0) / one_m - (double)labor_q / 20.0;
+}
+
+// marginal bracket tax in whole coin: floor(sum_b level_b overlap_b / 20)
+__device__ inline int64_t bracket_tax(int64_t income, const int32_t* levels, const int32_t* cutoffs, int K)
+{
+    if (income <= 0 || K <= 0) return 0;
+    int64_t acc = 0, lo = 0;
+    for (int b = 0; b < K; ++b) {
+        int64_t hi = b < K - 1 ? (int64_t)cutoffs[b] : INT64_MAX;
+        int64_t top = income < hi ? income : hi;
+        if (top > lo) acc += (int64_t)levels[b] * (top - lo);
+        lo = hi;
+        if (income <= hi) break;
+    }
+    return acc / 20;
+}
+
+// decoded action
+struct Act {
+    int type, r, p;  // type: 0 noop, 1 gather, 2 craft, 3 buy, 4 sell
+};
+
+__device__ inline Act decode_action(const EnvParams& P, int a)
+{
+    Act d{0, 0, 0};
+    if (a <= 0) return d;
+    if (a <= P.R) {
+        d.type = 1;
+        d.r = a - 1;
+        return d;
+    }
+    if (a == P.R + 1) {
+        d.type = 2;
+        return d;
+    }
+    int b = a - (P.R + 2);
+    const int RP = P.R * P.P;
+    if (b < RP) {
+        d.type = 3;
+    } else {
+        d.type = 4;
+        b -= RP;
+    }
+    d.r = b / P.P;
+    d.p = b - d.r * P.P;
+    return d;
+}
+
+template <int RM, int XM>
+__device__ inline bool craft_possible(const EnvParams& P, const Agent<RM, XM>& ag)
+{
+    int ok = 0;
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+        if (r < P.R && ag.res_inv[r] >= P.R_kappa) ++ok;
+    return ok >= P.R_d;
+}
+
+template <int RM, int XM>
+__device__ inline bool action_allowed(const EnvParams& P, const Agent<RM, XM>& ag, int nact, int a,
+                                      const int32_t* s_prices)
+{
+    if (a < 0 || a >= P.A) return false;
+    Act d = decode_action(P, a);
+    switch (d.type) {
+    case 0: return P.allow_noop != 0;
+    case 1: return true;
+    case 2: return craft_possible(P, ag);
+    case 3: return nact < P.max_orders && ag.coin_inv >= s_prices[d.p];
+    default: return nact < P.max_orders && rget(ag.res_inv, d.r) >= 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// block primitives (blockDim.x a multiple of 64)
+// ---------------------------------------------------------------------------
+__device__ inline int64_t block_sum_i64(int64_t v, int64_t* red)
+{
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane_id() == 0) red[w] = v;
+    __syncthreads();
+    int64_t tot = 0;
+    for (int j = 0; j < nw; ++j) tot += red[j];
+    return tot;
+}
+
+// exclusive scans of `nseg` segments of `len` ints (src -> dst); waves take
+// segments round-robin; the caller synchronises before and after.
+__device__ inline void seg_exclusive_scan(const int32_t* src, int32_t* dst, int nseg, int len)
+{
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = lane_id();
+    for (int s = w; s < nseg; s += nw) {
+        int32_t carry = 0;
+        for (int c = 0; c < len; c += 64) {
+            int j = c + lane;
+            int32_t v = j < len ? src[s * len + j] : 0;
+            int32_t inc = wave_inclusive_scan(v);
+            if (j < len) dst[s * len + j] = carry + inc - v;
+            carry += __shfl(inc, 63, 64);
+        }
+    }
+}
+
+// in-place ascending bitonic sort of `n2` (power of two) int64 keys in LDS
+__device__ inline void bitonic_sort_i64(int64_t* a, int n2)
+{
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+                int l = i ^ j;
+                if (l > i) {
+                    int64_t x = a[i], y = a[l];
+                    bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__host__ __device__ inline int next_pow2(int n)
+{
+    int p = 64;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// LDS carve-up shared by host (sizing) and device
+// ---------------------------------------------------------------------------
+struct Lds {
+    int32_t *hcnt, *hmin, *hexc;     // [HB] order-book buckets
+    int32_t *nbcnt, *nboff;          // [2 R P] new orders per (side, r, p)
+    int32_t *ncode, *ntab;           // [NL] new-order bucket per agent; agents by bucket rank
+    uint32_t* nkey;                  // [NL] new-order tie key
+    int64_t* sortbuf;                // [S2]
+    int32_t *prices, *cutoffs, *rates, *kr, *mstat, *misc;
+    int64_t* red;                    // [32]
+    double* dred;                    // [4]
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// Byte offsets of the LDS arrays; `base` null only sizes the layout.
+__host__ __device__ __forceinline__ size_t lds_layout(const EnvParams& P, int NL, unsigned char* base, Lds* L)
+{
+    const size_t NB = 2 * (size_t)P.R * (size_t)P.P, HB = (size_t)P.HB, nl = (size_t)NL;
+    const size_t S2 = (size_t)next_pow2(NL);
+    const size_t o_hcnt = 0;
+    const size_t o_hmin = align16(o_hcnt + 4 * HB);
+    const size_t o_hexc = align16(o_hmin + 4 * HB);
+    const size_t o_nbcnt = align16(o_hexc + 4 * HB);
+    const size_t o_nboff = align16(o_nbcnt + 4 * NB);
+    const size_t o_ncode = align16(o_nboff + 4 * NB);
+    const size_t o_ntab = align16(o_ncode + 4 * nl);
+    const size_t o_nkey = align16(o_ntab + 4 * nl);
+    const size_t o_sort = align16(o_nkey + 4 * nl);
+    const size_t o_prices = align16(o_sort + 8 * S2);
+    const size_t o_cut = align16(o_prices + 4 * EJ_MAX_P);
+    const size_t o_rates = align16(o_cut + 4 * EJ_MAX_K);
+    const size_t o_kr = align16(o_rates + 4 * EJ_MAX_K);
+    const size_t o_mstat = align16(o_kr + 4 * EJ_MAX_R);
+    const size_t o_misc = align16(o_mstat + 16 * EJ_MAX_R);
+    const size_t o_red = align16(o_misc + 4 * 16);
+    const size_t o_dred = align16(o_red + 8 * 32);
+    const size_t total = align16(o_dred + 8 * 4);
+    if (base) {
+        L->hcnt = (int32_t*)(base + o_hcnt);
+        L->hmin = (int32_t*)(base + o_hmin);
+        L->hexc = (int32_t*)(base + o_hexc);
+        L->nbcnt = (int32_t*)(base + o_nbcnt);
+        L->nboff = (int32_t*)(base + o_nboff);
+        L->ncode = (int32_t*)(base + o_ncode);
+        L->ntab = (int32_t*)(base + o_ntab);
+        L->nkey = (uint32_t*)(base + o_nkey);
+        L->sortbuf = (int64_t*)(base + o_sort);
+        L->prices = (int32_t*)(base + o_prices);
+        L->cutoffs = (int32_t*)(base + o_cut);
+        L->rates = (int32_t*)(base + o_rates);
+        L->kr = (int32_t*)(base + o_kr);
+        L->mstat = (int32_t*)(base + o_mstat);
+        L->misc = (int32_t*)(base + o_misc);
+        L->red = (int64_t*)(base + o_red);
+        L->dred = (double*)(base + o_dred);
+    }
+    return total;
+}
+
+// bucket position in matching-priority order within the (r, side) segment
+__device__ inline int bucket_pos(const EnvParams& P, int side, int p, int age)
+{
+    return side == 0 ? (P.P - 1 - p) * P.X + (P.X - 1 - age) : p * P.X + (P.X - 1 - age);
+}
+
+// Gini numerator and coin sum of the economy from coin values in sortbuf
+// (n live entries, padded with INT64_MAX to S2), then social welfare.
+__device__ inline double social_welfare_block(const EnvParams& P, const Lds& L, int n, int S2)
+{
+    bitonic_sort_i64(L.sortbuf, S2);
+    int64_t num = 0, sum = 0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        int64_t x = L.sortbuf[k];
+        num += (int64_t)(2 * k - n + 1) * x;
+        sum += x;
+    }
+    num = block_sum_i64(num, L.red);
+    sum = block_sum_i64(sum, L.red + 16);
+    double gini = 0.0;
+    if (sum > 0) gini = (double)num / ((double)n * (double)sum);
+    double eq = (1.0 - P.omega) + P.omega * (1.0 - gini);
+    return eq * (double)sum;
+}
+
+// market statistics after the step from the bucket histogram:
+// mstat[4r + 0..3] = best bid price, best ask price, #bids, #asks
+// `kr` null -> no fills; `skip_age` >= 0 -> that age has expired.
+__device__ inline void market_stats(const EnvParams& P, const Lds& L, const int32_t* kr, int skip_age)
+{
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = lane_id();
+    const int PX = P.P * P.X;
+    for (int seg = w; seg < 2 * P.R; seg += nw) {
+        const int r = seg >> 1, side = seg & 1;
+        const int k = kr ? kr[r] : 0;
+        int best = INT_MAX, count = 0;
+        for (int c = 0; c < PX; c += 64) {
+            int pos = c + lane;
+            if (pos < PX) {
+                int b = seg * PX + pos;
+                int cnt = L.hcnt[b];
+                int fill = k - L.hexc[b];
+                fill = fill < 0 ? 0 : (fill > cnt ? cnt : fill);
+                int alive = cnt - fill;
+                int age = P.X - 1 - (pos % P.X);
+                if (age == skip_age) alive = 0;
+                if (alive > 0 && pos < best) best = pos;
+                count += alive;
+            }
+        }
+        best = wave_min(best);
+        count = wave_sum(count);
+        if (lane == 0) {
+            int price = 0;
+            if (best != INT_MAX) {
+                int pl = best / P.X;
+                int p = side == 0 ? P.P - 1 - pl : pl;
+                price = L.prices[p];
+            }
+            L.mstat[4 * r + side] = price;
+            L.mstat[4 * r + 2 + side] = count;
+        }
+    }
+}
+
+// packs consecutive bf16 features into 32-bit stores
+struct RowWriter {
+    uint32_t* base;
+    uint32_t pend;
+    int d;
+    __device__ inline void put(float v)
+    {
+        uint32_t b = f32_to_bf16(v);
+        if (d & 1) base[d >> 1] = pend | (b << 16);
+        else pend = b;
+        ++d;
+    }
+};
+
+template <int RM, int XM>
+__device__ inline void write_obs_row(const EnvParams& P, const Lds& L, const Agent<RM, XM>& ag, int t,
+                                     uint16_t* row)
+{
+    const ej_obs_scales& s = P.sc;
+    RowWriter w{(uint32_t*)row, 0u, 0};
+    const int nact = n_active(ag, P.X);
+    w.put((float)ag.coin_inv * s.coin);
+    w.put((float)ag.coin_esc * s.coin);
+    w.put((float)ag.labor * s.labor);
+    w.put((float)nact * s.orders);
+    w.put((float)(ag.coin_inv + ag.coin_esc - ag.snap) * s.coin);
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+        if (r < P.R) w.put((float)ag.res_inv[r] * s.res);
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+        if (r < P.R) w.put((float)ag.res_esc[r] * s.res);
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+        if (r < P.R) w.put((float)ag.sg[r] * s.skill);
+    w.put((float)ag.sc * s.skill);
+    for (int b = 0; b < P.K; ++b) w.put((float)L.rates[b] * s.rate);
+    w.put((float)(t % P.P_tax) * s.phase);
+    for (int r = 0; r < P.R; ++r) {
+        w.put((float)L.mstat[4 * r + 0] * s.price);
+        w.put((float)L.mstat[4 * r + 1] * s.price);
+        w.put((float)L.mstat[4 * r + 2] * s.count);
+        w.put((float)L.mstat[4 * r + 3] * s.count);
+    }
+    while (w.d < P.Ds) w.put(0.0f);
+}
+
+// bits [lo, hi) of mask word `wd`
+__device__ inline uint32_t range_bits(int wd, int lo, int hi)
+{
+    int a = lo - 32 * wd, b = hi - 32 * wd;
+    a = a < 0 ? 0 : a;
+    b = b > 32 ? 32 : b;
+    if (a >= b) return 0u;
+    uint32_t hi_mask = b == 32 ? 0xffffffffu : ((1u << b) - 1u);
+    return hi_mask & ~((1u << a) - 1u);
+}
+
+template <int RM, int XM>
+__device__ inline void write_mask_row(const EnvParams& P, const Lds& L, const Agent<RM, XM>& ag, uint32_t* row)
+{
+    const int nact = n_active(ag, P.X);
+    const bool can_order = nact < P.max_orders;
+    // affordable price levels form a prefix: prices strictly increase
+    int lo = 0, hi = P.P;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (L.prices[mid] <= ag.coin_inv) lo = mid + 1;
+        else hi = mid;
+    }
+    const int n_afford = can_order ? lo : 0;
+    const bool craft = craft_possible(P, ag);
+    const int base_buy = P.R + 2, base_sell = P.R + 2 + P.R * P.P;
+    for (int wd = 0; wd < P.W; ++wd) {
+        uint32_t bits = 0;
+        if (P.allow_noop) bits |= range_bits(wd, 0, 1);
+        bits |= range_bits(wd, 1, P.R + 1);
+        if (craft) bits |= range_bits(wd, P.R + 1, P.R + 2);
+#pragma unroll
+        for (int r = 0; r < RM; ++r) {
+            if (r < P.R) {
+                bits |= range_bits(wd, base_buy + r * P.P, base_buy + r * P.P + n_afford);
+                if (can_order && ag.res_inv[r] >= 1)
+                    bits |= range_bits(wd, base_sell + r * P.P, base_sell + (r + 1) * P.P);
+            }
+        }
+        row[wd] = bits;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the step kernel: one workgroup per economy
+// ---------------------------------------------------------------------------
+template <int RM, int XM, int APT>
+__global__ void __launch_bounds__(1024 / APT)
+env_step_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__ act,
+                const int32_t* __restrict__ gov, float* __restrict__ rew, float* __restrict__ gov_rew,
+                uint8_t* __restrict__ done_out, uint16_t* __restrict__ obs, uint32_t* __restrict__ mask)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int e = blockIdx.x;
+    const int NT = blockDim.x, tid = threadIdx.x;
+    const int NL = NT * APT;
+    Lds L;
+    lds_layout(P, NL, smem, &L);
+    const int n = S.env_n[e];
+    const int64_t off = S.env_off[e];
+    const int64_t row0 = S.env_row[e];
+    const int t = S.env_t[e];
+    const int ep = S.env_ep[e];
+    const int R = P.R, X = P.X, K = P.K, PX = P.P * P.X;
+    const int S2 = next_pow2(NL);
+
+    for (int j = tid; j < P.P; j += NT) L.prices[j] = P.prices[j];
+    for (int j = tid; j < K - 1; j += NT) L.cutoffs[j] = P.cutoffs[j];
+    if (tid < K) {
+        int old = S.env_rates[e * K + tid];
+        int lv = old;
+        if (t % P.P_tax == 0) {  // government sets the period's rates at its first step
+            int g = gov[e * K + tid];
+            if (g >= 0 && g < EJ_GOV_LEVELS) lv = g;
+        }
+        L.rates[tid] = lv;
+    }
+    for (int j = tid; j < P.HB; j += NT) {
+        L.hcnt[j] = 0;
+        L.hmin[j] = INT_MAX;
+    }
+    for (int j = tid; j < 2 * R * P.P; j += NT) L.nbcnt[j] = 0;
+    for (int j = tid; j < S2; j += NT) L.sortbuf[j] = INT64_MAX;
+    __syncthreads();
+
+    Agent<RM, XM> ag[APT];
+    double u0[APT];
+    int eff[APT];
+    int my_rank[APT];
+    int invalid = 0;
+
+    // load, utilities of the step-start state, action validation (step-start mask)
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        eff[k] = 0;
+        my_rank[k] = 0;
+        if (li < n) {
+            load_agent(P, S, off + li, ag[k]);
+            const int64_t C = (int64_t)ag[k].coin_inv + ag[k].coin_esc;
+            u0[k] = utility(C, ag[k].labor, P.eta);
+            L.sortbuf[li] = C;
+            const int a = act[row0 + li];
+            if (action_allowed(P, ag[k], n_active(ag[k], X), a, L.prices)) eff[k] = a;
+            else ++invalid;
+        }
+    }
+    __syncthreads();
+    const double ug0 = social_welfare_block(P, L, n, S2);
+
+    // apply every agent's action; new orders go to slot t mod X
+    const int slot_new = t % X;
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        if (li >= n) continue;
+        L.ncode[li] = -1;
+        Act d = decode_action(P, eff[k]);
+        Agent<RM, XM>& a = ag[k];
+        if (d.type == 1) {  // gather: floor(SG + rho), rho ~ U[0, 1.1)
+            u64x4 w = philox(P.seed, PURPOSE_ENV, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)li);
+            int64_t rho_q = (int64_t)(((w.x >> 32) * 72090ull) >> 32);
+            int64_t amount = ((int64_t)rget(a.sg, d.r) + rho_q) >> 16;
+            radd(a.res_inv, d.r, (int32_t)amount);
+            a.labor += P.labor_gather;
+        } else if (d.type == 2) {  // craft: R_d fullest eligible types, ties to the lower id
+            uint32_t used = 0;
+            for (int c = 0; c < P.R_d; ++c) {
+                int best = -1, bestv = -1;
+#pragma unroll
+                for (int r = 0; r < RM; ++r) {
+                    if (r < R && !((used >> r) & 1u) && a.res_inv[r] >= P.R_kappa && a.res_inv[r] > bestv) {
+                        best = r;
+                        bestv = a.res_inv[r];
+                    }
+                }
+                used |= 1u << best;
+                radd(a.res_inv, best, -P.R_kappa);
+            }
+            a.coin_inv += (int32_t)(((int64_t)a.sc * P.kappa_c) >> 16);
+            a.labor += P.labor_craft;
+        } else if (d.type >= 3) {  // order with escrow
+            u64x4 w = philox(P.seed, PURPOSE_ENV, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)li);
+            const int side = d.type == 4;
+            if (side == 0) {
+                a.coin_inv -= L.prices[d.p];
+                a.coin_esc += L.prices[d.p];
+            } else {
+                radd(a.res_inv, d.r, -1);
+                radd(a.res_esc, d.r, 1);
+            }
+            a.labor += P.labor_trade;
+            L.ncode[li] = (side * R + d.r) * P.P + d.p;
+            L.nkey[li] = (uint32_t)(w.y >> 32);
+        }
+    }
+    __syncthreads();
+
+    // placement rank of each new order among this step's orders of the same
+    // (side, r, p): by tie key, then agent id
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        if (li >= n) continue;
+        const int code = L.ncode[li];
+        if (code < 0) continue;
+        const uint32_t key = L.nkey[li];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            int cj = L.ncode[j];
+            if (cj == code) {
+                uint32_t kj = L.nkey[j];
+                rank += (kj < key) || (kj == key && j < li);
+            }
+        }
+        my_rank[k] = rank;
+        atomicAdd(&L.nbcnt[code], 1);
+        Act d = decode_action(P, eff[k]);
+#pragma unroll
+        for (int s = 0; s < XM; ++s)
+            if (s == slot_new) ag[k].slot[s] = slot_pack(d.type == 4, d.r, d.p, rank);
+    }
+    __syncthreads();
+    seg_exclusive_scan(L.nbcnt, L.nboff, 1, 2 * R * P.P);
+    __syncthreads();
+
+    // new-order table and the bucket histogram of every live order
+    const int tX = t % X;
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        if (li >= n) continue;
+        if (L.ncode[li] >= 0) L.ntab[L.nboff[L.ncode[li]] + my_rank[k]] = li;
+#pragma unroll
+        for (int s = 0; s < XM; ++s) {
+            uint32_t sl = ag[k].slot[s];
+            if (s < X && slot_valid(sl)) {
+                int side = slot_side(sl), r = slot_r(sl), p = slot_p(sl);
+                int age = (tX - s + X) % X;
+                int b = (r * 2 + side) * PX + bucket_pos(P, side, p, age);
+                atomicAdd(&L.hcnt[b], 1);
+                atomicMin(&L.hmin[b], slot_rank(sl));
+            }
+        }
+    }
+    __syncthreads();
+    seg_exclusive_scan(L.hcnt, L.hexc, 2 * R, PX);
+    __syncthreads();
+
+    // trades per resource: k_r = max_p min(#bids >= price p, #asks <= price p)
+    {
+        const int w = tid >> 6, nw = NT >> 6, lane = lane_id();
+        for (int r = w; r < R; r += nw) {
+            int best = 0;
+            for (int c = 0; c < P.P; c += 64) {
+                int p = c + lane;
+                if (p < P.P) {
+                    int bb = (r * 2 + 0) * PX + (P.P - p) * X - 1;  // last bid bucket with price >= p
+                    int ba = (r * 2 + 1) * PX + (p + 1) * X - 1;    // last ask bucket with price <= p
+                    int nbid = L.hexc[bb] + L.hcnt[bb];
+                    int nask = L.hexc[ba] + L.hcnt[ba];
+                    int m = nbid < nask ? nbid : nask;
+                    best = m > best ? m : best;
+                }
+            }
+            best = wave_max(best);
+            if (lane == 0) L.kr[r] = best;
+        }
+    }
+    __syncthreads();
+
+    // settlement: every agent settles its own filled orders
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        if (li >= n) continue;
+        Agent<RM, XM>& a = ag[k];
+#pragma unroll
+        for (int s = 0; s < XM; ++s) {
+            uint32_t sl = a.slot[s];
+            if (!(s < X && slot_valid(sl))) continue;
+            const int side = slot_side(sl), r = slot_r(sl), p = slot_p(sl);
+            const int age = (tX - s + X) % X;
+            const int b = (r * 2 + side) * PX + bucket_pos(P, side, p, age);
+            const int g = L.hexc[b] + (slot_rank(sl) - L.hmin[b]);
+            if (g >= L.kr[r]) continue;
+            // the counterpart holds rank g on the other side
+            const int ob = (r * 2 + (1 - side)) * PX;
+            int lo = 0, hi = PX - 1;
+            while (lo < hi) {  // largest pos with hexc <= g
+                int mid = (lo + hi + 1) >> 1;
+                if (L.hexc[ob + mid] <= g) lo = mid;
+                else hi = mid - 1;
+            }
+            const int opos = lo;
+            const int oage = X - 1 - (opos % X);
+            const int opl = opos / X;
+            const int op = side == 0 ? opl : P.P - 1 - opl;
+            const int my_price = L.prices[p], other_price = L.prices[op];
+            int q;
+            if (age != oage) {
+                q = age < oage ? my_price : other_price;  // the younger order was placed last
+            } else {
+                // Both placed this step (an uncrossed book never pairs two
+                // older orders): the larger (key, agent) counts as placed later.
+                const int orank = L.hmin[ob + opos] + (g - L.hexc[ob + opos]);
+                const int ocode = ((1 - side) * R + r) * P.P + op;
+                const int idx = L.nboff[ocode] + orank;
+                q = side == 0 ? my_price : other_price;
+                if (age == 0 && idx >= 0 && idx < n) {
+                    const int oagent = L.ntab[idx];
+                    const uint32_t mk = L.nkey[li], okey = L.nkey[oagent];
+                    const bool mine_later = mk > okey || (mk == okey && li > oagent);
+                    q = mine_later ? my_price : other_price;
+                }
+            }
+            if (side == 0) {
+                a.coin_esc -= my_price;
+                a.coin_inv += my_price - q;
+                radd(a.res_inv, r, 1);
+            } else {
+                radd(a.res_esc, r, -1);
+                a.coin_inv += q;
+            }
+            a.slot[s] = 0u;
+        }
+        // expiry: the order placed at t - X + 1 has had its X clearings
+        const int se = (t + 1) % X;
+#pragma unroll
+        for (int s = 0; s < XM; ++s) {
+            if (s != se) continue;
+            uint32_t sl = a.slot[s];
+            if (!slot_valid(sl)) continue;
+            const int r = slot_r(sl), p = slot_p(sl);
+            if (slot_side(sl) == 0) {
+                a.coin_esc -= L.prices[p];
+                a.coin_inv += L.prices[p];
+            } else {
+                radd(a.res_esc, r, -1);
+                radd(a.res_inv, r, 1);
+            }
+            a.slot[s] = 0u;
+        }
+    }
+
+    // tax collection and redistribution at the last step of a period
+    if ((t + 1) % P.P_tax == 0) {
+        if (K > 0) {
+            int64_t mine = 0;
+#pragma unroll
+            for (int k = 0; k < APT; ++k) {
+                const int li = tid + k * NT;
+                if (li >= n) continue;
+                Agent<RM, XM>& a = ag[k];
+                int64_t C = (int64_t)a.coin_inv + a.coin_esc;
+                int64_t tax = bracket_tax(C - a.snap, L.rates, L.cutoffs, K);
+                if (tax > a.coin_inv) tax = a.coin_inv;
+                a.coin_inv -= (int32_t)tax;
+                mine += tax;
+            }
+            const int64_t pool = block_sum_i64(mine, L.red);
+            const int64_t period = t / P.P_tax;
+            const int64_t share = pool / n, rem = pool % n;
+#pragma unroll
+            for (int k = 0; k < APT; ++k) {
+                const int li = tid + k * NT;
+                if (li >= n) continue;
+                int64_t rot = (((int64_t)li - period) % n + n) % n;
+                ag[k].coin_inv += (int32_t)(share + (rot < rem ? 1 : 0));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < APT; ++k) ag[k].snap = ag[k].coin_inv + ag[k].coin_esc;
+    }
+
+    // rewards (Eq. (2)) and the end-of-step coin for the welfare
+    __syncthreads();
+    for (int j = tid; j < S2; j += NT) L.sortbuf[j] = INT64_MAX;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        if (li >= n) continue;
+        const int64_t C = (int64_t)ag[k].coin_inv + ag[k].coin_esc;
+        const double u1 = utility(C, ag[k].labor, P.eta);
+        rew[row0 + li] = (float)(u1 - u0[k]);
+        L.sortbuf[li] = C;
+    }
+    __syncthreads();
+    const double ug1 = social_welfare_block(P, L, n, S2);
+    const int64_t n_invalid = block_sum_i64(invalid, L.red);
+    if (tid == 0) {
+        gov_rew[e] = (float)(ug1 - ug0);
+        int bad_gov = 0;
+        if (t % P.P_tax == 0)
+            for (int b = 0; b < K; ++b) {
+                int g = gov[e * K + b];
+                bad_gov += (g < 0 || g >= EJ_GOV_LEVELS);
+            }
+        S.invalid[2 * e] += n_invalid;
+        S.invalid[2 * e + 1] += bad_gov;
+    }
+
+    // time advance; automatic reset at the episode end
+    const int t1 = t + 1;
+    const bool done = t1 >= P.T;
+    const int t_next = done ? 0 : t1;
+    const int ep_next = done ? ep + 1 : ep;
+    if (done) {
+        if (tid < K) L.rates[tid] = 0;
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+            const int li = tid + k * NT;
+            if (li < n) reset_agent(P, e, ep_next, li, ag[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        if (li >= n) continue;
+        store_agent(P, S, off + li, ag[k]);
+        done_out[row0 + li] = done ? 1 : 0;
+    }
+    if (tid == 0) {
+        S.env_t[e] = t_next;
+        S.env_ep[e] = ep_next;
+    }
+    if (tid < K) S.env_rates[e * K + tid] = L.rates[tid];
+
+    if (obs == nullptr && mask == nullptr) return;
+    // observation of the post-step state (the book is empty after a reset)
+    if (done) {
+        for (int j = tid; j < 4 * R; j += NT) L.mstat[j] = 0;
+    } else {
+        market_stats(P, L, L.kr, X - 1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        if (li >= n) continue;
+        if (obs) write_obs_row(P, L, ag[k], t_next, obs + (row0 + li) * (int64_t)P.Ds);
+        if (mask) write_mask_row(P, L, ag[k], mask + (row0 + li) * (int64_t)P.W);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// observation of the current state (population rows, masks, government)
+// ---------------------------------------------------------------------------
+template <int RM, int XM, int APT>
+__global__ void __launch_bounds__(1024 / APT)
+env_observe_kernel(const EnvParams P, const EnvState S, uint16_t* __restrict__ obs, uint32_t* __restrict__ mask,
+                   float* __restrict__ gov_obs)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int e = blockIdx.x;
+    const int NT = blockDim.x, tid = threadIdx.x;
+    const int NL = NT * APT;
+    Lds L;
+    lds_layout(P, NL, smem, &L);
+    const int n = S.env_n[e];
+    const int64_t off = S.env_off[e];
+    const int64_t row0 = S.env_row[e];
+    const int t = S.env_t[e];
+    const int R = P.R, X = P.X, K = P.K, PX = P.P * P.X;
+    const int S2 = next_pow2(NL);
+    for (int j = tid; j < P.P; j += NT) L.prices[j] = P.prices[j];
+    if (tid < K) L.rates[tid] = S.env_rates[e * K + tid];
+    for (int j = tid; j < P.HB; j += NT) {
+        L.hcnt[j] = 0;
+        L.hexc[j] = 0;
+    }
+    __syncthreads();
+    Agent<RM, XM> ag[APT];
+    const int tX = t % X;
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        if (li >= n) continue;
+        load_agent(P, S, off + li, ag[k]);
+#pragma unroll
+        for (int s = 0; s < XM; ++s) {
+            uint32_t sl = ag[k].slot[s];
+            if (s < X && slot_valid(sl)) {
+                int side = slot_side(sl), r = slot_r(sl), p = slot_p(sl);
+                int age = (tX - s + X) % X;
+                atomicAdd(&L.hcnt[(r * 2 + side) * PX + bucket_pos(P, side, p, age)], 1);
+            }
+        }
+    }
+    __syncthreads();
+    market_stats(P, L, nullptr, -1);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        if (li >= n) continue;
+        write_obs_row(P, L, ag[k], t, obs + (row0 + li) * (int64_t)P.Ds);
+        write_mask_row(P, L, ag[k], mask + (row0 + li) * (int64_t)P.W);
+    }
+    if (gov_obs == nullptr) return;
+    float* g = gov_obs + (int64_t)e * P.Dg;
+    for (int feat = 0; feat < 3 + R; ++feat) {
+        __syncthreads();
+        for (int j = tid; j < S2; j += NT) L.sortbuf[j] = INT64_MAX;
+        __syncthreads();
+        int64_t s1 = 0, s2 = 0;
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+            const int li = tid + k * NT;
+            if (li >= n) continue;
+            const Agent<RM, XM>& a = ag[k];
+            int64_t C = (int64_t)a.coin_inv + a.coin_esc;
+            int64_t v = feat == 0 ? C : feat == 1 ? C - a.snap : feat == 2 ? (int64_t)a.labor
+                                                                              : (int64_t)rget(a.res_inv, feat - 3);
+            L.sortbuf[li] = v;
+            s1 += v;
+            s2 += v * v;
+        }
+        s1 = block_sum_i64(s1, L.red);
+        s2 = block_sum_i64(s2, L.red + 16);
+        bitonic_sort_i64(L.sortbuf, S2);
+        if (tid == 0) {
+            double mean = (double)s1 / (double)n;
+            double var = (double)s2 / (double)n - mean * mean;
+            if (var < 0.0) var = 0.0;
+            g[3 * feat + 0] = (float)mean;
+            g[3 * feat + 1] = (float)sqrt(var);
+            g[3 * feat + 2] = (float)L.sortbuf[(n - 1) / 2];
+        }
+    }
+    if (tid == 0) {
+        int d = 3 * (3 + R);
+        for (int b = 0; b < K; ++b) g[d++] = (float)L.rates[b] * P.sc.rate;
+        g[d++] = (float)(t % P.P_tax) * P.sc.phase;
+        for (int r = 0; r < R; ++r)
+            for (int j = 0; j < 4; ++j) g[d++] = (float)L.mstat[4 * r + j];
+    }
+}
+
+template <int RM, int XM, int APT>
+__global__ void __launch_bounds__(1024 / APT) env_reset_kernel(const EnvParams P, const EnvState S, int ep)
+{
+    const int e = blockIdx.x;
+    const int n = S.env_n[e];
+    const int64_t off = S.env_off[e];
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = threadIdx.x + k * blockDim.x;
+        if (li >= n) continue;
+        Agent<RM, XM> ag;
+        reset_agent(P, e, ep, li, ag);
+        store_agent(P, S, off + li, ag);
+    }
+    if (threadIdx.x == 0) {
+        S.env_t[e] = 0;
+        S.env_ep[e] = ep;
+    }
+    if ((int)threadIdx.x < P.K) S.env_rates[e * P.K + threadIdx.x] = 0;
+}
+
+__global__ void env_random_actions_kernel(const EnvParams P, const EnvState S, uint64_t act_seed,
+                                          int32_t* __restrict__ act, int32_t* __restrict__ gov)
+{
+    const int e = blockIdx.x;
+    const int n = S.env_n[e];
+    const int64_t row0 = S.env_row[e];
+    const int t = S.env_t[e], ep = S.env_ep[e];
+    for (int li = threadIdx.x; li < n; li += blockDim.x) {
+        u64x4 w = philox(act_seed, PURPOSE_ACT, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)li);
+        act[row0 + li] = (int32_t)(((w.x >> 32) * (uint64_t)P.A) >> 32);
+    }
+    if ((int)threadIdx.x < P.K) {
+        const int b = threadIdx.x;
+        u64x4 w = philox(act_seed, PURPOSE_GOV, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)(b >> 2));
+        gov[e * P.K + b] = (int32_t)(((word_of(w, b & 3) >> 32) * 21ull) >> 32);
+    }
+}
+
+}  // namespace econ
+
+// ===========================================================================
+// host side: the handle and the C ABI
+// ===========================================================================
+using namespace econ;
+
+struct ej_env {
+    EnvParams P;
+    int E = 0, NT = 64, APT = 1, variant = 0;  // variant 0: R<=4, X<=16; 1: R<=8, X<=32
+    int64_t M = 0;
+    std::vector<int32_t> n, off, row;
+    int32_t* d_field = nullptr;
+    int32_t* d_t = nullptr;
+    int32_t* d_ep = nullptr;
+    int32_t* d_rates = nullptr;
+    int32_t* d_n = nullptr;
+    int32_t* d_off = nullptr;
+    int32_t* d_row = nullptr;
+    int64_t* d_invalid = nullptr;
+    size_t lds = 0;
+    EnvState state() const
+    {
+        return EnvState{d_field, d_t, d_ep, d_rates, d_n, d_off, d_row, d_invalid};
+    }
+};
+
+static int choose_launch(ej_env* h, int apt)
+{
+    const int N = h->P.N;
+    int nt = (N + apt - 1) / apt;
+    nt = (nt + 63) / 64 * 64;
+    if (nt > 1024 / apt) return EJ_EUNSUPPORTED;
+    h->APT = apt;
+    h->NT = nt;
+    h->lds = lds_layout(h->P, nt * apt, nullptr, nullptr);
+    return EJ_OK;
+}
+
+// Kernels are instantiated for one agent per thread (APT = 1): with several
+// agents per thread the register arrays of the agent state spill.
+#define EJ_DISPATCH(h, KERNEL, ...)                                                                        \
+    do {                                                                                                    \
+        if ((h)->variant == 0) KERNEL<4, 16, 1><<<(h)->E, (h)->NT, (h)->lds, st>>>(__VA_ARGS__);           \
+        else KERNEL<8, 32, 1><<<(h)->E, (h)->NT, (h)->lds, st>>>(__VA_ARGS__);                             \
+    } while (0)
+
+extern "C" {
+
+const char* ej_strerror(int code)
+{
+    switch (code) {
+    case EJ_OK: return "ok";
+    case EJ_EINVAL: return "invalid argument or configuration";
+    case EJ_ENOMEM: return "out of memory";
+    case EJ_EHIP: return "HIP runtime error";
+    case EJ_EUNSUPPORTED: return "configuration outside the supported limits";
+    default: return "unknown error";
+    }
+}
+
+int ej_last_hip_error(void) { return g_last_hip; }
+
+static int validate(const ej_env_config* c)
+{
+    if (!c) return EJ_EINVAL;
+    if (c->E <= 0 || c->N <= 0 || c->R <= 0 || c->P <= 0 || c->X <= 0 || c->P_tax <= 0 || c->T <= 0 || c->K < 0)
+        return EJ_EINVAL;
+    if (c->N > EJ_MAX_N || c->R > EJ_MAX_R || c->P > EJ_MAX_P || c->K > EJ_MAX_K || c->X > EJ_MAX_X)
+        return EJ_EUNSUPPORTED;
+    if ((int64_t)c->R * 2 * c->P * c->X > 8192) return EJ_EUNSUPPORTED;
+    if (c->R_d < 0 || c->R_d > c->R || c->R_kappa < 1 || c->max_orders < 0 || c->start_coin < 0) return EJ_EINVAL;
+    if (c->labor_gather < 0 || c->labor_craft < 0 || c->labor_trade < 0) return EJ_EINVAL;
+    if (!(c->eta >= 0.0) || c->eta == 1.0 || !(c->omega >= 0.0 && c->omega <= 1.0)) return EJ_EINVAL;
+    for (int p = 0; p < c->P; ++p) {
+        if (c->prices[p] <= 0) return EJ_EINVAL;
+        if (p > 0 && c->prices[p] <= c->prices[p - 1]) return EJ_EINVAL;
+    }
+    for (int b = 0; b + 1 < c->K; ++b) {
+        if (c->cutoffs[b] <= 0) return EJ_EINVAL;
+        if (b > 0 && c->cutoffs[b] <= c->cutoffs[b - 1]) return EJ_EINVAL;
+    }
+    return EJ_OK;
+}
+
+int ej_env_create(const ej_env_config* cfg, const int32_t* h_n_per_env, ej_env** out)
+{
+    if (!out) return EJ_EINVAL;
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc != EJ_OK) return rc;
+    ej_env* h = new (std::nothrow) ej_env();
+    if (!h) return EJ_ENOMEM;
+    EnvParams& P = h->P;
+    std::memset(&P, 0, sizeof(P));
+    P.N = cfg->N; P.R = cfg->R; P.P = cfg->P; P.X = cfg->X; P.max_orders = cfg->max_orders;
+    P.P_tax = cfg->P_tax; P.K = cfg->K; P.T = cfg->T; P.R_kappa = cfg->R_kappa; P.R_d = cfg->R_d;
+    P.kappa_c = cfg->kappa_c; P.start_coin = cfg->start_coin; P.labor_gather = cfg->labor_gather;
+    P.labor_craft = cfg->labor_craft; P.labor_trade = cfg->labor_trade; P.allow_noop = cfg->allow_noop;
+    P.A = 2 + P.R + 2 * P.R * P.P;
+    P.W = (P.A + 31) / 32;
+    P.D = 7 + 7 * P.R + P.K;
+    P.Ds = (P.D + 7) / 8 * 8;
+    P.Dg = 3 * (3 + P.R) + P.K + 1 + 4 * P.R;
+    P.HB = P.R * 2 * P.P * P.X;
+    P.eta = cfg->eta; P.omega = cfg->omega; P.seed = cfg->seed;
+    std::memcpy(P.prices, cfg->prices, sizeof(P.prices));
+    std::memcpy(P.cutoffs, cfg->cutoffs, sizeof(P.cutoffs));
+    P.sc = cfg->scales;
+    h->E = cfg->E;
+    h->variant = (P.R <= 4 && P.X <= 16) ? 0 : 1;
+    h->n.resize(h->E);
+    h->off.resize(h->E);
+    h->row.resize(h->E + 1);
+    int64_t slots = 0, rows = 0;
+    for (int e = 0; e < h->E; ++e) {
+        int ne = h_n_per_env ? h_n_per_env[e] : P.N;
+        if (ne <= 0 || ne > P.N) {
+            delete h;
+            return EJ_EINVAL;
+        }
+        h->n[e] = ne;
+        h->off[e] = (int32_t)slots;
+        h->row[e] = (int32_t)rows;
+        slots += (ne + 15) / 16 * 16;  // 64-byte aligned economies
+        rows += ne;
+    }
+    h->row[h->E] = (int32_t)rows;
+    if (slots > INT32_MAX || rows > INT32_MAX) {
+        delete h;
+        return EJ_EUNSUPPORTED;
+    }
+    h->M = rows;
+    P.Ntot = slots;
+    rc = choose_launch(h, 1);
+    if (rc != EJ_OK) {
+        delete h;
+        return rc;
+    }
+    const size_t nf = (size_t)n_fields(P.R, P.X);
+    bool ok = hipMalloc(&h->d_field, nf * (size_t)slots * 4) == hipSuccess &&
+              hipMalloc(&h->d_t, 4 * (size_t)h->E) == hipSuccess && hipMalloc(&h->d_ep, 4 * (size_t)h->E) == hipSuccess &&
+              hipMalloc(&h->d_rates, 4 * (size_t)h->E * (size_t)(P.K > 0 ? P.K : 1)) == hipSuccess &&
+              hipMalloc(&h->d_n, 4 * (size_t)h->E) == hipSuccess && hipMalloc(&h->d_off, 4 * (size_t)h->E) == hipSuccess &&
+              hipMalloc(&h->d_row, 4 * (size_t)(h->E + 1)) == hipSuccess &&
+              hipMalloc(&h->d_invalid, 16 * (size_t)h->E) == hipSuccess;
+    if (!ok) {
+        ej_env_destroy(h);
+        return EJ_ENOMEM;
+    }
+    if (hipMemcpy(h->d_n, h->n.data(), 4 * (size_t)h->E, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_off, h->off.data(), 4 * (size_t)h->E, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_row, h->row.data(), 4 * (size_t)(h->E + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(h->d_invalid, 0, 16 * (size_t)h->E) != hipSuccess ||
+        hipMemset(h->d_field, 0, nf * (size_t)slots * 4) != hipSuccess) {
+        set_last_hip_error(hipGetLastError());
+        ej_env_destroy(h);
+        return EJ_EHIP;
+    }
+    rc = ej_env_reset(h, 0, nullptr);
+    if (rc == EJ_OK && hipDeviceSynchronize() != hipSuccess) rc = EJ_EHIP;
+    if (rc != EJ_OK) {
+        ej_env_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return EJ_OK;
+}
+
+int ej_env_destroy(ej_env* h)
+{
+    if (!h) return EJ_EINVAL;
+    (void)hipFree(h->d_field);
+    (void)hipFree(h->d_t);
+    (void)hipFree(h->d_ep);
+    (void)hipFree(h->d_rates);
+    (void)hipFree(h->d_n);
+    (void)hipFree(h->d_off);
+    (void)hipFree(h->d_row);
+    (void)hipFree(h->d_invalid);
+    delete h;
+    return EJ_OK;
+}
+
+int ej_env_dims(const ej_env* h, ej_env_dims_t* out)
+{
+    if (!h || !out) return EJ_EINVAL;
+    out->M = h->M;
+    out->A = h->P.A;
+    out->mask_words = h->P.W;
+    out->D = h->P.D;
+    out->D_stride = h->P.Ds;
+    out->D_gov = h->P.Dg;
+    out->K = h->P.K;
+    return EJ_OK;
+}
+
+const int32_t* ej_env_row_offsets(const ej_env* h) { return h ? h->row.data() : nullptr; }
+
+int ej_env_reset(ej_env* h, int32_t episode, void* stream)
+{
+    if (!h || episode < 0) return EJ_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    EnvState S = h->state();
+    EJ_DISPATCH(h, env_reset_kernel, h->P, S, (int)episode);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+int ej_env_step(ej_env* h, const int32_t* d_act, const int32_t* d_gov, float* d_rew, float* d_gov_rew,
+                uint8_t* d_done, uint16_t* d_obs, uint32_t* d_mask, void* stream)
+{
+    if (!h || !d_act || !d_rew || !d_gov_rew || !d_done) return EJ_EINVAL;
+    if (h->P.K > 0 && !d_gov) return EJ_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    EnvState S = h->state();
+    EJ_DISPATCH(h, env_step_kernel, h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs, d_mask);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+int ej_env_observe(ej_env* h, uint16_t* d_obs, uint32_t* d_mask, float* d_gov_obs, void* stream)
+{
+    if (!h || !d_obs || !d_mask) return EJ_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    EnvState S = h->state();
+    EJ_DISPATCH(h, env_observe_kernel, h->P, S, d_obs, d_mask, d_gov_obs);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+int ej_env_random_actions(ej_env* h, uint64_t act_seed, int32_t* d_act, int32_t* d_gov, void* stream)
+{
+    if (!h || !d_act || (h->P.K > 0 && !d_gov)) return EJ_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    env_random_actions_kernel<<<h->E, 256, 0, st>>>(h->P, h->state(), act_seed, d_act, d_gov);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+int ej_env_get_state(ej_env* h, const ej_state_view* v, void* stream)
+{
+    if (!h || !v) return EJ_EINVAL;
+    const EnvParams& P = h->P;
+    const int E = h->E, K = P.K, R = P.R, X = P.X;
+    const size_t nf = (size_t)n_fields(R, X);
+    std::vector<int32_t> f(nf * (size_t)P.Ntot), t(E), ep(E), rates((size_t)E * (K > 0 ? K : 1));
+    EJ_HIP(hipStreamSynchronize((hipStream_t)stream));
+    EJ_HIP(hipMemcpy(f.data(), h->d_field, f.size() * 4, hipMemcpyDeviceToHost));
+    EJ_HIP(hipMemcpy(t.data(), h->d_t, 4 * (size_t)E, hipMemcpyDeviceToHost));
+    EJ_HIP(hipMemcpy(ep.data(), h->d_ep, 4 * (size_t)E, hipMemcpyDeviceToHost));
+    EJ_HIP(hipMemcpy(rates.data(), h->d_rates, rates.size() * 4, hipMemcpyDeviceToHost));
+    const int64_t M = h->M, st = P.Ntot;
+    for (int e = 0; e < E; ++e) {
+        if (v->t) v->t[e] = t[e];
+        if (v->ep) v->ep[e] = ep[e];
+        if (v->rates)
+            for (int b = 0; b < K; ++b) v->rates[(size_t)e * K + b] = rates[(size_t)e * K + b];
+        for (int i = 0; i < h->n[e]; ++i) {
+            const int64_t g = h->off[e] + i, rw = h->row[e] + i;
+            if (v->coin_inv) v->coin_inv[rw] = f[F_COIN_INV() * st + g];
+            if (v->coin_esc) v->coin_esc[rw] = f[F_COIN_ESC() * st + g];
+            if (v->labor) v->labor[rw] = f[F_LABOR() * st + g];
+            if (v->snap) v->snap[rw] = f[F_SNAP() * st + g];
+            if (v->sc) v->sc[rw] = f[F_SC() * st + g];
+            for (int r = 0; r < R; ++r) {
+                if (v->res_inv) v->res_inv[r * M + rw] = f[F_RES_INV(R, r) * st + g];
+                if (v->res_esc) v->res_esc[r * M + rw] = f[F_RES_ESC(R, r) * st + g];
+                if (v->sg) v->sg[r * M + rw] = f[F_SG(R, r) * st + g];
+            }
+            for (int s = 0; s < X; ++s) {
+                uint32_t sl = (uint32_t)f[F_SLOT(R, s) * st + g];
+                if (v->orders)
+                    v->orders[s * M + rw] = slot_valid(sl) ? slot_side(sl) + 2 * (slot_r(sl) + R * slot_p(sl)) : -1;
+            }
+        }
+    }
+    return EJ_OK;
+}
+
+int ej_env_set_state(ej_env* h, const ej_state_view* v, void* stream)
+{
+    if (!h || !v || !v->t || !v->ep || !v->coin_inv || !v->coin_esc || !v->labor || !v->snap || !v->sc ||
+        !v->res_inv || !v->res_esc || !v->sg || !v->orders || (h->P.K > 0 && !v->rates))
+        return EJ_EINVAL;
+    const EnvParams& P = h->P;
+    const int E = h->E, K = P.K, R = P.R, X = P.X;
+    const size_t nf = (size_t)n_fields(R, X);
+    const int64_t M = h->M, st = P.Ntot;
+    std::vector<int32_t> f(nf * (size_t)P.Ntot, 0);
+    for (int e = 0; e < E; ++e) {
+        const int te = v->t[e];
+        if (te < 0 || te >= P.T || v->ep[e] < 0) return EJ_EINVAL;
+        const int n = h->n[e];
+        // placement ranks of live orders: rank by (tie key, agent) within (t0, side, r, p)
+        struct O {
+            int i, s, code, t0;
+            uint32_t key;
+        };
+        std::vector<O> orders;
+        for (int i = 0; i < n; ++i) {
+            const int64_t g = h->off[e] + i, rw = h->row[e] + i;
+            f[F_COIN_INV() * st + g] = v->coin_inv[rw];
+            f[F_COIN_ESC() * st + g] = v->coin_esc[rw];
+            f[F_LABOR() * st + g] = v->labor[rw];
+            f[F_SNAP() * st + g] = v->snap[rw];
+            f[F_SC() * st + g] = v->sc[rw];
+            for (int r = 0; r < R; ++r) {
+                f[F_RES_INV(R, r) * st + g] = v->res_inv[r * M + rw];
+                f[F_RES_ESC(R, r) * st + g] = v->res_esc[r * M + rw];
+                f[F_SG(R, r) * st + g] = v->sg[r * M + rw];
+            }
+            for (int s = 0; s < X; ++s) {
+                const int code = v->orders[s * M + rw];
+                if (code < 0) continue;
+                if ((code >> 1) >= R * P.P) return EJ_EINVAL;
+                const int t0 = te - 1 - ((((te - 1 - s) % X) + X) % X);
+                if (t0 < 0 || s == te % X) return EJ_EINVAL;
+                u64x4 w = philox(P.seed, PURPOSE_ENV, (uint64_t)e, (uint64_t)v->ep[e], (uint64_t)t0, (uint64_t)i);
+                orders.push_back(O{i, s, code, t0, (uint32_t)(w.y >> 32)});
+            }
+        }
+        for (size_t a = 0; a < orders.size(); ++a) {
+            int rank = 0;
+            for (size_t b = 0; b < orders.size(); ++b) {
+                if (orders[b].code != orders[a].code || orders[b].t0 != orders[a].t0) continue;
+                rank += orders[b].key < orders[a].key || (orders[b].key == orders[a].key && orders[b].i < orders[a].i);
+            }
+            const O& o = orders[a];
+            const int side = o.code & 1, r = (o.code >> 1) % R, p = (o.code >> 1) / R;
+            f[F_SLOT(R, o.s) * st + h->off[e] + o.i] = (int32_t)slot_pack(side, r, p, rank);
+        }
+    }
+    std::vector<int32_t> rates((size_t)E * (K > 0 ? K : 1), 0);
+    for (size_t j = 0; j < (size_t)E * K; ++j) rates[j] = v->rates[j];
+    EJ_HIP(hipStreamSynchronize((hipStream_t)stream));
+    EJ_HIP(hipMemcpy(h->d_field, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+    EJ_HIP(hipMemcpy(h->d_t, v->t, 4 * (size_t)E, hipMemcpyHostToDevice));
+    EJ_HIP(hipMemcpy(h->d_ep, v->ep, 4 * (size_t)E, hipMemcpyHostToDevice));
+    EJ_HIP(hipMemcpy(h->d_rates, rates.data(), rates.size() * 4, hipMemcpyHostToDevice));
+    return EJ_OK;
+}
+
+int ej_env_status(ej_env* h, int64_t* h_invalid_actions, int64_t* h_invalid_gov, void* stream)
+{
+    if (!h) return EJ_EINVAL;
+    std::vector<int64_t> c(2 * (size_t)h->E);
+    EJ_HIP(hipStreamSynchronize((hipStream_t)stream));
+    EJ_HIP(hipMemcpy(c.data(), h->d_invalid, c.size() * 8, hipMemcpyDeviceToHost));
+    int64_t a = 0, g = 0;
+    for (int e = 0; e < h->E; ++e) {
+        a += c[2 * e];
+        g += c[2 * e + 1];
+    }
+    if (h_invalid_actions) *h_invalid_actions = a;
+    if (h_invalid_gov) *h_invalid_gov = g;
+    return EJ_OK;
+}
+
+}  // extern "C"
