@@ -176,6 +176,46 @@ int ej_env_set_state(ej_env* env, const ej_state_view* h_view, void* stream);
  * since create (summed over economies). */
 int ej_env_status(ej_env* env, int64_t* h_invalid_actions, int64_t* h_invalid_gov, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Shared population policy (Sec. 4 "Experimental details": all population
+ * agents share one policy and one value network; Sec. 3 "Action masking").
+ * Network: D -> H -> H -> (A logits, 1 value), ReLU, bf16 operands with fp32
+ * accumulation.  Parameters are one flat fp32 vector (row-major W[in][out]
+ * followed by its bias, for W1, b1, W2, b2, W3, b3; W3 has A + 1 columns,
+ * the last one the value head).  The kernels read a bf16 "work" copy in
+ * their own chunked layout, refreshed by ej_mlp_sync_weights.
+ * Supported: D <= 64, D_stride a multiple of 8 in [D, 64], H in
+ * {64, 128, 256, 512}, A + 1 <= 1024.
+ * ------------------------------------------------------------------------ */
+typedef struct ej_mlp_desc {
+    int32_t D, D_stride, H, A;
+} ej_mlp_desc;
+
+typedef struct ej_mlp_layout_t {
+    int64_t n_params;                 /* fp32 parameter count */
+    int64_t n_work;                   /* bf16 work-copy element count */
+    int64_t W1, b1, W2, b2, W3, b3;   /* element offsets in the parameter vector */
+} ej_mlp_layout_t;
+
+int ej_mlp_layout(const ej_mlp_desc* m, ej_mlp_layout_t* out);
+
+/* d_params [n_params] fp32 -> d_work [n_work] bf16 (round to nearest even). */
+int ej_mlp_sync_weights(const ej_mlp_desc* m, const float* d_params, uint16_t* d_work, void* stream);
+
+/* Policy forward over M rows: d_obs [M * D_stride] bf16 bits (as written by
+ * ej_env_step / ej_env_observe), d_mask [M * ceil(A/32)] action-mask bits.
+ * Writes the sampled action d_act [M], its log-probability d_logp [M], the
+ * value d_val [M] and the entropy of the masked distribution d_ent [M];
+ * d_logits [M * A] (nullable) receives the raw logits (debugging and tests).
+ * Sampling is exact for the masked softmax: the logits are taken in chunks
+ * of 128 actions, a chunk is chosen by weighted reservoir with one uniform
+ * and the action inside it by inverse CDF with a second one; the uniforms of
+ * row r, chunk c come from the counter-based generator keyed (seed, r, ctr,
+ * c / 2).  Logits are never written to memory unless d_logits is given. */
+int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const uint16_t* d_obs,
+                      const uint32_t* d_mask, int64_t M, uint64_t seed, uint64_t ctr, int32_t* d_act, float* d_logp,
+                      float* d_val, float* d_ent, float* d_logits, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

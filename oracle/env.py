@@ -106,6 +106,21 @@ def philox4x64(ctr, key) -> np.ndarray:
     return out
 
 
+def sample_uniforms(seed: int, rows, ctr: int, n_chunks: int):
+    """The two uniforms per (row, 128-action chunk) of the policy sampler:
+    words 2(c mod 2) and 2(c mod 2) + 1 of Philox(seed, purpose 5;
+    row, ctr, c / 2, 0); u = (top 24 bits + 1/2) / 2^24."""
+    rows = np.asarray(rows, dtype=np.int64)
+    u1 = np.zeros((len(rows), n_chunks))
+    u2 = np.zeros((len(rows), n_chunks))
+    for m, r in enumerate(rows):
+        for c in range(n_chunks):
+            w = philox4x64([int(r), int(ctr), c // 2, 0], [int(seed), 5])
+            u1[m, c] = ((int(w[2 * (c % 2)]) >> 40) + 0.5) / 16777216.0
+            u2[m, c] = ((int(w[2 * (c % 2) + 1]) >> 40) + 0.5) / 16777216.0
+    return u1, u2
+
+
 def utility(coin: int, labor_q: int, eta: float) -> float:
     return lib().oc_utility(int(coin), int(labor_q), float(eta))
 

@@ -40,11 +40,18 @@ def unpack_mask(mask_words: np.ndarray, A: int) -> np.ndarray:
     return ((m[:, a // 32] >> (a % 32).astype(np.uint32)) & 1).astype(bool)
 
 
-def mlp(obs: np.ndarray, w: dict):
-    """Logits [M, A] and values [M] of the two-hidden-layer ReLU network."""
+def mlp(obs: np.ndarray, w: dict, bf16_hidden: bool = False):
+    """Logits [M, A] and values [M] of the two-hidden-layer ReLU network.
+    bf16_hidden rounds the hidden activations to bf16 (the precision in
+    which a bf16 kernel feeds them to the next layer), so that a sampling
+    decision can be taken in the kernel's precision."""
     x = np.asarray(obs, dtype=np.float64)
     h1 = np.maximum(x @ w["W1"] + w["b1"], 0.0)
+    if bf16_hidden:
+        h1 = bf16_round(h1.astype(np.float32)).astype(np.float64)
     h2 = np.maximum(h1 @ w["W2"] + w["b2"], 0.0)
+    if bf16_hidden:
+        h2 = bf16_round(h2.astype(np.float32)).astype(np.float64)
     out = h2 @ w["W3"] + w["b3"]
     return out[:, :-1], out[:, -1]
 
@@ -81,6 +88,42 @@ def sample_inverse_cdf(logp: np.ndarray, u: np.ndarray):
         act[m] = idx
         lo = cdf[m, idx - 1] if idx > 0 else 0.0
         margin[m] = min(abs(uu - lo), abs(cdf[m, idx] - uu))
+    return act, margin
+
+
+def sample_chunked(logp: np.ndarray, u1: np.ndarray, u2: np.ndarray, chunk: int = 128):
+    """Exact categorical sampling in chunks of `chunk` actions: chunk c (total
+    probability S_c) becomes the candidate when u1_c * (S_0 + ... + S_c) < S_c
+    (weighted reservoir); inside the candidate the action is the first one
+    whose cumulative probability within the chunk exceeds u2_c * S_c.
+    Returns the actions and the smallest distance of any of the row's
+    decisions from its threshold (relative to the quantity compared)."""
+    p = np.exp(logp)
+    M, A = p.shape
+    NC = (A + chunk - 1) // chunk
+    act = np.zeros(M, np.int64)
+    margin = np.full(M, np.inf)
+    for m in range(M):
+        W = 0.0
+        for c in range(NC):
+            pc = p[m, c * chunk:(c + 1) * chunk]
+            Sc = pc.sum()
+            if Sc <= 0.0:
+                continue
+            W += Sc
+            lhs = u1[m, c] * W
+            if c > 0:
+                margin[m] = min(margin[m], abs(lhs - Sc) / W)
+            if lhs < Sc:
+                cdf = np.cumsum(pc)
+                target = u2[m, c] * Sc
+                j = int(np.searchsorted(cdf, target, side="right"))
+                j = min(j, len(pc) - 1)
+                while pc[j] == 0.0 and j > 0:
+                    j -= 1
+                act[m] = c * chunk + j
+                lo = cdf[j - 1] if j > 0 else 0.0
+                margin[m] = min(margin[m], abs(target - lo) / Sc, abs(cdf[j] - target) / Sc)
     return act, margin
 
 

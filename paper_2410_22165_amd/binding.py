@@ -44,6 +44,14 @@ class EjStateView(C.Structure):
     _fields_ = [(n, C.POINTER(C.c_int32)) for n in _STATE_FIELDS]
 
 
+class EjMlpDesc(C.Structure):
+    _fields_ = [("D", C.c_int32), ("D_stride", C.c_int32), ("H", C.c_int32), ("A", C.c_int32)]
+
+
+class EjMlpLayout(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_params", "n_work", "W1", "b1", "W2", "b2", "W3", "b3")]
+
+
 class EconError(RuntimeError):
     pass
 
@@ -84,11 +92,12 @@ def _declare_learner(L):
     """Signatures of the policy / learner entry points (present once built)."""
     vp, i32, i64, u64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_float
     table = {
-        "ej_policy_forward": [vp, vp, vp, i64, u64, u64, vp, vp, vp, vp, vp, vp],
+        "ej_mlp_layout": [C.POINTER(EjMlpDesc), C.POINTER(EjMlpLayout)],
+        "ej_mlp_sync_weights": [C.POINTER(EjMlpDesc), vp, vp, vp],
+        "ej_policy_forward": [C.POINTER(EjMlpDesc), vp, vp, vp, vp, i64, u64, u64, vp, vp, vp, vp, vp, vp],
         "ej_gae": [vp, vp, vp, vp, i32, i64, f32, f32, vp, vp, vp],
         "ej_ppo_backward": [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i64, i64, vp, vp, vp, vp],
         "ej_adam": [vp, vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp],
-        "ej_mlp_sync_weights": [vp, vp, vp],
     }
     for name, args in table.items():
         fn = getattr(L, name, None)
@@ -238,3 +247,47 @@ class Env:
             out[n] = st[n][:, lo:hi].copy()
         out["n_active"] = (out["orders"] >= 0).sum(axis=0).astype(np.int32)
         return out
+
+
+class Mlp:
+    """Shared policy network parameters on the GPU: the flat fp32 vector and
+    its bf16 work copy (both torch tensors; the kernels own the layouts)."""
+
+    def __init__(self, D: int, D_stride: int, H: int, A: int, weights: dict | None = None):
+        import torch
+        self.desc = EjMlpDesc(D, D_stride, H, A)
+        lay = EjMlpLayout()
+        check(lib().ej_mlp_layout(C.byref(self.desc), C.byref(lay)), "ej_mlp_layout")
+        self.layout = {n: int(getattr(lay, n)) for n, _ in EjMlpLayout._fields_}
+        self.D, self.Ds, self.H, self.A = D, D_stride, H, A
+        self.params = torch.zeros(self.layout["n_params"], dtype=torch.float32, device="cuda")
+        self.work = torch.zeros(self.layout["n_work"], dtype=torch.int16, device="cuda")
+        if weights is not None:
+            self.load(weights)
+
+    def flat(self, weights: dict) -> np.ndarray:
+        v = np.zeros(self.layout["n_params"], np.float32)
+        for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            a = np.asarray(weights[k], np.float32).ravel()
+            v[self.layout[k]:self.layout[k] + a.size] = a
+        return v
+
+    def unflat(self, v) -> dict:
+        v = np.asarray(v, np.float32)
+        D, H, A1 = self.D, self.H, self.A + 1
+        shapes = dict(W1=(D, H), b1=(H,), W2=(H, H), b2=(H,), W3=(H, A1), b3=(A1,))
+        return {k: v[self.layout[k]:self.layout[k] + int(np.prod(s))].reshape(s) for k, s in shapes.items()}
+
+    def load(self, weights: dict, stream=None):
+        import torch
+        self.params.copy_(torch.from_numpy(self.flat(weights)))
+        self.sync(stream)
+
+    def sync(self, stream=None):
+        check(lib().ej_mlp_sync_weights(C.byref(self.desc), ptr(self.params), ptr(self.work), stream_ptr(stream)),
+              "ej_mlp_sync_weights")
+
+    def forward(self, obs, mask, M: int, seed: int, ctr: int, act, logp, val, ent, logits=None, stream=None):
+        check(lib().ej_policy_forward(C.byref(self.desc), ptr(self.params), ptr(self.work), ptr(obs), ptr(mask), M,
+                                      seed, ctr, ptr(act), ptr(logp), ptr(val), ptr(ent), ptr(logits),
+                                      stream_ptr(stream)), "ej_policy_forward")

@@ -1,0 +1,133 @@
+"""GPU parity of the policy forward (C ABI) against the oracle network.
+
+Logits and values within 2e-2 absolute of the float64 oracle (bf16 weights);
+sampled actions identical to the oracle's sampler where the decision is not
+within rounding distance of a threshold (the oracle then takes it in the
+kernel's precision: bf16 hidden activations); masked actions never drawn;
+the sampler's distribution matches the softmax (chi-square)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import env as oe
+from oracle import policy as op
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # (D, Ds, H, A, M)
+    (11, 16, 64, 9, 300),
+    (35, 40, 256, 125, 1000),      # shape of the 1024 x 100 economy's policy
+    (49, 56, 512, 507, 333),       # 1000-agent economy: 5 resources, 50 prices
+    (64, 64, 128, 300, 129),
+    (35, 40, 256, 125, 1),
+]
+
+
+def run_forward(D, Ds, H, A, M, seed=0, with_logits=True):
+    import torch
+    from paper_2410_22165_amd import binding
+    print(f"[gpu] policy D={D} H={H} A={A} M={M}", flush=True)
+    w = W.policy_weights(D, H, A, seed=seed)
+    rng = np.random.default_rng(seed)
+    for k in ("b1", "b2", "b3"):
+        w[k] = (rng.standard_normal(w[k].shape) * 0.1).astype(np.float32)
+    mlp = binding.Mlp(D, Ds, H, A, w)
+    obs = W.synthetic_obs(M, D, Ds, seed=seed)
+    mask = W.synthetic_masks(M, A, seed=seed)
+    dev = "cuda"
+    t_obs = torch.from_numpy(obs.view(np.int16)).to(dev)
+    t_mask = torch.from_numpy(mask.view(np.int32)).to(dev)
+    out = dict(act=torch.zeros(M, dtype=torch.int32, device=dev), logp=torch.zeros(M, device=dev),
+               val=torch.zeros(M, device=dev), ent=torch.zeros(M, device=dev),
+               logits=torch.zeros((M, A), device=dev) if with_logits else None)
+    mlp.forward(t_obs, t_mask, M, 1234, 7, out["act"], out["logp"], out["val"], out["ent"], out["logits"])
+    torch.cuda.synchronize()
+    res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    return w, obs, mask, res
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_policy_forward_parity(case):
+    D, Ds, H, A, M = case
+    w, obs, mask, g = run_forward(D, Ds, H, A, M)
+    x = oe.bf16_bits_to_f32(obs[:, :D]).astype(np.float64)
+    wb = op.bf16_weights(w)
+    logits, value = op.mlp(x, wb)
+    allowed = op.unpack_mask(mask, A)
+    # logits and values: 2e-2 absolute against the float64 network
+    assert np.abs(g["logits"] - logits).max() <= 2e-2, np.abs(g["logits"] - logits).max()
+    assert np.abs(g["val"] - value).max() <= 2e-2
+    lp = op.masked_log_softmax(logits, allowed)
+    ent = op.entropy(lp)
+    assert np.abs(g["ent"] - ent).max() <= 2e-2
+    # every sampled action is allowed, and its log-probability is consistent
+    assert allowed[np.arange(M), g["act"]].all()
+    assert np.abs(g["logp"] - lp[np.arange(M), g["act"]]).max() <= 2e-2
+    # decisions: the oracle samples from bf16-hidden logits with the same uniforms
+    l16, _ = op.mlp(x, wb, bf16_hidden=True)
+    lp16 = op.masked_log_softmax(l16, allowed)
+    NC = (A + 1 + 127) // 128
+    u1, u2 = oe.sample_uniforms(1234, np.arange(M), 7, NC)
+    pad = NC * 128 - A
+    lp16p = np.concatenate([lp16, np.full((M, pad), -np.inf)], axis=1)
+    a_o, margin = op.sample_chunked(lp16p, u1, u2)
+    safe = margin > 1e-4
+    assert safe.mean() > 0.9
+    assert np.array_equal(g["act"][safe], a_o[safe]), np.flatnonzero(g["act"][safe] != a_o[safe])[:10]
+
+
+def test_sampler_distribution_chi_square():
+    """Many rows with the same observation: the empirical action histogram
+    matches the softmax of the oracle logits."""
+    import scipy.stats
+    import torch
+    from paper_2410_22165_amd import binding
+    D, Ds, H, A, M = 35, 40, 256, 125, 200000
+    w = W.policy_weights(D, H, A, seed=3)
+    w["W3"] *= 3.0  # a peaked, non-uniform distribution
+    mlp = binding.Mlp(D, Ds, H, A, w)
+    obs1 = W.synthetic_obs(1, D, Ds, seed=3)
+    mask1 = W.synthetic_masks(1, A, seed=3, p_allow=0.3)
+    obs = np.repeat(obs1, M, axis=0)
+    mask = np.repeat(mask1, M, axis=0)
+    dev = "cuda"
+    act = torch.zeros(M, dtype=torch.int32, device=dev)
+    f = [torch.zeros(M, device=dev) for _ in range(3)]
+    mlp.forward(torch.from_numpy(obs.view(np.int16)).to(dev), torch.from_numpy(mask.view(np.int32)).to(dev), M, 99, 0,
+                act, *f)
+    counts = np.bincount(act.cpu().numpy(), minlength=A)
+    allowed = op.unpack_mask(mask1, A)[0]
+    assert counts[~allowed].sum() == 0
+    x = oe.bf16_bits_to_f32(obs1[:, :D]).astype(np.float64)
+    logits, _ = op.mlp(x, op.bf16_weights(w), bf16_hidden=True)
+    p = np.exp(op.masked_log_softmax(logits, allowed[None])[0])
+    exp_c = p[allowed] * M
+    keep = exp_c > 5
+    chi = scipy.stats.chisquare(counts[allowed][keep], exp_c[keep] * counts[allowed][keep].sum() / exp_c[keep].sum())
+    assert chi.pvalue > 1e-4, chi
+
+
+def test_sampler_multi_chunk_distribution():
+    """507 actions (4 chunks of 128): the chunk reservoir draws each chunk
+    with its total probability."""
+    import torch
+    from paper_2410_22165_amd import binding
+    D, Ds, H, A, M = 49, 56, 512, 507, 100000
+    w = W.policy_weights(D, H, A, seed=4)
+    mlp = binding.Mlp(D, Ds, H, A, w)
+    obs1 = W.synthetic_obs(1, D, Ds, seed=4)
+    mask1 = W.synthetic_masks(1, A, seed=4, p_allow=0.5)
+    dev = "cuda"
+    act = torch.zeros(M, dtype=torch.int32, device=dev)
+    f = [torch.zeros(M, device=dev) for _ in range(3)]
+    mlp.forward(torch.from_numpy(np.repeat(obs1, M, 0).view(np.int16)).to(dev),
+                torch.from_numpy(np.repeat(mask1, M, 0).view(np.int32)).to(dev), M, 5, 0, act, *f)
+    a = act.cpu().numpy()
+    x = oe.bf16_bits_to_f32(obs1[:, :D]).astype(np.float64)
+    logits, _ = op.mlp(x, op.bf16_weights(w), bf16_hidden=True)
+    allowed = op.unpack_mask(mask1, A)[0]
+    p = np.exp(op.masked_log_softmax(logits, allowed[None])[0])
+    for c in range(4):
+        frac = ((a >= 128 * c) & (a < 128 * (c + 1))).mean()
+        pc = p[128 * c:128 * (c + 1)].sum()
+        assert abs(frac - pc) < 5 * np.sqrt(pc * (1 - pc) / M) + 1e-3, (c, frac, pc)

@@ -138,3 +138,25 @@ def affine_permutation(M: int, epoch: int, seed: int = 0):
             break
     c = int(rng.integers(0, max(M, 1)))
     return a, c
+
+
+def synthetic_obs(M: int, D: int, Ds: int, seed: int = 0) -> np.ndarray:
+    """Observation rows as bf16 bit patterns [M, Ds]: values k/16 with
+    k in -40..40 (exact in bf16), zero padding beyond D."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x0B5]))
+    v = (rng.integers(-40, 41, size=(M, D)) / 16.0).astype(np.float32)
+    bits = np.zeros((M, Ds), np.uint16)
+    bits[:, :D] = (v.view(np.uint32) >> 16).astype(np.uint16)
+    return bits
+
+
+def synthetic_masks(M: int, A: int, seed: int = 0, p_allow: float = 0.4) -> np.ndarray:
+    """Action-mask words [M, ceil(A/32)]; every row allows at least one action."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x3A5C]))
+    allow = rng.random((M, A)) < p_allow
+    allow[np.arange(M), rng.integers(0, A, size=M)] = True
+    W = (A + 31) // 32
+    words = np.zeros((M, W), np.uint32)
+    for a in range(A):
+        words[:, a // 32] |= allow[:, a].astype(np.uint32) << np.uint32(a % 32)
+    return words
