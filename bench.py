@@ -1,0 +1,206 @@
+"""Throughput of the batched economy rollout step on one MI355X.
+
+A step is one pass of the hot path over the 1024-economy x 100-agent
+synthetic workload (3 resources, 20 price levels, order lifetime 10, tax
+period 100, 1000-step episodes): the shared policy network samples every
+agent's action from the current observation (35 -> 256 -> 256 -> 125 + 1,
+bf16 MFMA), the government draws its tax levels, and the economy step
+applies the actions, clears the markets, taxes and redistributes, computes
+the rewards and writes the next observation and action mask.  Inputs are
+resident in HBM before the timed region starts.
+
+Prints one JSON line (metric, value, ms_per_step, roofline of the dominant
+kernel measured with HIP events, CPU-oracle baseline on a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+WORKLOAD = "econ_e1024_n100"
+POLICY_WORKLOAD = "econ_e4096_n100_ppo"  # the policy network shape (hidden 256)
+
+
+def env_bytes_per_agent_step(cfg, D, A) -> int:
+    """Algorithmic HBM bytes one agent-step of the economy must move:
+    mutable state read and written (coin in inventory and escrow, labor,
+    period snapshot, R inventories, R escrows, X order slots: int32), the
+    skills read (R + 1 int32), the action read, the reward and done flag
+    written, the bf16 observation (D features) and the mask bits written."""
+    R, X = cfg["R"], cfg["X"]
+    mutable = 4 * (4 + 2 * R + X)
+    return 2 * mutable + 4 * (R + 1) + 4 + 4 + 1 + 2 * D + 4 * ((A + 31) // 32)
+
+
+def policy_flops_per_row(D, H, A) -> int:
+    return 2 * (D * H + H * H + H * (A + 1))
+
+
+def cpu_baseline(cfg, weights, budget_s: float = 12.0):
+    """The oracle as it stands (C economy, float64 numpy policy with its own
+    sampler), single-threaded, on a bounded sample: economies of the same
+    workload stepped until the time budget is spent."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import env as oe
+    from oracle import policy as op
+
+    sc = W.obs_scales(cfg)
+    Ds = W.obs_stride(cfg)
+    A = W.num_actions(cfg)
+    D = W.obs_dim(cfg)
+    envs = [oe.OracleEnv(cfg, e=e, seed=cfg["seed"]) for e in range(4)]
+    wb = op.bf16_weights(weights)
+    agent_steps = 0
+    steps = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            for e, env in enumerate(envs):
+                obs, mask, _ = env.observe(sc, Ds, with_gov=False)
+                x = oe.bf16_bits_to_f32(obs[:, :D]).astype(np.float64)
+                logits, _ = op.mlp(x, wb)
+                lp = op.masked_log_softmax(logits, op.unpack_mask(mask, A))
+                u1, u2 = oe.sample_uniforms(1, np.arange(cfg["N"]) + e * cfg["N"], steps, 1)
+                act, _ = op.sample_chunked(np.concatenate([lp, np.full((cfg["N"], 128 - A), -np.inf)], 1), u1, u2)
+                _, gov = env.random_actions(2)
+                env.step(act.astype(np.int32), gov)
+                agent_steps += cfg["N"]
+            steps += 1
+        dt = time.perf_counter() - t0
+    return dict(value=agent_steps / dt, unit="agent-steps/s", cores=1, kind="oracle",
+                sample=f"{len(envs)} economies x {cfg['N']} agents x {steps} steps of the same workload "
+                       f"(C economy step + float64 numpy policy and sampler), {dt:.1f} s, one thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (one process, one MI355X)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2410_22165_amd import binding
+
+    torch.cuda.set_device(0)
+    wl = W.workload(WORKLOAD)
+    cfg = wl["env"]
+    H = W.workload(POLICY_WORKLOAD)["hidden"]
+    env = binding.Env(cfg, W.obs_scales(cfg))
+    b = env.buffers()
+    M, A, D, Ds = env.M, env.A, env.D, env.Ds
+    weights = W.policy_weights(D, H, A, seed=0)
+    mlp = binding.Mlp(D, Ds, H, A, weights)
+    dev = torch.device("cuda")
+    act = torch.zeros(M, dtype=torch.int32, device=dev)
+    logp, val, ent = (torch.zeros(M, device=dev) for _ in range(3))
+    stream = torch.cuda.current_stream()
+    env.observe(b["obs"], b["mask"])
+
+    def policy(i):
+        mlp.forward(b["obs"], b["mask"], M, 1, i, act, logp, val, ent)
+
+    def economy(i):
+        env.random_actions(2, None, b["gov"])
+        env.step(act, b["gov"], b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
+
+    for i in range(args.warmup):
+        policy(i)
+        economy(i)
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for i in range(args.steps):
+        policy(args.warmup + i)
+        economy(args.warmup + i)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(stop)
+    ms_step = ms_total / args.steps
+    value = M * args.steps / (ms_total / 1e3)
+
+    # per-kernel durations with HIP events on the launch stream
+    n_k = min(args.steps, 100)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(n_k)]
+    for i in range(n_k):
+        ev[i][0].record(stream)
+        policy(10 ** 6 + i)
+        ev[i][1].record(stream)
+        env.random_actions(2, None, b["gov"])
+        ev[i][2].record(stream)
+        env.step(act, b["gov"], b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
+        ev[i][3].record(stream)
+    torch.cuda.synchronize()
+    ms_pol = float(np.mean([ev[i][0].elapsed_time(ev[i][1]) for i in range(n_k)]))
+    ms_env = float(np.mean([ev[i][2].elapsed_time(ev[i][3]) for i in range(n_k)]))
+
+    env_bytes = env_bytes_per_agent_step(cfg, D, A) * M
+    pol_flops = policy_flops_per_row(D, H, A) * M
+    env_gbs = env_bytes / (ms_env / 1e3) / 1e9
+    pol_tflops = pol_flops / (ms_pol / 1e3) / 1e12
+    kernels = {
+        "env_step_kernel": {"bound": "hbm", "achieved": env_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": env_gbs / HBM_PEAK_GBS, "ms": ms_env,
+                            "algorithmic_bytes_per_launch": env_bytes},
+        "policy_forward_kernel": {"bound": "mfma", "achieved": pol_tflops, "peak": BF16_PEAK_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": pol_tflops / BF16_PEAK_TFLOPS, "ms": ms_pol,
+                                  "algorithmic_flops_per_launch": pol_flops},
+    }
+    dom = "env_step_kernel" if ms_env >= ms_pol else "policy_forward_kernel"
+    k = kernels[dom]
+    roofline = {"kernel": dom, "bound": k["bound"], "achieved": round(k["achieved"], 3), "peak": k["peak"],
+                "unit": k["unit"], "frac": round(k["frac"], 5), "traffic": None}
+
+    out = {
+        "metric": "agent-steps/sec (env+policy) at E×N=1024×100",
+        "value": round(value, 1),
+        "unit": "agent-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32 economy + bf16 MFMA / fp32 policy",
+        "data": "synthetic (seed-generated economies; random-init policy weights)",
+        "config": {"workload": WORKLOAD, "E": cfg["E"], "N": cfg["N"], "R": cfg["R"], "P": cfg["P"],
+                   "X": cfg["X"], "P_tax": cfg["P_tax"], "K": cfg["K"], "T": cfg["T"],
+                   "policy": f"{D}->{H}->{H}->{A}+1", "parallelism": "one workgroup per economy"},
+        "roofline": roofline,
+        "kernels": {n: {kk: (round(v, 5) if isinstance(v, float) else v) for kk, v in d.items()}
+                    for n, d in kernels.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, weights, args.cpu_budget)
+        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)
+    env.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -163,7 +163,8 @@ int ej_env_observe(ej_env* env, uint16_t* d_obs, uint32_t* d_mask, float* d_gov_
 
 /* Synthetic workload actions for the current step of every economy: uniform
  * over the A population actions, keyed (act_seed, economy, episode, step,
- * agent), and uniform government levels over 0..20. */
+ * agent), and uniform government levels over 0..20.  d_act may be NULL
+ * (government levels only). */
 int ej_env_random_actions(ej_env* env, uint64_t act_seed, int32_t* d_act, int32_t* d_gov, void* stream);
 
 /* Synchronous copies of the whole state to / from host arrays (checkpoint
@@ -215,6 +216,67 @@ int ej_mlp_sync_weights(const ej_mlp_desc* m, const float* d_params, uint16_t* d
 int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const uint16_t* d_obs,
                       const uint32_t* d_mask, int64_t M, uint64_t seed, uint64_t ctr, int32_t* d_act, float* d_logp,
                       float* d_val, float* d_ent, float* d_logits, void* stream);
+
+/* ------------------------------------------------------------------------
+ * PPO learner (Table 2: clipped surrogate, clipped value loss, entropy
+ * bonus, GAE; Sec. 4: population agents share the network).
+ * ------------------------------------------------------------------------ */
+
+/* Generalised advantage estimation over a rollout of T steps and M rows
+ * (all arrays [T * M], time-major): d_done[t] = 1 when step t ended an
+ * episode; d_last_val [M] is the value of the state after the last step.
+ * adv_t = delta_t + gamma lam (1 - done_t) adv_{t+1},
+ * delta_t = r_t + gamma (1 - done_t) V_{t+1} - V_t; ret = adv + V. fp32. */
+int ej_gae(const float* d_rew, const float* d_val, const uint8_t* d_done, const float* d_last_val, int32_t T,
+           int64_t M, float gamma, float lam, float* d_adv, float* d_ret, void* stream);
+
+/* A minibatch of the rollout storage (every array indexed by the sample
+ * index s in [0, M_total), device pointers): observation rows and mask
+ * words as written by the environment, the action taken, its log-probability
+ * and the value at collection time, the advantage and the return.  Row j of
+ * the epoch is the sample (perm_a * j + perm_c) mod M_total (perm_a coprime
+ * with M_total makes this a permutation); the minibatch is epoch rows
+ * [row_begin, row_begin + rows). */
+typedef struct ej_ppo_batch {
+    const uint16_t* obs;
+    const uint32_t* mask;
+    const int32_t* act;
+    const float* logp_old;
+    const float* val_old;
+    const float* adv;
+    const float* ret;
+    int64_t M_total, perm_a, perm_c, row_begin, rows;
+} ej_ppo_batch;
+
+/* clip epsilon (0.2), value clip (10), value coefficient c_v (0.25),
+ * entropy coefficient c_e (0.1, annealed by the caller) */
+typedef struct ej_ppo_hparams {
+    float clip, vclip, vf_coef, ent_coef;
+} ej_ppo_hparams;
+
+/* Bytes of device scratch ej_ppo_backward needs for a minibatch of `rows`. */
+int ej_ppo_workspace_size(const ej_mlp_desc* m, int64_t rows, int64_t* bytes);
+
+/* Loss and gradient of one PPO minibatch with respect to every parameter:
+ *   L = mean(-min(rho A, clip(rho, 1 - eps, 1 + eps) A))
+ *     + c_v mean(1/2 max((V - R)^2, (V_old + clip(V - V_old, -vclip, vclip) - R)^2))
+ *     - c_e mean(H),
+ * rho = exp(log pi(a) - logp_old), A the advantage normalised over the
+ * minibatch (population std + 1e-8), H the entropy of the masked policy.
+ * The forward pass is recomputed from the stored observations (activations
+ * of the rollout are never stored).  d_grads [n_params] is overwritten (not
+ * accumulated); d_loss [4] receives mean surrogate, value, entropy terms and
+ * the clipped fraction.  d_workspace: caller-owned device scratch of at
+ * least ej_ppo_workspace_size bytes.  Deterministic: the weight gradients
+ * are reduced over a fixed split in a fixed order. */
+int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const ej_ppo_batch* b,
+                    const ej_ppo_hparams* hp, void* d_workspace, int64_t workspace_bytes, float* d_grads,
+                    float* d_loss, void* stream);
+
+/* Adam (Kingma & Ba) with bias correction on n fp32 parameters; `step` is
+ * the 1-based update count. */
+int ej_adam(float* d_params, const float* d_grads, float* d_m, float* d_v, int64_t n, int32_t step, float lr,
+            float beta1, float beta2, float eps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -52,6 +52,15 @@ class EjMlpLayout(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_params", "n_work", "W1", "b1", "W2", "b2", "W3", "b3")]
 
 
+class EjPpoBatch(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("obs", "mask", "act", "logp_old", "val_old", "adv", "ret")] + [
+        (n, C.c_int64) for n in ("M_total", "perm_a", "perm_c", "row_begin", "rows")]
+
+
+class EjPpoHparams(C.Structure):
+    _fields_ = [(n, C.c_float) for n in ("clip", "vclip", "vf_coef", "ent_coef")]
+
+
 class EconError(RuntimeError):
     pass
 
@@ -96,8 +105,10 @@ def _declare_learner(L):
         "ej_mlp_sync_weights": [C.POINTER(EjMlpDesc), vp, vp, vp],
         "ej_policy_forward": [C.POINTER(EjMlpDesc), vp, vp, vp, vp, i64, u64, u64, vp, vp, vp, vp, vp, vp],
         "ej_gae": [vp, vp, vp, vp, i32, i64, f32, f32, vp, vp, vp],
-        "ej_ppo_backward": [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, i64, i64, vp, vp, vp, vp],
-        "ej_adam": [vp, vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp],
+        "ej_ppo_workspace_size": [C.POINTER(EjMlpDesc), i64, C.POINTER(i64)],
+        "ej_ppo_backward": [C.POINTER(EjMlpDesc), vp, vp, C.POINTER(EjPpoBatch), C.POINTER(EjPpoHparams), vp, i64,
+                            vp, vp, vp],
+        "ej_adam": [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp],
     }
     for name, args in table.items():
         fn = getattr(L, name, None)
@@ -291,3 +302,30 @@ class Mlp:
         check(lib().ej_policy_forward(C.byref(self.desc), ptr(self.params), ptr(self.work), ptr(obs), ptr(mask), M,
                                       seed, ctr, ptr(act), ptr(logp), ptr(val), ptr(ent), ptr(logits),
                                       stream_ptr(stream)), "ej_policy_forward")
+
+
+def gae(rew, val, done, last_val, T: int, M: int, gamma: float, lam: float, adv, ret, stream=None):
+    check(lib().ej_gae(ptr(rew), ptr(val), ptr(done), ptr(last_val), T, M, gamma, lam, ptr(adv), ptr(ret),
+                       stream_ptr(stream)), "ej_gae")
+
+
+def adam(params, grads, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    check(lib().ej_adam(ptr(params), ptr(grads), ptr(m), ptr(v), params.numel(), step, lr, beta1, beta2, eps,
+                        stream_ptr(stream)), "ej_adam")
+
+
+def ppo_workspace_bytes(mlp: "Mlp", rows: int) -> int:
+    out = C.c_int64()
+    check(lib().ej_ppo_workspace_size(C.byref(mlp.desc), rows, C.byref(out)), "ej_ppo_workspace_size")
+    return int(out.value)
+
+
+def ppo_backward(mlp: "Mlp", storage: dict, M_total: int, perm_a: int, perm_c: int, row_begin: int, rows: int,
+                 hp: dict, workspace, grads, loss, stream=None):
+    """storage: torch tensors obs, mask, act, logp_old, val_old, adv, ret indexed by sample."""
+    b = EjPpoBatch(*(ptr(storage[k]) for k in ("obs", "mask", "act", "logp_old", "val_old", "adv", "ret")),
+                   M_total, perm_a, perm_c, row_begin, rows)
+    h = EjPpoHparams(hp["clip"], hp["vclip"], hp["vf_coef"], hp["ent_coef"])
+    check(lib().ej_ppo_backward(C.byref(mlp.desc), ptr(mlp.params), ptr(mlp.work), C.byref(b), C.byref(h),
+                                ptr(workspace), workspace.numel(), ptr(grads), ptr(loss), stream_ptr(stream)),
+          "ej_ppo_backward")

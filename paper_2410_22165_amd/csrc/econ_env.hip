@@ -1046,9 +1046,11 @@ __global__ void env_random_actions_kernel(const EnvParams P, const EnvState S, u
     const int n = S.env_n[e];
     const int64_t row0 = S.env_row[e];
     const int t = S.env_t[e], ep = S.env_ep[e];
-    for (int li = threadIdx.x; li < n; li += blockDim.x) {
-        u64x4 w = philox(act_seed, PURPOSE_ACT, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)li);
-        act[row0 + li] = (int32_t)(((w.x >> 32) * (uint64_t)P.A) >> 32);
+    if (act) {
+        for (int li = threadIdx.x; li < n; li += blockDim.x) {
+            u64x4 w = philox(act_seed, PURPOSE_ACT, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)li);
+            act[row0 + li] = (int32_t)(((w.x >> 32) * (uint64_t)P.A) >> 32);
+        }
     }
     if ((int)threadIdx.x < P.K) {
         const int b = threadIdx.x;
@@ -1290,7 +1292,7 @@ int ej_env_observe(ej_env* h, uint16_t* d_obs, uint32_t* d_mask, float* d_gov_ob
 
 int ej_env_random_actions(ej_env* h, uint64_t act_seed, int32_t* d_act, int32_t* d_gov, void* stream)
 {
-    if (!h || !d_act || (h->P.K > 0 && !d_gov)) return EJ_EINVAL;
+    if (!h || (h->P.K > 0 && !d_gov)) return EJ_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     env_random_actions_kernel<<<h->E, 256, 0, st>>>(h->P, h->state(), act_seed, d_act, d_gov);
     EJ_LAUNCH_CHECK();

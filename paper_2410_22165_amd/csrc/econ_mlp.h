@@ -35,7 +35,7 @@ __host__ inline int mlp_dims(int D, int Ds, int H, int A, MlpDims* d)
     d->H = H;
     d->A = A;
     d->A1 = A + 1;
-    d->K1p = round_up(D, 32);
+    d->K1p = 64;  // first-layer input padded to 64 (one layout for every D <= 64)
     d->A1p = round_up(A + 1, 128);
     d->NC = d->A1p / 128;
     int64_t o = 0;
@@ -129,9 +129,10 @@ __device__ inline void zero_acc(f32x4 (&acc)[RT][CT])
 // `kstride`: elements between the global chunks of consecutive k-steps.
 template <int RT, int N>
 __device__ inline void dense_layer(f32x4 (&acc)[RT][N / 16], const uint16_t* abuf, int as, int arow0, int K,
-                                   const uint16_t* __restrict__ wglob, int64_t kstride, uint16_t* wbuf)
+                                   const uint16_t* __restrict__ wglob, int64_t kstride, uint16_t* wbuf,
+                                   bool zero = true, int acol0 = 0)
 {
-    zero_acc(acc);
+    if (zero) zero_acc(acc);
     ChunkRegs<N> regs;
     chunk_load<N>(regs, wglob);
     const int nk = K / 32;
@@ -140,7 +141,7 @@ __device__ inline void dense_layer(f32x4 (&acc)[RT][N / 16], const uint16_t* abu
         chunk_store<N>(regs, wbuf);
         __syncthreads();
         if (kt + 1 < nk) chunk_load<N>(regs, wglob + (int64_t)(kt + 1) * kstride);
-        mfma_chunk<RT, N / 16>(acc, abuf, as, arow0, kt * 32, wbuf);
+        mfma_chunk<RT, N / 16>(acc, abuf, as, arow0, acol0 + kt * 32, wbuf);
     }
 }
 

@@ -1,0 +1,768 @@
+// econ_ppo.hip -- the PPO learner on gfx950: generalised advantage
+// estimation, the fused minibatch backward of the shared policy network, the
+// weight-gradient GEMMs with a deterministic split-M reduction, and Adam.
+//
+// PPO as configured in the paper's Table 2 (clipped surrogate, clipped value
+// loss with coefficient c_v, entropy bonus c_e, GAE(gamma, lambda)); the
+// network and its masked softmax are those of econ_policy.hip.
+//
+// Backward data flow for a minibatch of `rows` samples (row j of the epoch
+// maps to sample (a j + c) mod M):
+//   ppo_rows_kernel  per 128-row tile: gathers the samples, recomputes
+//     h1, h2 and the logits (never stored per rollout: activations are
+//     recomputed here), forms the loss gradient dY = dL/d[logits | value]
+//     from the row statistics of the masked softmax, and back-propagates
+//     dh2 = (dY W3^T) * [h2 > 0] and dh1 = (dh2 W2^T) * [h1 > 0].  The GEMM
+//     operands of the weight gradients (obs, h1, h2, dY, dh2, dh1) are
+//     written in bf16 "m-block" layout [rows / 32][column][32 rows].
+//   dw_kernel        dW = X^T Y as bf16 MFMA with the 32-row m-block as the
+//     k-step; every workgroup owns a C tile and a contiguous range of
+//     m-blocks and writes an fp32 partial; column sums of Y give the bias
+//     gradients.
+//   dw_reduce_kernel sums the partials in a fixed order (deterministic).
+#include "econ_mlp.h"
+
+namespace econ {
+
+struct PpoBatchDev {
+    const uint16_t* obs;
+    const uint32_t* mask;
+    const int32_t* act;
+    const float* logp_old;
+    const float* val_old;
+    const float* adv;
+    const float* ret;
+    int64_t Mtot, a, c, begin, rows;
+};
+
+struct PpoHp {
+    float clip, vclip, vf_coef, ent_coef;
+};
+
+__device__ inline int64_t sample_of(const PpoBatchDev& B, int64_t j)
+{
+    return (int64_t)(((uint64_t)B.a * (uint64_t)(B.begin + j) + (uint64_t)B.c) % (uint64_t)B.Mtot);
+}
+
+// ---------------------------------------------------------------------------
+// GAE: one thread per row, reverse over time; coalesced over rows
+// ---------------------------------------------------------------------------
+__global__ void gae_kernel(const float* __restrict__ rew, const float* __restrict__ val,
+                           const uint8_t* __restrict__ done, const float* __restrict__ last_val, int T, int64_t M,
+                           float gamma, float lam, float* __restrict__ adv, float* __restrict__ ret)
+{
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M; m += (int64_t)gridDim.x * blockDim.x) {
+        float next_val = last_val[m], next_adv = 0.f;
+        for (int t = T - 1; t >= 0; --t) {
+            const int64_t i = (int64_t)t * M + m;
+            const float nonterm = done[i] ? 0.f : 1.f;
+            const float v = val[i];
+            const float delta = rew[i] + gamma * next_val * nonterm - v;
+            next_adv = delta + gamma * lam * nonterm * next_adv;
+            adv[i] = next_adv;
+            ret[i] = next_adv + v;
+            next_val = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// advantage statistics of the minibatch (two deterministic stages)
+// ---------------------------------------------------------------------------
+__global__ void adv_stats_partial(const PpoBatchDev B, double* __restrict__ part)
+{
+    __shared__ double red[2][16];
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < B.rows; j += (int64_t)gridDim.x * blockDim.x) {
+        const double a = B.adv[sample_of(B, j)];
+        s1 += a;
+        s2 += a * a;
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        red[0][w] = s1;
+        red[1][w] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+            a += red[0][k];
+            b += red[1][k];
+        }
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// stats[0] = mean, stats[1] = 1 / (population std + 1e-8)
+__global__ void adv_stats_final(const double* __restrict__ part, int nb, int64_t rows, float* __restrict__ stats)
+{
+    if (threadIdx.x != 0) return;
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < nb; ++k) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    const double mean = a / (double)rows;
+    double var = b / (double)rows - mean * mean;
+    if (var < 0.0) var = 0.0;
+    stats[0] = (float)mean;
+    stats[1] = (float)(1.0 / (sqrt(var) + 1e-8));
+}
+
+// ---------------------------------------------------------------------------
+// the fused row kernel
+// ---------------------------------------------------------------------------
+__device__ inline float group16_max(float v)
+{
+#pragma unroll
+    for (int k = 1; k < 16; k <<= 1) v = fmaxf(v, __shfl_xor(v, k, 64));
+    return v;
+}
+__device__ inline float group16_sum(float v)
+{
+#pragma unroll
+    for (int k = 1; k < 16; k <<= 1) v += __shfl_xor(v, k, 64);
+    return v;
+}
+
+// 4 consecutive rows (acc element order) of one column -> 8-byte store in the m-block layout
+__device__ inline void store_mblock4(uint16_t* T, int ncol, int64_t jrow, int col, const float (&v)[4])
+{
+    const int64_t mb = jrow >> 5;
+    const int r = (int)(jrow & 31);
+    uint2 p;
+    p.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+    p.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+    *(uint2*)(T + (mb * ncol + col) * 32 + r) = p;
+}
+
+// bias + ReLU of a hidden layer: bf16 into the wave's own LDS rows, the
+// m-block copy for the weight gradient, and the ReLU mask bits
+template <int RT, int CT>
+__device__ inline void ppo_hidden_epilogue(const f32x4 (&acc)[RT][CT], const float* __restrict__ bias, uint16_t* hbuf,
+                                           int hs, int arow0, uint16_t* Tout, int64_t tile_row0,
+                                           uint32_t (&bits)[RT][(CT + 7) / 8])
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int w = 0; w < (CT + 7) / 8; ++w) bits[rt][w] = 0u;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int col = ct * 16 + (l & 15);
+        const float b = bias[col];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int rloc = arow0 + rt * 16 + 4 * (l >> 4);
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float x = acc[rt][ct][i] + b;
+                v[i] = x > 0.f ? x : 0.f;
+                if (x > 0.f) bits[rt][ct >> 3] |= 1u << ((ct & 7) * 4 + i);
+                hbuf[(rloc + i) * hs + col] = f32_to_bf16(v[i]);
+            }
+            store_mblock4(Tout, CT * 16, tile_row0 + rloc, col, v);
+        }
+    }
+}
+
+template <int H>
+struct PpoTile {
+    using T = MlpTile<H>;
+    static constexpr int YS = 128 + 8;  // LDS row stride of the dY chunk
+};
+
+template <int H>
+size_t ppo_rows_lds_bytes(int W)
+{
+    using T = MlpTile<H>;
+    return (size_t)T::TILE * T::HS * 2 + (size_t)T::TILE * PpoTile<H>::YS * 2 + (size_t)T::WREG * 2 +
+           (size_t)T::TILE * 6 * 4 + (size_t)T::TILE * W * 4 + 64 * 4;
+}
+
+template <int H>
+__global__ void __launch_bounds__(256)
+ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
+                const PpoBatchDev B, const PpoHp hp, const float* __restrict__ stats, int W,
+                uint16_t* __restrict__ Tobs, uint16_t* __restrict__ Th1, uint16_t* __restrict__ Th2,
+                uint16_t* __restrict__ TdY, uint16_t* __restrict__ Tdh2, uint16_t* __restrict__ Tdh1,
+                float* __restrict__ loss_parts)
+{
+    using T = MlpTile<H>;
+    constexpr int RT = T::RT, RPW = T::RPW, TILE = T::TILE, HS = T::HS, YS = PpoTile<H>::YS;
+    constexpr int CT = H / 16;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* hbuf = (uint16_t*)smem;
+    uint16_t* ybuf = hbuf + TILE * HS;
+    uint16_t* wbuf = ybuf + TILE * YS;
+    float* rinfo = (float*)(wbuf + T::WREG);  // [6][TILE]: act, logp_old, val_old, adv_hat, ret, valid
+    uint32_t* smask = (uint32_t*)(rinfo + 6 * TILE);
+    float* lred = (float*)(smask + TILE * W);  // [4 waves][4]
+
+    const int wave = threadIdx.x >> 6, l = lane_id();
+    const int64_t tile_row0 = (int64_t)blockIdx.x * TILE;
+    const int arow0 = wave * RPW;
+    const float inv_n = 1.0f / (float)B.rows;
+
+    // gather the tile's samples
+    for (int r = threadIdx.x; r < TILE; r += 256) {
+        const int64_t j = tile_row0 + r;
+        float va = 0.f, lpo = 0.f, vo = 0.f, ah = 0.f, rt = 0.f, valid = 0.f;
+        if (j < B.rows) {
+            const int64_t s = sample_of(B, j);
+            va = __int_as_float(B.act[s]);
+            lpo = B.logp_old[s];
+            vo = B.val_old[s];
+            ah = (B.adv[s] - stats[0]) * stats[1];
+            rt = B.ret[s];
+            valid = 1.f;
+            for (int w = 0; w < W; ++w) smask[r * W + w] = B.mask[s * W + w];
+        } else {
+            for (int w = 0; w < W; ++w) smask[r * W + w] = 0u;
+        }
+        rinfo[0 * TILE + r] = va;
+        rinfo[1 * TILE + r] = lpo;
+        rinfo[2 * TILE + r] = vo;
+        rinfo[3 * TILE + r] = ah;
+        rinfo[4 * TILE + r] = rt;
+        rinfo[5 * TILE + r] = valid;
+    }
+    const int ppr = d.K1p / 8;
+    for (int p = threadIdx.x; p < TILE * ppr; p += 256) {
+        const int r = p / ppr, cc = p - r * ppr;
+        const int64_t j = tile_row0 + r;
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (j < B.rows && cc * 8 < d.Ds) v = *(const uint4*)(B.obs + sample_of(B, j) * d.Ds + cc * 8);
+        *(uint4*)(hbuf + r * HS + cc * 8) = v;
+    }
+    __syncthreads();
+    // observation m-blocks for dW1: piece = (block, column, quarter of 8 rows)
+    for (int p = threadIdx.x; p < (TILE / 32) * d.K1p * 4; p += 256) {
+        const int q = p & 3, col = (p >> 2) % d.K1p, blk = (p >> 2) / d.K1p;
+        uint32_t w4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r0 = blk * 32 + q * 8 + 2 * k;
+            w4[k] = (uint32_t)hbuf[r0 * HS + col] | ((uint32_t)hbuf[(r0 + 1) * HS + col] << 16);
+        }
+        const int64_t mb = (tile_row0 >> 5) + blk;
+        *(uint4*)(Tobs + (mb * d.K1p + col) * 32 + q * 8) = uint4{w4[0], w4[1], w4[2], w4[3]};
+    }
+
+    f32x4 acc[RT][CT];
+    uint32_t m1[RT][(CT + 7) / 8], m2[RT][(CT + 7) / 8];
+    dense_layer<RT, H>(acc, hbuf, HS, arow0, d.K1p, work + d.oW1f, (int64_t)H * 32, wbuf);
+    ppo_hidden_epilogue<RT, CT>(acc, params + d.ob1, hbuf, HS, arow0, Th1, tile_row0, m1);
+    dense_layer<RT, H>(acc, hbuf, HS, arow0, H, work + d.oW2f, (int64_t)H * 32, wbuf);
+    ppo_hidden_epilogue<RT, CT>(acc, params + d.ob2, hbuf, HS, arow0, Th2, tile_row0, m2);
+
+    // ---- pass 1: statistics of the masked softmax, logit of the taken action, value
+    const float NEG = -__builtin_huge_valf();
+    float sm[RT][4], sS[RT][4], sT[RT][4], za[RT][4], zv[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            sm[rt][i] = NEG;
+            sS[rt][i] = 0.f;
+            sT[rt][i] = 0.f;
+            za[rt][i] = 0.f;
+            zv[rt][i] = 0.f;
+        }
+    f32x4 acc3[RT][8];
+    for (int c = 0; c < d.NC; ++c) {
+        dense_layer<RT, 128>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32,
+                             wbuf);
+        float bcol[8];
+#pragma unroll
+        for (int ct = 0; ct < 8; ++ct) {
+            const int col = c * 128 + ct * 16 + (l & 15);
+            bcol[ct] = col < d.A1 ? params[d.ob3 + col] : 0.f;
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int rloc = arow0 + rt * 16 + 4 * (l >> 4) + i;
+                const int a_taken = __float_as_int(rinfo[rloc]);
+                float zmax = NEG, zsel = 0.f, zval = 0.f;
+#pragma unroll
+                for (int ct = 0; ct < 8; ++ct) {
+                    const int col = c * 128 + ct * 16 + (l & 15);
+                    const float z = acc3[rt][ct][i] + bcol[ct];
+                    const bool ok = col < d.A && ((smask[rloc * W + (col >> 5)] >> (col & 31)) & 1u);
+                    if (ok) zmax = fmaxf(zmax, z);
+                    if (col == a_taken) zsel = z;
+                    if (col == d.A) zval = z;
+                }
+                zmax = group16_max(zmax);
+                za[rt][i] += group16_sum(zsel);
+                zv[rt][i] += group16_sum(zval);
+                if (zmax == NEG) continue;
+                float s = 0.f, t = 0.f;
+#pragma unroll
+                for (int ct = 0; ct < 8; ++ct) {
+                    const int col = c * 128 + ct * 16 + (l & 15);
+                    const float z = acc3[rt][ct][i] + bcol[ct];
+                    const bool ok = col < d.A && ((smask[rloc * W + (col >> 5)] >> (col & 31)) & 1u);
+                    if (ok) {
+                        const float e = __expf(z - zmax);
+                        s += e;
+                        t += e * (z - zmax);
+                    }
+                }
+                s = group16_sum(s);
+                t = group16_sum(t);
+                const float m = sm[rt][i], mn = fmaxf(m, zmax);
+                const float fo = m == NEG ? 0.f : __expf(m - mn), fc = __expf(zmax - mn);
+                sT[rt][i] = (m == NEG ? 0.f : fo * (sT[rt][i] + (m - mn) * sS[rt][i])) + fc * (t + (zmax - mn) * s);
+                sS[rt][i] = sS[rt][i] * fo + s * fc;
+                sm[rt][i] = mn;
+            }
+    }
+
+    // ---- per-row loss terms and gradient coefficients
+    float lse[RT][4], ent[RT][4], cpg[RT][4], dzv[RT][4];
+    float part_pg = 0.f, part_vf = 0.f, part_ent = 0.f, part_clip = 0.f;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rloc = arow0 + rt * 16 + 4 * (l >> 4) + i;
+            const bool valid = rinfo[5 * TILE + rloc] != 0.f && sS[rt][i] > 0.f;
+            const float lS = valid ? __logf(sS[rt][i]) : 0.f;
+            lse[rt][i] = sm[rt][i] + lS;
+            const float h = valid ? lS - sT[rt][i] / sS[rt][i] : 0.f;
+            ent[rt][i] = h;
+            const float lpn = za[rt][i] - lse[rt][i];
+            const float ratio = __expf(lpn - rinfo[1 * TILE + rloc]);
+            const float ah = rinfo[3 * TILE + rloc];
+            const float s1 = ratio * ah;
+            const float rc = fminf(fmaxf(ratio, 1.f - hp.clip), 1.f + hp.clip);
+            const float s2 = rc * ah;
+            const bool active = !(s1 > s2);
+            cpg[rt][i] = valid ? (active ? -ah * ratio : 0.f) * inv_n : 0.f;
+            const float V = zv[rt][i], vo = rinfo[2 * TILE + rloc], R = rinfo[4 * TILE + rloc];
+            const float dvv = V - vo;
+            const float vc = vo + fminf(fmaxf(dvv, -hp.vclip), hp.vclip);
+            const float l1 = (V - R) * (V - R), l2 = (vc - R) * (vc - R);
+            const float gv = l1 >= l2 ? (V - R) : ((dvv >= -hp.vclip && dvv <= hp.vclip) ? (vc - R) : 0.f);
+            dzv[rt][i] = valid ? hp.vf_coef * gv * inv_n : 0.f;
+            if (valid && (l & 15) == 0) {
+                part_pg += -fminf(s1, s2);
+                part_vf += 0.5f * fmaxf(l1, l2);
+                part_ent += h;
+                part_clip += fabsf(ratio - 1.f) > hp.clip ? 1.f : 0.f;
+            }
+        }
+    {
+        part_pg = wave_sum(part_pg);
+        part_vf = wave_sum(part_vf);
+        part_ent = wave_sum(part_ent);
+        part_clip = wave_sum(part_clip);
+        if (l == 0) {
+            lred[wave * 4 + 0] = part_pg;
+            lred[wave * 4 + 1] = part_vf;
+            lred[wave * 4 + 2] = part_ent;
+            lred[wave * 4 + 3] = part_clip;
+        }
+    }
+
+    // ---- pass 2: dY = dL/d[logits | value] per chunk, dh2 += dY W3^T
+    const float cent = hp.ent_coef * inv_n;
+    f32x4 dh[RT][CT];
+    for (int c = 0; c < d.NC; ++c) {
+        if (d.NC > 1)
+            dense_layer<RT, 128>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32,
+                                 wbuf);
+        float bcol[8];
+#pragma unroll
+        for (int ct = 0; ct < 8; ++ct) {
+            const int col = c * 128 + ct * 16 + (l & 15);
+            bcol[ct] = col < d.A1 ? params[d.ob3 + col] : 0.f;
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int rloc0 = arow0 + rt * 16 + 4 * (l >> 4);
+#pragma unroll
+            for (int ct = 0; ct < 8; ++ct) {
+                const int col = c * 128 + ct * 16 + (l & 15);
+                float g[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int rloc = rloc0 + i;
+                    const float z = acc3[rt][ct][i] + bcol[ct];
+                    const bool ok = col < d.A && ((smask[rloc * W + (col >> 5)] >> (col & 31)) & 1u);
+                    float gg = 0.f;
+                    if (ok) {
+                        const float lp = z - lse[rt][i];
+                        const float p = __expf(lp);
+                        const int a_taken = __float_as_int(rinfo[rloc]);
+                        gg = cpg[rt][i] * ((col == a_taken ? 1.f : 0.f) - p) + cent * p * (lp + ent[rt][i]);
+                    } else if (col == d.A) {
+                        gg = dzv[rt][i];
+                    }
+                    g[i] = gg;
+                    ybuf[rloc * YS + ct * 16 + (l & 15)] = f32_to_bf16(gg);
+                }
+                store_mblock4(TdY, d.A1p, tile_row0 + rloc0, col, g);
+            }
+        }
+        dense_layer<RT, H>(dh, ybuf, YS, arow0, 128, work + d.oW3b + (int64_t)c * 4 * H * 32, (int64_t)H * 32, wbuf,
+                           c == 0);
+    }
+
+    // ---- dh2 = (dY W3^T) * [h2 > 0] -> LDS (A operand of the next product) and m-blocks
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int col = ct * 16 + (l & 15);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int rloc = arow0 + rt * 16 + 4 * (l >> 4);
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[i] = ((m2[rt][ct >> 3] >> ((ct & 7) * 4 + i)) & 1u) ? dh[rt][ct][i] : 0.f;
+                hbuf[(rloc + i) * HS + col] = f32_to_bf16(v[i]);
+            }
+            store_mblock4(Tdh2, H, tile_row0 + rloc, col, v);
+        }
+    }
+    // ---- dh1 = (dh2 W2^T) * [h1 > 0] -> m-blocks
+    dense_layer<RT, H>(dh, hbuf, HS, arow0, H, work + d.oW2b, (int64_t)H * 32, wbuf);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int col = ct * 16 + (l & 15);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int rloc = arow0 + rt * 16 + 4 * (l >> 4);
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = ((m1[rt][ct >> 3] >> ((ct & 7) * 4 + i)) & 1u) ? dh[rt][ct][i] : 0.f;
+            store_mblock4(Tdh1, H, tile_row0 + rloc, col, v);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        float s = 0.f;
+        for (int w = 0; w < 4; ++w) s += lred[w * 4 + threadIdx.x];
+        loss_parts[(int64_t)blockIdx.x * 4 + threadIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradients: C[j][n] = sum_m X[m][j] Y[m][n] over m-blocks
+// ---------------------------------------------------------------------------
+template <int WJ, int WN, int TJ, int TN>
+__global__ void __launch_bounds__(WJ* WN * 64)
+dw_kernel(const uint16_t* __restrict__ Tx, int J, const uint16_t* __restrict__ Ty, int N, int64_t nmb, int G,
+          float* __restrict__ part, float* __restrict__ colsum)
+{
+    constexpr int CJ = WJ * TJ * 16, CN = WN * TN * 16, NTH = WJ * WN * 64;
+    __shared__ __align__(16) uint16_t xs[CJ * WSTRIDE];
+    __shared__ __align__(16) uint16_t ys[CN * WSTRIDE];
+    const int njt = J / CJ;
+    const int jt = blockIdx.x % njt, nt = blockIdx.x / njt;
+    const int j0 = jt * CJ, n0 = nt * CN;
+    const int g = blockIdx.y;
+    const int64_t mb0 = nmb * g / G, mb1 = nmb * (g + 1) / G;
+    const int wave = threadIdx.x >> 6, l = lane_id();
+    const int wj = wave % WJ, wn = wave / WJ;
+    f32x4 acc[TJ][TN];
+#pragma unroll
+    for (int a = 0; a < TJ; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float cs = 0.f;
+    constexpr int PX = CJ * 4, PY = CN * 4;  // 16-byte pieces per tile
+    uint4 rx[(PX + NTH - 1) / NTH], ry[(PY + NTH - 1) / NTH];
+    auto load = [&](int64_t mb) {
+#pragma unroll
+        for (int k = 0; k < (PX + NTH - 1) / NTH; ++k) {
+            const int p = threadIdx.x + k * NTH;
+            if (p < PX) rx[k] = *(const uint4*)(Tx + (mb * J + j0 + (p >> 2)) * 32 + (p & 3) * 8);
+        }
+#pragma unroll
+        for (int k = 0; k < (PY + NTH - 1) / NTH; ++k) {
+            const int p = threadIdx.x + k * NTH;
+            if (p < PY) ry[k] = *(const uint4*)(Ty + (mb * N + n0 + (p >> 2)) * 32 + (p & 3) * 8);
+        }
+    };
+    if (mb0 < mb1) load(mb0);
+    for (int64_t mb = mb0; mb < mb1; ++mb) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < (PX + NTH - 1) / NTH; ++k) {
+            const int p = threadIdx.x + k * NTH;
+            if (p < PX) *(uint4*)(xs + (p >> 2) * WSTRIDE + (p & 3) * 8) = rx[k];
+        }
+#pragma unroll
+        for (int k = 0; k < (PY + NTH - 1) / NTH; ++k) {
+            const int p = threadIdx.x + k * NTH;
+            if (p < PY) *(uint4*)(ys + (p >> 2) * WSTRIDE + (p & 3) * 8) = ry[k];
+        }
+        __syncthreads();
+        if (mb + 1 < mb1) load(mb + 1);
+        bf16x8 af[TJ];
+#pragma unroll
+        for (int a = 0; a < TJ; ++a) af[a] = lds_frag(xs + (wj * TJ * 16 + a * 16 + (l & 15)) * WSTRIDE + 8 * (l >> 4));
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            const bf16x8 bf = lds_frag(ys + (wn * TN * 16 + b * 16 + (l & 15)) * WSTRIDE + 8 * (l >> 4));
+#pragma unroll
+            for (int a = 0; a < TJ; ++a) acc[a][b] = mfma16(af[a], bf, acc[a][b]);
+        }
+        if (jt == 0 && (int)threadIdx.x < CN) {
+            const uint16_t* yrow = ys + threadIdx.x * WSTRIDE;
+#pragma unroll
+            for (int m = 0; m < 32; ++m) cs += bf16_to_f32(yrow[m]);
+        }
+    }
+    float* out = part + (int64_t)g * J * N;
+#pragma unroll
+    for (int a = 0; a < TJ; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            const int n = n0 + wn * TN * 16 + b * 16 + (l & 15);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = j0 + wj * TJ * 16 + a * 16 + 4 * (l >> 4) + i;
+                out[(int64_t)j * N + n] = acc[a][b][i];
+            }
+        }
+    if (jt == 0 && (int)threadIdx.x < CN) colsum[(int64_t)g * N + n0 + threadIdx.x] = cs;
+}
+
+// grad[woff + j ldw + n] = sum_g part[g][j][n] (j < Jv, n < Nv); bias from the column sums
+__global__ void dw_reduce_kernel(const float* __restrict__ part, const float* __restrict__ colsum, int J, int N,
+                                 int G, int Jv, int Nv, float* __restrict__ grad, int64_t woff, int ldw, int64_t boff)
+{
+    const int64_t total = (int64_t)J * N;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total + N;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        if (idx < total) {
+            const int j = (int)(idx / N), n = (int)(idx % N);
+            if (j >= Jv || n >= Nv) continue;
+            float s = 0.f;
+            for (int g = 0; g < G; ++g) s += part[(int64_t)g * total + idx];
+            grad[woff + (int64_t)j * ldw + n] = s;
+        } else {
+            const int n = (int)(idx - total);
+            if (n >= Nv) continue;
+            float s = 0.f;
+            for (int g = 0; g < G; ++g) s += colsum[(int64_t)g * N + n];
+            grad[boff + n] = s;
+        }
+    }
+}
+
+__global__ void loss_final_kernel(const float* __restrict__ parts, int nparts, int64_t rows, float* __restrict__ out)
+{
+    if (threadIdx.x >= 4) return;
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k) s += parts[4 * k + threadIdx.x];
+    out[threadIdx.x] = (float)(s / (double)rows);
+}
+
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct PpoWorkspace {
+    int64_t nmb, ntiles, G;
+    size_t o_obs, o_h1, o_h2, o_dy, o_dh2, o_dh1, o_p1, o_p2, o_p3, o_c1, o_c2, o_c3, o_adv, o_stats, o_loss, bytes;
+};
+
+static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int ppo_tile_rows(int H) { return H <= 256 ? 128 : 64; }
+
+static int ppo_workspace(const MlpDims& d, int64_t rows, PpoWorkspace* w)
+{
+    const int TILE = ppo_tile_rows(d.H);
+    w->ntiles = (rows + TILE - 1) / TILE;
+    w->nmb = w->ntiles * TILE / 32;
+    w->G = w->nmb < 256 ? w->nmb : 256;
+    if (w->G < 1) w->G = 1;
+    size_t o = 0;
+    const size_t mbrow = (size_t)w->nmb * 32 * 2;  // bytes per column of an m-block buffer
+    w->o_obs = o; o = al256(o + mbrow * d.K1p);
+    w->o_h1 = o; o = al256(o + mbrow * d.H);
+    w->o_h2 = o; o = al256(o + mbrow * d.H);
+    w->o_dy = o; o = al256(o + mbrow * d.A1p);
+    w->o_dh2 = o; o = al256(o + mbrow * d.H);
+    w->o_dh1 = o; o = al256(o + mbrow * d.H);
+    w->o_p1 = o; o = al256(o + (size_t)w->G * d.K1p * d.H * 4);
+    w->o_p2 = o; o = al256(o + (size_t)w->G * d.H * d.H * 4);
+    w->o_p3 = o; o = al256(o + (size_t)w->G * d.H * d.A1p * 4);
+    w->o_c1 = o; o = al256(o + (size_t)w->G * d.H * 4);
+    w->o_c2 = o; o = al256(o + (size_t)w->G * d.H * 4);
+    w->o_c3 = o; o = al256(o + (size_t)w->G * d.A1p * 4);
+    w->o_adv = o; o = al256(o + 2 * 1024 * 8);
+    w->o_stats = o; o = al256(o + 16);
+    w->o_loss = o; o = al256(o + (size_t)w->ntiles * 16);
+    w->bytes = o;
+    return EJ_OK;
+}
+
+static int launch_dw(const uint16_t* Tx, int J, const uint16_t* Ty, int N, int64_t nmb, int G, float* part,
+                     float* colsum, hipStream_t st)
+{
+    auto grid = [&](int CJ, int CN) { return dim3((unsigned)((J / CJ) * (N / CN)), (unsigned)G); };
+    if (J % 256 == 0 && N % 256 == 0) {
+        dw_kernel<4, 2, 4, 8><<<grid(256, 256), 512, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
+    } else if (J % 256 == 0 && N % 128 == 0) {
+        dw_kernel<4, 2, 4, 4><<<grid(256, 128), 512, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
+    } else if (J % 128 == 0 && N % 128 == 0) {
+        dw_kernel<2, 2, 4, 4><<<grid(128, 128), 256, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
+    } else if (J % 64 == 0 && N % 256 == 0) {
+        dw_kernel<1, 8, 4, 2><<<grid(64, 256), 512, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
+    } else if (J % 64 == 0 && N % 128 == 0) {
+        dw_kernel<1, 4, 4, 2><<<grid(64, 128), 256, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
+    } else if (J % 64 == 0 && N % 64 == 0) {
+        dw_kernel<1, 4, 4, 1><<<grid(64, 64), 256, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
+    } else {
+        return EJ_EUNSUPPORTED;
+    }
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+template <int H>
+static int launch_rows(const MlpDims& d, const float* params, const uint16_t* work, const PpoBatchDev& B,
+                       const PpoHp& hp, const float* stats, int W, uint16_t* const* T, float* loss_parts, int64_t ntiles,
+                       hipStream_t st)
+{
+    const size_t lds = ppo_rows_lds_bytes<H>(W);
+    ppo_rows_kernel<H><<<(unsigned)ntiles, 256, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[1], T[2], T[3],
+                                                           T[4], T[5], loss_parts);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+}  // namespace econ
+
+using namespace econ;
+
+extern "C" {
+
+int ej_gae(const float* d_rew, const float* d_val, const uint8_t* d_done, const float* d_last_val, int32_t T,
+           int64_t M, float gamma, float lam, float* d_adv, float* d_ret, void* stream)
+{
+    if (!d_rew || !d_val || !d_done || !d_last_val || !d_adv || !d_ret || T <= 0 || M < 0) return EJ_EINVAL;
+    if (M == 0) return EJ_OK;
+    int64_t blocks = (M + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    gae_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(d_rew, d_val, d_done, d_last_val, T, M, gamma, lam,
+                                                                 d_adv, d_ret);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+int ej_ppo_workspace_size(const ej_mlp_desc* m, int64_t rows, int64_t* bytes)
+{
+    if (!m || !bytes || rows <= 0) return EJ_EINVAL;
+    MlpDims d;
+    int rc = mlp_dims(m->D, m->D_stride, m->H, m->A, &d);
+    if (rc != EJ_OK) return rc;
+    PpoWorkspace w;
+    ppo_workspace(d, rows, &w);
+    *bytes = (int64_t)w.bytes;
+    return EJ_OK;
+}
+
+int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const ej_ppo_batch* b,
+                    const ej_ppo_hparams* hp, void* d_workspace, int64_t workspace_bytes, float* d_grads,
+                    float* d_loss, void* stream)
+{
+    if (!m || !d_params || !d_work || !b || !hp || !d_workspace || !d_grads || !d_loss) return EJ_EINVAL;
+    if (!b->obs || !b->mask || !b->act || !b->logp_old || !b->val_old || !b->adv || !b->ret) return EJ_EINVAL;
+    if (b->M_total <= 0 || b->M_total > INT32_MAX || b->rows <= 0 || b->perm_a <= 0 || b->perm_c < 0 ||
+        b->row_begin < 0 || b->row_begin + b->rows > INT32_MAX)
+        return EJ_EINVAL;
+    MlpDims d;
+    int rc = mlp_dims(m->D, m->D_stride, m->H, m->A, &d);
+    if (rc != EJ_OK) return rc;
+    PpoWorkspace w;
+    ppo_workspace(d, b->rows, &w);
+    if (workspace_bytes < (int64_t)w.bytes) return EJ_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char* ws = (unsigned char*)d_workspace;
+    const int64_t a = b->M_total == 1 ? 1 : b->perm_a % b->M_total;
+    if (a == 0) return EJ_EINVAL;
+    PpoBatchDev B{b->obs, b->mask, b->act, b->logp_old, b->val_old, b->adv, b->ret, b->M_total, a,
+                  b->perm_c % b->M_total, b->row_begin, b->rows};
+    PpoHp h{hp->clip, hp->vclip, hp->vf_coef, hp->ent_coef};
+    const int W = (m->A + 31) / 32;
+    double* advp = (double*)(ws + w.o_adv);
+    float* stats = (float*)(ws + w.o_stats);
+    int nb = (int)((b->rows + 255) / 256);
+    if (nb > 1024) nb = 1024;
+    adv_stats_partial<<<nb, 256, 0, st>>>(B, advp);
+    EJ_LAUNCH_CHECK();
+    adv_stats_final<<<1, 64, 0, st>>>(advp, nb, b->rows, stats);
+    EJ_LAUNCH_CHECK();
+    uint16_t* T[6] = {(uint16_t*)(ws + w.o_obs), (uint16_t*)(ws + w.o_h1), (uint16_t*)(ws + w.o_h2),
+                      (uint16_t*)(ws + w.o_dy), (uint16_t*)(ws + w.o_dh2), (uint16_t*)(ws + w.o_dh1)};
+    float* lparts = (float*)(ws + w.o_loss);
+    switch (m->H) {
+    case 64: rc = launch_rows<64>(d, d_params, d_work, B, h, stats, W, T, lparts, w.ntiles, st); break;
+    case 128: rc = launch_rows<128>(d, d_params, d_work, B, h, stats, W, T, lparts, w.ntiles, st); break;
+    case 256: rc = launch_rows<256>(d, d_params, d_work, B, h, stats, W, T, lparts, w.ntiles, st); break;
+    default: rc = launch_rows<512>(d, d_params, d_work, B, h, stats, W, T, lparts, w.ntiles, st); break;
+    }
+    if (rc != EJ_OK) return rc;
+    float *p1 = (float*)(ws + w.o_p1), *p2 = (float*)(ws + w.o_p2), *p3 = (float*)(ws + w.o_p3);
+    float *c1 = (float*)(ws + w.o_c1), *c2 = (float*)(ws + w.o_c2), *c3 = (float*)(ws + w.o_c3);
+    const int G = (int)w.G;
+    if ((rc = launch_dw(T[0], d.K1p, T[5], d.H, w.nmb, G, p1, c1, st)) != EJ_OK) return rc;
+    if ((rc = launch_dw(T[1], d.H, T[4], d.H, w.nmb, G, p2, c2, st)) != EJ_OK) return rc;
+    if ((rc = launch_dw(T[2], d.H, T[3], d.A1p, w.nmb, G, p3, c3, st)) != EJ_OK) return rc;
+    auto red_blocks = [](int64_t n) { int64_t bl = (n + 255) / 256; return (unsigned)(bl > 2048 ? 2048 : bl); };
+    dw_reduce_kernel<<<red_blocks((int64_t)d.K1p * d.H + d.H), 256, 0, st>>>(p1, c1, d.K1p, d.H, G, d.D, d.H, d_grads,
+                                                                            d.oW1, d.H, d.ob1);
+    EJ_LAUNCH_CHECK();
+    dw_reduce_kernel<<<red_blocks((int64_t)d.H * d.H + d.H), 256, 0, st>>>(p2, c2, d.H, d.H, G, d.H, d.H, d_grads,
+                                                                          d.oW2, d.H, d.ob2);
+    EJ_LAUNCH_CHECK();
+    dw_reduce_kernel<<<red_blocks((int64_t)d.H * d.A1p + d.A1p), 256, 0, st>>>(p3, c3, d.H, d.A1p, G, d.H, d.A1,
+                                                                              d_grads, d.oW3, d.A1, d.ob3);
+    EJ_LAUNCH_CHECK();
+    loss_final_kernel<<<1, 64, 0, st>>>(lparts, (int)w.ntiles, b->rows, d_loss);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+int ej_adam(float* d_params, const float* d_grads, float* d_m, float* d_v, int64_t n, int32_t step, float lr,
+            float beta1, float beta2, float eps, void* stream)
+{
+    if (!d_params || !d_grads || !d_m || !d_v || n <= 0 || step <= 0) return EJ_EINVAL;
+    const float c1 = (float)(1.0 - pow((double)beta1, (double)step));
+    const float c2 = (float)(1.0 - pow((double)beta2, (double)step));
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    adam_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(d_params, d_grads, d_m, d_v, n, lr, beta1, beta2,
+                                                                  eps, c1, c2);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+}  // extern "C"
