@@ -211,11 +211,17 @@ int ej_mlp_sync_weights(const ej_mlp_desc* m, const float* d_params, uint16_t* d
  * Sampling is exact for the masked softmax: the logits are taken in chunks
  * of 128 actions, a chunk is chosen by weighted reservoir with one uniform
  * and the action inside it by inverse CDF with a second one; the uniforms of
- * row r, chunk c come from the counter-based generator keyed (seed, r, ctr,
- * c / 2).  Logits are never written to memory unless d_logits is given. */
+ * row r, chunk c come from the counter-based generator keyed (seed, r, ctr',
+ * c / 2) with ctr' = ctr + *d_ctr_base (d_ctr_base: nullable device
+ * uint64_t, read when the kernel runs, so that a captured graph replayed
+ * many times draws fresh uniforms after each ej_counter_add).  Logits are
+ * never written to memory unless d_logits is given. */
 int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const uint16_t* d_obs,
-                      const uint32_t* d_mask, int64_t M, uint64_t seed, uint64_t ctr, int32_t* d_act, float* d_logp,
-                      float* d_val, float* d_ent, float* d_logits, void* stream);
+                      const uint32_t* d_mask, int64_t M, uint64_t seed, uint64_t ctr, const uint64_t* d_ctr_base,
+                      int32_t* d_act, float* d_logp, float* d_val, float* d_ent, float* d_logits, void* stream);
+
+/* *d_counter += inc on the stream (one tiny kernel; usable inside a graph). */
+int ej_counter_add(uint64_t* d_counter, uint64_t inc, void* stream);
 
 /* ------------------------------------------------------------------------
  * PPO learner (Table 2: clipped surrogate, clipped value loss, entropy

@@ -168,16 +168,31 @@ def gae(rew, val, done, last_val, gamma: float, lam: float):
     return adv, adv + val
 
 
-def ppo_loss_torch(params: dict, obs, allowed, act, logp_old, val_old, adv, ret, hp: dict):
+def _round_bf16_straight_through(h):
+    """Values rounded to bf16 (via float32, ties to even); gradient passed
+    through unchanged."""
+    r = h.detach().to(torch.float32).to(torch.bfloat16).to(torch.float64)
+    return h + (r - h.detach())
+
+
+def ppo_loss_torch(params: dict, obs, allowed, act, logp_old, val_old, adv, ret, hp: dict,
+                   bf16_hidden: bool = False):
     """PPO minibatch loss in float64 torch ops; returns (loss, terms).
 
     Advantages are normalised over the minibatch (population standard
     deviation, + 1e-8).  loss = mean(-min(rho A, clip(rho) A))
                               + c_v mean(1/2 max((V-R)^2, (Vclip-R)^2))
-                              - c_e mean(H)."""
+                              - c_e mean(H).
+    bf16_hidden rounds the hidden activations to bf16 in the forward pass
+    (straight-through in the backward pass): the clip decisions are then
+    taken in the precision of a bf16 kernel."""
     x = torch.as_tensor(np.asarray(obs, np.float64))
     h1 = torch.relu(x @ params["W1"] + params["b1"])
+    if bf16_hidden:
+        h1 = _round_bf16_straight_through(h1)
     h2 = torch.relu(h1 @ params["W2"] + params["b2"])
+    if bf16_hidden:
+        h2 = _round_bf16_straight_through(h2)
     out = h2 @ params["W3"] + params["b3"]
     logits, v = out[:, :-1], out[:, -1]
     allowed_t = torch.as_tensor(allowed)
@@ -201,13 +216,14 @@ def ppo_loss_torch(params: dict, obs, allowed, act, logp_old, val_old, adv, ret,
     return loss, dict(pg=pg, vf=vl, ent=en)
 
 
-def ppo_grads(w_f32: dict, obs, mask_words, act, logp_old, val_old, adv, ret, hp: dict):
+def ppo_grads(w_f32: dict, obs, mask_words, act, logp_old, val_old, adv, ret, hp: dict,
+              bf16_hidden: bool = False):
     """Float64 loss and autograd gradients with respect to the bf16 weights."""
     w = bf16_weights(w_f32)
     A = w["W3"].shape[1] - 1
     params = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in w.items()}
     loss, terms = ppo_loss_torch(params, obs, unpack_mask(mask_words, A), act, logp_old, val_old, adv,
-                                 ret, hp)
+                                 ret, hp, bf16_hidden=bf16_hidden)
     loss.backward()
     return (float(loss.detach()), {k: float(v.detach()) for k, v in terms.items()},
             {k: params[k].grad.numpy().copy() for k in params})

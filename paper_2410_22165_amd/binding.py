@@ -103,7 +103,8 @@ def _declare_learner(L):
     table = {
         "ej_mlp_layout": [C.POINTER(EjMlpDesc), C.POINTER(EjMlpLayout)],
         "ej_mlp_sync_weights": [C.POINTER(EjMlpDesc), vp, vp, vp],
-        "ej_policy_forward": [C.POINTER(EjMlpDesc), vp, vp, vp, vp, i64, u64, u64, vp, vp, vp, vp, vp, vp],
+        "ej_policy_forward": [C.POINTER(EjMlpDesc), vp, vp, vp, vp, i64, u64, u64, vp, vp, vp, vp, vp, vp, vp],
+        "ej_counter_add": [vp, u64, vp],
         "ej_gae": [vp, vp, vp, vp, i32, i64, f32, f32, vp, vp, vp],
         "ej_ppo_workspace_size": [C.POINTER(EjMlpDesc), i64, C.POINTER(i64)],
         "ej_ppo_backward": [C.POINTER(EjMlpDesc), vp, vp, C.POINTER(EjPpoBatch), C.POINTER(EjPpoHparams), vp, i64,
@@ -298,9 +299,10 @@ class Mlp:
         check(lib().ej_mlp_sync_weights(C.byref(self.desc), ptr(self.params), ptr(self.work), stream_ptr(stream)),
               "ej_mlp_sync_weights")
 
-    def forward(self, obs, mask, M: int, seed: int, ctr: int, act, logp, val, ent, logits=None, stream=None):
+    def forward(self, obs, mask, M: int, seed: int, ctr: int, act, logp, val, ent, logits=None, stream=None,
+                ctr_base=None):
         check(lib().ej_policy_forward(C.byref(self.desc), ptr(self.params), ptr(self.work), ptr(obs), ptr(mask), M,
-                                      seed, ctr, ptr(act), ptr(logp), ptr(val), ptr(ent), ptr(logits),
+                                      seed, ctr, ptr(ctr_base), ptr(act), ptr(logp), ptr(val), ptr(ent), ptr(logits),
                                       stream_ptr(stream)), "ej_policy_forward")
 
 
@@ -329,3 +331,7 @@ def ppo_backward(mlp: "Mlp", storage: dict, M_total: int, perm_a: int, perm_c: i
     check(lib().ej_ppo_backward(C.byref(mlp.desc), ptr(mlp.params), ptr(mlp.work), C.byref(b), C.byref(h),
                                 ptr(workspace), workspace.numel(), ptr(grads), ptr(loss), stream_ptr(stream)),
           "ej_ppo_backward")
+
+
+def counter_add(counter, inc: int, stream=None):
+    check(lib().ej_counter_add(ptr(counter), inc, stream_ptr(stream)), "ej_counter_add")

@@ -138,4 +138,118 @@ __device__ inline T wave_inclusive_scan(T v)
     return v;
 }
 
+// ---------------------------------------------------------------------------
+// DPP (data-parallel primitives inside a 16-lane row): no LDS round trip.
+// Row = lanes 16r .. 16r + 15 of the wave.
+// ---------------------------------------------------------------------------
+enum : int {
+    DPP_XOR1 = 0xB1,        // quad_perm(1, 0, 3, 2)
+    DPP_XOR2 = 0x4E,        // quad_perm(2, 3, 0, 1)
+    DPP_ROW_SHR1 = 0x111,
+    DPP_ROW_SHR2 = 0x112,
+    DPP_ROW_SHR4 = 0x114,
+    DPP_ROW_SHR8 = 0x118,
+    DPP_ROW_MIRROR = 0x140,
+    DPP_ROW_HALF_MIRROR = 0x141,
+};
+
+template <int CTRL>
+__device__ inline float dpp_f(float v, float fill = 0.f)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, fill),
+                                                                 __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline int dpp_i(int v, int fill = 0)
+{
+    return __builtin_amdgcn_update_dpp(fill, v, CTRL, 0xF, 0xF, false);
+}
+
+// all-reduce over the 16 lanes of each row
+__device__ inline float row16_sum(float v)
+{
+    v += dpp_f<DPP_XOR1>(v);
+    v += dpp_f<DPP_XOR2>(v);
+    v += dpp_f<DPP_ROW_HALF_MIRROR>(v);
+    v += dpp_f<DPP_ROW_MIRROR>(v);
+    return v;
+}
+__device__ inline float row16_max(float v)
+{
+    v = fmaxf(v, dpp_f<DPP_XOR1>(v));
+    v = fmaxf(v, dpp_f<DPP_XOR2>(v));
+    v = fmaxf(v, dpp_f<DPP_ROW_HALF_MIRROR>(v));
+    v = fmaxf(v, dpp_f<DPP_ROW_MIRROR>(v));
+    return v;
+}
+__device__ inline int row16_min_i(int v)
+{
+    v = min(v, dpp_i<DPP_XOR1>(v));
+    v = min(v, dpp_i<DPP_XOR2>(v));
+    v = min(v, dpp_i<DPP_ROW_HALF_MIRROR>(v));
+    v = min(v, dpp_i<DPP_ROW_MIRROR>(v));
+    return v;
+}
+__device__ inline int row16_max_i(int v)
+{
+    v = max(v, dpp_i<DPP_XOR1>(v));
+    v = max(v, dpp_i<DPP_XOR2>(v));
+    v = max(v, dpp_i<DPP_ROW_HALF_MIRROR>(v));
+    v = max(v, dpp_i<DPP_ROW_MIRROR>(v));
+    return v;
+}
+__device__ inline int row16_sum_i(int v)
+{
+    v += dpp_i<DPP_XOR1>(v);
+    v += dpp_i<DPP_XOR2>(v);
+    v += dpp_i<DPP_ROW_HALF_MIRROR>(v);
+    v += dpp_i<DPP_ROW_MIRROR>(v);
+    return v;
+}
+// inclusive prefix sum inside each 16-lane row
+__device__ inline float row16_scan(float v)
+{
+    v += dpp_f<DPP_ROW_SHR1>(v);
+    v += dpp_f<DPP_ROW_SHR2>(v);
+    v += dpp_f<DPP_ROW_SHR4>(v);
+    v += dpp_f<DPP_ROW_SHR8>(v);
+    return v;
+}
+__device__ inline int row16_scan_i(int v)
+{
+    v += dpp_i<DPP_ROW_SHR1>(v);
+    v += dpp_i<DPP_ROW_SHR2>(v);
+    v += dpp_i<DPP_ROW_SHR4>(v);
+    v += dpp_i<DPP_ROW_SHR8>(v);
+    return v;
+}
+
+// wave-wide (64-lane) versions: rows first, then the four row results
+__device__ inline int wave_sum_i(int v)
+{
+    v = row16_sum_i(v);
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
+           __builtin_amdgcn_readlane(v, 48);
+}
+__device__ inline int wave_max_i(int v)
+{
+    v = row16_max_i(v);
+    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+__device__ inline int wave_min_i(int v)
+{
+    v = row16_min_i(v);
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+__device__ inline int wave_scan_i(int v)
+{
+    v = row16_scan_i(v);
+    const int t0 = __builtin_amdgcn_readlane(v, 15), t1 = __builtin_amdgcn_readlane(v, 31),
+              t2 = __builtin_amdgcn_readlane(v, 47);
+    const int row = lane_id() >> 4;
+    return v + (row >= 1 ? t0 : 0) + (row >= 2 ? t1 : 0) + (row >= 3 ? t2 : 0);
+}
+
 }  // namespace econ

@@ -55,6 +55,7 @@ struct EnvState {
     const int32_t* env_off;  // [E]   first state slot of the economy
     const int32_t* env_row;  // [E+1] first row of the economy
     int64_t* invalid;        // [E][2] rejected population actions / government levels
+    double* ug;              // [E]   social welfare of the current state (NaN: not known)
 };
 
 // state field indices
@@ -310,9 +311,9 @@ __device__ inline void seg_exclusive_scan(const int32_t* src, int32_t* dst, int 
         for (int c = 0; c < len; c += 64) {
             int j = c + lane;
             int32_t v = j < len ? src[s * len + j] : 0;
-            int32_t inc = wave_inclusive_scan(v);
+            int32_t inc = wave_scan_i(v);
             if (j < len) dst[s * len + j] = carry + inc - v;
-            carry += __shfl(inc, 63, 64);
+            carry += __builtin_amdgcn_readlane(inc, 63);
         }
     }
 }
@@ -412,16 +413,32 @@ __device__ inline int bucket_pos(const EnvParams& P, int side, int p, int age)
     return side == 0 ? (P.P - 1 - p) * P.X + (P.X - 1 - age) : p * P.X + (P.X - 1 - age);
 }
 
-// Gini numerator and coin sum of the economy from coin values in sortbuf
-// (n live entries, padded with INT64_MAX to S2), then social welfare.
+// Gini numerator sum_k (2k - n + 1) x_(k) and coin sum of the economy from
+// the coin values in sortbuf (n live entries, padded with INT64_MAX to S2),
+// then the social welfare.  Small economies take each value's rank by
+// counting (ties ordered by index: any order of equal values gives the same
+// sum); larger ones sort in LDS.
 __device__ inline double social_welfare_block(const EnvParams& P, const Lds& L, int n, int S2)
 {
-    bitonic_sort_i64(L.sortbuf, S2);
     int64_t num = 0, sum = 0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        int64_t x = L.sortbuf[k];
-        num += (int64_t)(2 * k - n + 1) * x;
-        sum += x;
+    if (n <= 256) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int64_t x = L.sortbuf[i];
+            int rank = 0;
+            for (int j = 0; j < n; ++j) {
+                const int64_t y = L.sortbuf[j];
+                rank += (y < x) || (y == x && j < i);
+            }
+            num += (int64_t)(2 * rank - n + 1) * x;
+            sum += x;
+        }
+    } else {
+        bitonic_sort_i64(L.sortbuf, S2);
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            int64_t x = L.sortbuf[k];
+            num += (int64_t)(2 * k - n + 1) * x;
+            sum += x;
+        }
     }
     num = block_sum_i64(num, L.red);
     sum = block_sum_i64(sum, L.red + 16);
@@ -456,8 +473,8 @@ __device__ inline void market_stats(const EnvParams& P, const Lds& L, const int3
                 count += alive;
             }
         }
-        best = wave_min(best);
-        count = wave_sum(count);
+        best = wave_min_i(best);
+        count = wave_sum_i(count);
         if (lane == 0) {
             int price = 0;
             if (best != INT_MAX) {
@@ -626,7 +643,8 @@ env_step_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__
         }
     }
     __syncthreads();
-    const double ug0 = social_welfare_block(P, L, n, S2);
+    const double cached_ug = S.ug[e];
+    const double ug0 = cached_ug == cached_ug ? cached_ug : social_welfare_block(P, L, n, S2);
 
     // apply every agent's action; new orders go to slot t mod X
     const int slot_new = t % X;
@@ -743,7 +761,7 @@ env_step_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__
                     best = m > best ? m : best;
                 }
             }
-            best = wave_max(best);
+            best = wave_max_i(best);
             if (lane == 0) L.kr[r] = best;
         }
     }
@@ -904,6 +922,7 @@ env_step_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__
     if (tid == 0) {
         S.env_t[e] = t_next;
         S.env_ep[e] = ep_next;
+        S.ug[e] = done ? __builtin_nan("") : ug1;  // the next step starts from this state
     }
     if (tid < K) S.env_rates[e * K + tid] = L.rates[tid];
 
@@ -915,12 +934,30 @@ env_step_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__
         market_stats(P, L, L.kr, X - 1);
     }
     __syncthreads();
+    // Rows go through LDS (the bucket arrays are free now) so that the whole
+    // economy's rows leave in coalesced 16-byte stores; direct stores when
+    // they do not fit.
+    const size_t obs_bytes = obs ? (size_t)n * P.Ds * 2 : 0, mask_bytes = mask ? (size_t)n * P.W * 4 : 0;
+    const bool staged = obs_bytes + mask_bytes <= (size_t)3 * P.HB * 4;
+    uint16_t* so = (uint16_t*)L.hcnt;
+    uint32_t* smk = (uint32_t*)((unsigned char*)L.hcnt + obs_bytes);
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
         const int li = tid + k * NT;
         if (li >= n) continue;
-        if (obs) write_obs_row(P, L, ag[k], t_next, obs + (row0 + li) * (int64_t)P.Ds);
-        if (mask) write_mask_row(P, L, ag[k], mask + (row0 + li) * (int64_t)P.W);
+        if (obs) write_obs_row(P, L, ag[k], t_next, (staged ? so : obs + row0 * (int64_t)P.Ds) + li * (int64_t)P.Ds);
+        if (mask) write_mask_row(P, L, ag[k], (staged ? smk : mask + row0 * (int64_t)P.W) + li * (int64_t)P.W);
+    }
+    if (!staged) return;
+    __syncthreads();
+    if (obs) {
+        const uint4* src = (const uint4*)so;
+        uint4* dst = (uint4*)(obs + row0 * (int64_t)P.Ds);
+        for (int j = tid; j < (int)(obs_bytes / 16); j += NT) dst[j] = src[j];
+    }
+    if (mask) {
+        uint32_t* dst = mask + row0 * (int64_t)P.W;
+        for (int j = tid; j < n * P.W; j += NT) dst[j] = smk[j];
     }
 }
 
@@ -1035,6 +1072,7 @@ __global__ void __launch_bounds__(1024 / APT) env_reset_kernel(const EnvParams P
     if (threadIdx.x == 0) {
         S.env_t[e] = 0;
         S.env_ep[e] = ep;
+        S.ug[e] = __builtin_nan("");
     }
     if ((int)threadIdx.x < P.K) S.env_rates[e * P.K + threadIdx.x] = 0;
 }
@@ -1079,10 +1117,11 @@ struct ej_env {
     int32_t* d_off = nullptr;
     int32_t* d_row = nullptr;
     int64_t* d_invalid = nullptr;
+    double* d_ug = nullptr;
     size_t lds = 0;
     EnvState state() const
     {
-        return EnvState{d_field, d_t, d_ep, d_rates, d_n, d_off, d_row, d_invalid};
+        return EnvState{d_field, d_t, d_ep, d_rates, d_n, d_off, d_row, d_invalid, d_ug};
     }
 };
 
@@ -1204,7 +1243,8 @@ int ej_env_create(const ej_env_config* cfg, const int32_t* h_n_per_env, ej_env**
               hipMalloc(&h->d_rates, 4 * (size_t)h->E * (size_t)(P.K > 0 ? P.K : 1)) == hipSuccess &&
               hipMalloc(&h->d_n, 4 * (size_t)h->E) == hipSuccess && hipMalloc(&h->d_off, 4 * (size_t)h->E) == hipSuccess &&
               hipMalloc(&h->d_row, 4 * (size_t)(h->E + 1)) == hipSuccess &&
-              hipMalloc(&h->d_invalid, 16 * (size_t)h->E) == hipSuccess;
+              hipMalloc(&h->d_invalid, 16 * (size_t)h->E) == hipSuccess &&
+              hipMalloc(&h->d_ug, 8 * (size_t)h->E) == hipSuccess;
     if (!ok) {
         ej_env_destroy(h);
         return EJ_ENOMEM;
@@ -1239,6 +1279,7 @@ int ej_env_destroy(ej_env* h)
     (void)hipFree(h->d_off);
     (void)hipFree(h->d_row);
     (void)hipFree(h->d_invalid);
+    (void)hipFree(h->d_ug);
     delete h;
     return EJ_OK;
 }
@@ -1399,6 +1440,8 @@ int ej_env_set_state(ej_env* h, const ej_state_view* v, void* stream)
     EJ_HIP(hipMemcpy(h->d_t, v->t, 4 * (size_t)E, hipMemcpyHostToDevice));
     EJ_HIP(hipMemcpy(h->d_ep, v->ep, 4 * (size_t)E, hipMemcpyHostToDevice));
     EJ_HIP(hipMemcpy(h->d_rates, rates.data(), rates.size() * 4, hipMemcpyHostToDevice));
+    std::vector<double> unknown((size_t)E, __builtin_nan(""));
+    EJ_HIP(hipMemcpy(h->d_ug, unknown.data(), 8 * (size_t)E, hipMemcpyHostToDevice));
     return EJ_OK;
 }
 

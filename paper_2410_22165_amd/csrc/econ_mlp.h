@@ -62,32 +62,6 @@ __host__ inline int mlp_dims(int D, int Ds, int H, int A, MlpDims* d)
 // ---------------------------------------------------------------------------
 constexpr int WSTRIDE = 40;
 
-// Global chunk (N x 32 bf16, contiguous) -> registers.  256 threads; each
-// thread moves N/64 16-byte pieces.
-template <int N>
-struct ChunkRegs {
-    uint4 v[N / 64];
-};
-
-template <int N>
-__device__ inline void chunk_load(ChunkRegs<N>& r, const uint16_t* __restrict__ src)
-{
-    const uint4* s = (const uint4*)src;
-#pragma unroll
-    for (int j = 0; j < N / 64; ++j) r.v[j] = s[threadIdx.x + 256 * j];
-}
-
-template <int N>
-__device__ inline void chunk_store(const ChunkRegs<N>& r, uint16_t* wbuf)
-{
-#pragma unroll
-    for (int j = 0; j < N / 64; ++j) {
-        const int piece = threadIdx.x + 256 * j;  // 16-byte piece: row n = piece / 4, k-quarter piece % 4
-        const int n = piece >> 2, q = piece & 3;
-        *(uint4*)(wbuf + n * WSTRIDE + q * 8) = r.v[j];
-    }
-}
-
 __device__ inline bf16x8 lds_frag(const uint16_t* p) { return *(const bf16x8*)p; }
 
 __device__ inline f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c)
@@ -133,14 +107,32 @@ __device__ inline void dense_layer(f32x4 (&acc)[RT][N / 16], const uint16_t* abu
                                    bool zero = true, int acol0 = 0)
 {
     if (zero) zero_acc(acc);
-    ChunkRegs<N> regs;
-    chunk_load<N>(regs, wglob);
+    // register prefetch of the next chunk: plain scalars (an aggregate here
+    // ends up in scratch memory)
+    constexpr int NP = N / 64;
+    uint4 q0, q1, q2, q3, q4, q5, q6, q7;
+    auto gload = [&](const uint16_t* src) {
+        const uint4* g = (const uint4*)src + threadIdx.x;
+        q0 = g[0];
+        if constexpr (NP > 1) q1 = g[256];
+        if constexpr (NP > 2) { q2 = g[512]; q3 = g[768]; }
+        if constexpr (NP > 4) { q4 = g[1024]; q5 = g[1280]; q6 = g[1536]; q7 = g[1792]; }
+    };
+    auto sput = [&](int j, uint4 v) {
+        const int piece = threadIdx.x + 256 * j;
+        *(uint4*)(wbuf + (piece >> 2) * WSTRIDE + (piece & 3) * 8) = v;
+    };
+    gload(wglob);
     const int nk = K / 32;
     for (int kt = 0; kt < nk; ++kt) {
         __syncthreads();  // everyone is done with the previous chunk
-        chunk_store<N>(regs, wbuf);
+        sput(0, q0);
+        if constexpr (NP > 1) sput(1, q1);
+        if constexpr (NP > 2) { sput(2, q2); sput(3, q3); }
+        if constexpr (NP > 4) { sput(4, q4); sput(5, q5); sput(6, q6); sput(7, q7); }
         __syncthreads();
-        if (kt + 1 < nk) chunk_load<N>(regs, wglob + (int64_t)(kt + 1) * kstride);
+        // the last step re-reads its own chunk: no branch around the loads
+        gload(wglob + (int64_t)(kt + 1 < nk ? kt + 1 : kt) * kstride);
         mfma_chunk<RT, N / 16>(acc, abuf, as, arow0, acol0 + kt * 32, wbuf);
     }
 }

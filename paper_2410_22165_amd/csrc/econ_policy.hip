@@ -19,96 +19,30 @@
 
 namespace econ {
 
-// per-row running state of the online softmax (LDS, one slot of 8 floats per row)
+// per-row running state of the online softmax (LDS, RS_N floats per row)
 enum { RS_M = 0, RS_S, RS_T, RS_W, RS_ACT, RS_Z, RS_VAL, RS_N };
-
-// Consume one 128-wide logit chunk of 16 rows that the wave staged in
-// `scr` [16][128] (logit + bias; columns >= A1 hold junk and are ignored).
-__device__ inline void softmax_chunk_rows(const MlpDims& d, const float* scr, float* rstate, int c, int64_t grow0,
-                                          int64_t M, const uint32_t* __restrict__ mask, int W, float u1_lane,
-                                          float u2_lane)
-{
-    const int l = lane_id();
-    const float NEG = -__builtin_huge_valf();
-    for (int r = 0; r < 16; ++r) {
-        const int64_t row = grow0 + r;
-        if (row >= M) break;
-        const float2 z = *(const float2*)(scr + r * 128 + 2 * l);
-        const int a0 = c * 128 + 2 * l, a1 = a0 + 1;
-        const uint32_t mw = (a0 < d.A) ? mask[row * W + (a0 >> 5)] : 0u;
-        const bool ok0 = a0 < d.A && ((mw >> (a0 & 31)) & 1u);
-        const bool ok1 = a1 < d.A && ((mw >> (a1 & 31)) & 1u);
-        float* st = rstate + r * RS_N;
-        if (a0 == d.A) st[RS_VAL] = z.x;  // the value head sits right after the logits
-        if (a1 == d.A) st[RS_VAL] = z.y;
-        float mc = wave_max(fmaxf(ok0 ? z.x : NEG, ok1 ? z.y : NEG));
-        if (mc == NEG) continue;  // nothing allowed in this chunk
-        const float e0 = ok0 ? __expf(z.x - mc) : 0.f;
-        const float e1 = ok1 ? __expf(z.y - mc) : 0.f;
-        const float incl = wave_inclusive_scan(e0 + e1);
-        const float Sc = __shfl(incl, 63, 64);
-        const float Tc = wave_sum(e0 * (z.x - mc) + e1 * (z.y - mc));
-        const float m = st[RS_M], S = st[RS_S], T = st[RS_T], Wr = st[RS_W];
-        const float mn = fmaxf(m, mc);
-        const float fo = (m == NEG) ? 0.f : __expf(m - mn), fc = __expf(mc - mn);
-        const float Sn = S * fo + Sc * fc;
-        const float Tn = (m == NEG ? 0.f : fo * (T + (m - mn) * S)) + fc * (Tc + (mc - mn) * Sc);
-        const float Wn = Wr * fo + Sc * fc;
-        const float u1 = __shfl(u1_lane, r, 64), u2 = __shfl(u2_lane, r, 64);
-        bool take = u1 * Wn < Sc * fc;
-        int pick = -1;
-        float zpick = 0.f;
-        if (take) {
-            const float target = u2 * Sc;
-            const uint64_t hit = __ballot(incl > target);
-            int ln;
-            if (hit) {
-                ln = __builtin_ctzll(hit);
-            } else {  // rounding put the target at the very top: the last allowed action
-                ln = 63 - __builtin_clzll(__ballot(ok0 || ok1));
-            }
-            const float ex = __shfl(incl - (e0 + e1), ln, 64);
-            const float f0 = __shfl(e0, ln, 64), f1 = __shfl(e1, ln, 64);
-            const float z0 = __shfl(z.x, ln, 64), z1 = __shfl(z.y, ln, 64);
-            const bool first = (hit && ex + f0 > target) || (!hit && f1 == 0.f);
-            pick = c * 128 + 2 * ln + (first ? 0 : 1);
-            zpick = first ? z0 : z1;
-        }
-        if (l == 0) {
-            st[RS_M] = mn;
-            st[RS_S] = Sn;
-            st[RS_T] = Tn;
-            st[RS_W] = Wn;
-            if (take) {
-                st[RS_ACT] = __int_as_float(pick);
-                st[RS_Z] = zpick;
-            }
-        }
-        wave_lds_fence();
-    }
-}
 
 template <int H>
 __global__ void __launch_bounds__(256)
 policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
                       const uint16_t* __restrict__ obs, const uint32_t* __restrict__ mask, int64_t M, int W,
-                      uint64_t seed, uint64_t ctr, int32_t* __restrict__ act, float* __restrict__ logp,
-                      float* __restrict__ val, float* __restrict__ ent, float* __restrict__ logits)
+                      uint64_t seed, uint64_t ctr_arg, const uint64_t* __restrict__ ctr_base,
+                      int32_t* __restrict__ act, float* __restrict__ logp, float* __restrict__ val,
+                      float* __restrict__ ent, float* __restrict__ logits)
 {
+    const uint64_t ctr = ctr_arg + (ctr_base ? *ctr_base : 0ull);
     using T = MlpTile<H>;
     constexpr int RT = T::RT, RPW = T::RPW, TILE = T::TILE, HS = T::HS;
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* hbuf = (uint16_t*)smem;
     uint16_t* wbuf = hbuf + TILE * HS;
-    float* scratch = (float*)(wbuf + T::WREG);  // [4 waves][16][128]
-    float* rstate = scratch + 4 * 16 * 128;       // [4 waves][RPW][RS_N]
+    uint32_t* smask = (uint32_t*)(wbuf + T::WREG);  // [TILE][W]
+    float* rstate = (float*)(smask + TILE * W);      // [TILE][RS_N] running softmax state per row
     const int wave = threadIdx.x >> 6, l = lane_id();
     const int64_t row0 = (int64_t)blockIdx.x * TILE;
     const int arow0 = wave * RPW;
-    float* scr = scratch + wave * 16 * 128;
-    float* rs = rstate + wave * RPW * RS_N;
 
-    // observation tile -> activation buffer columns [0, K1p)
+    // observation tile -> activation buffer columns [0, K1p); mask rows -> LDS
     const int ppr = d.K1p / 8;
     for (int p = threadIdx.x; p < TILE * ppr; p += 256) {
         const int r = p / ppr, cc = p - r * ppr;
@@ -117,9 +51,13 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
         if (row < M && cc * 8 < d.Ds) v = *(const uint4*)(obs + row * d.Ds + cc * 8);
         *(uint4*)(hbuf + r * HS + cc * 8) = v;
     }
-    for (int j = l; j < RPW * RS_N; j += 64) {
-        const int k = j % RS_N;
-        rs[j] = (k == RS_M) ? -__builtin_huge_valf() : (k == RS_ACT ? __int_as_float(0) : 0.f);
+    for (int p = threadIdx.x; p < TILE * W; p += 256) {
+        const int64_t row = row0 + p / W;
+        smask[p] = row < M ? mask[row0 * W + p] : 0u;
+    }
+    for (int p = threadIdx.x; p < TILE * RS_N; p += 256) {
+        const int k = p % RS_N;
+        rstate[p] = k == RS_M ? -__builtin_huge_valf() : (k == RS_ACT ? __int_as_float(0) : 0.f);
     }
 
     f32x4 acc[RT][H / 16];
@@ -128,47 +66,112 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     dense_layer<RT, H>(acc, hbuf, HS, arow0, H, work + d.oW2f, (int64_t)H * 32, wbuf);
     epilogue_relu<RT, H / 16>(acc, params + d.ob2, hbuf, HS, arow0);
 
+    // The logits are consumed in the MFMA accumulator layout: lane l owns rows
+    // 4 (l / 16) + i of each 16-row tile, so the 16 lanes of a DPP row share
+    // one matrix row.  The running state of each row lives in LDS between
+    // chunks (registers are taken by the accumulators).
+    const float NEG = -__builtin_huge_valf();
     for (int c = 0; c < d.NC; ++c) {
         f32x4 acc3[RT][8];
         dense_layer<RT, 128>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32,
                              wbuf);
+        // uniforms of chunk c: lane j < RPW draws for the wave's row j
+        float u1L = 0.f, u2L = 0.f;
+        if (l < RPW) {
+            u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row0 + arow0 + l), ctr, (uint64_t)(c >> 1), 0);
+            u1L = unif24(word_of(w, 2 * (c & 1)));
+            u2L = unif24(word_of(w, 2 * (c & 1) + 1));
+        }
+        float bcol[8];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int64_t grow0 = row0 + arow0 + rt * 16;
-            // per-row uniforms: lane r < 16 draws for row grow0 + r
-            float u1 = 0.f, u2 = 0.f;
-            if (l < 16) {
-                u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(grow0 + l), ctr, (uint64_t)(c >> 1), 0);
-                u1 = unif24(word_of(w, 2 * (c & 1)));
-                u2 = unif24(word_of(w, 2 * (c & 1) + 1));
-            }
+        for (int ct = 0; ct < 8; ++ct) {
+            const int col = c * 128 + ct * 16 + (l & 15);
+            bcol[ct] = col < d.A1 ? params[d.ob3 + col] : 0.f;
+        }
 #pragma unroll
-            for (int ct = 0; ct < 8; ++ct) {
-                const int col = c * 128 + ct * 16 + (l & 15);
-                const float b = col < d.A1 ? params[d.ob3 + col] : 0.f;
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) scr[(4 * (l >> 4) + i) * 128 + ct * 16 + (l & 15)] = acc3[rt][ct][i] + b;
-            }
-            wave_lds_fence();
-            if (logits) {
-                for (int r = 0; r < 16; ++r) {
-                    const int64_t row = grow0 + r;
-                    if (row >= M) break;
-                    for (int j = l; j < 128; j += 64) {
-                        const int a = c * 128 + j;
-                        if (a < d.A) logits[row * d.A + a] = scr[r * 128 + j];
+            for (int i = 0; i < 4; ++i) {
+                const int rw = rt * 16 + 4 * (l >> 4) + i;  // row within the wave
+                const int rloc = arow0 + rw;
+                const float u1 = __shfl(u1L, rw, 64), u2 = __shfl(u2L, rw, 64);
+                float z[8];
+                bool ok[8];
+                float zval = 0.f, zmax = NEG;
+#pragma unroll
+                for (int ct = 0; ct < 8; ++ct) {
+                    const int col = c * 128 + ct * 16 + (l & 15);
+                    const int wi = c * 4 + (ct >> 1);
+                    const uint32_t mw = wi < W ? smask[rloc * W + wi] : 0u;
+                    z[ct] = acc3[rt][ct][i] + bcol[ct];
+                    ok[ct] = col < d.A && ((mw >> (col & 31)) & 1u);
+                    if (col == d.A) zval = z[ct];
+                    if (ok[ct]) zmax = fmaxf(zmax, z[ct]);
+                }
+                float* st = rstate + rloc * RS_N;
+                const float zv = row16_sum(zval);  // the value head sits right after the logits
+                const float mc = row16_max(zmax);
+                const bool any = mc != NEG;
+                float e[8], P[8], carry = 0.f, tl = 0.f;
+#pragma unroll
+                for (int ct = 0; ct < 8; ++ct) {
+                    e[ct] = ok[ct] ? __expf(z[ct] - mc) : 0.f;
+                    tl += ok[ct] ? e[ct] * (z[ct] - mc) : 0.f;
+                    P[ct] = carry + row16_scan(e[ct]);
+                    carry += row16_sum(e[ct]);
+                }
+                const float Sc = carry;
+                const float Tc = row16_sum(tl);
+                if (logits) {
+                    const int64_t row = row0 + rloc;
+                    if (row < M)
+#pragma unroll
+                        for (int ct = 0; ct < 8; ++ct) {
+                            const int col = c * 128 + ct * 16 + (l & 15);
+                            if (col < d.A) logits[row * d.A + col] = z[ct];
+                        }
+                }
+                const float m = st[RS_M], S0 = st[RS_S], T0 = st[RS_T], W0 = st[RS_W];
+                const float mn = any ? fmaxf(m, mc) : m;
+                const float fo = (m == NEG) ? 0.f : __expf(m - mn), fc = any ? __expf(mc - mn) : 0.f;
+                const float Tn = (m == NEG ? 0.f : fo * (T0 + (m - mn) * S0)) + (any ? fc * (Tc + (mc - mn) * Sc) : 0.f);
+                const float Sn = S0 * fo + Sc * fc;
+                const float Wn = W0 * fo + Sc * fc;
+                const bool take = any && u1 * Wn < Sc * fc;
+                // first allowed action whose cumulative weight exceeds u2 * Sc
+                const float target = u2 * Sc;
+                int key = 1 << 20, last = -1;
+#pragma unroll
+                for (int ct = 7; ct >= 0; --ct) {
+                    if (ok[ct] && P[ct] > target) key = ct * 16 + (l & 15);
+                    if (ok[ct] && last < 0) last = ct * 16 + (l & 15);
+                }
+                key = row16_min_i(key);
+                if (key == (1 << 20)) key = row16_max_i(last);  // rounding put the target at the top
+                float zk = 0.f;
+#pragma unroll
+                for (int ct = 0; ct < 8; ++ct)
+                    if (ct * 16 + (l & 15) == key) zk = z[ct];
+                zk = row16_sum(zk);
+                if ((l & 15) == 0) {
+                    st[RS_M] = mn;
+                    st[RS_S] = Sn;
+                    st[RS_T] = Tn;
+                    st[RS_W] = Wn;
+                    st[RS_VAL] += zv;
+                    if (take) {
+                        st[RS_ACT] = __int_as_float(c * 128 + key);
+                        st[RS_Z] = zk;
                     }
                 }
             }
-            softmax_chunk_rows(d, scr, rs + rt * 16 * RS_N, c, grow0, M, mask, W, u1, u2);
-            wave_lds_fence();
-        }
     }
-    // outputs: log-probability of the sampled action, entropy, value
-    for (int r = l; r < RPW; r += 64) {
-        const int64_t row = row0 + arow0 + r;
+    __syncthreads();
+    // outputs: sampled action, its log-probability, entropy, value
+    for (int r = threadIdx.x; r < TILE; r += 256) {
+        const int64_t row = row0 + r;
         if (row >= M) continue;
-        const float* st = rs + r * RS_N;
+        const float* st = rstate + r * RS_N;
         const float S = st[RS_S];
         int a = __float_as_int(st[RS_ACT]);
         float lp = 0.f, h = 0.f;
@@ -220,22 +223,22 @@ __global__ void mlp_sync_kernel(const MlpDims d, const float* __restrict__ p, ui
 }
 
 template <int H>
-size_t policy_lds_bytes()
+size_t policy_lds_bytes(int W)
 {
     using T = MlpTile<H>;
-    return (size_t)T::TILE * T::HS * 2 + (size_t)T::WREG * 2 + 4 * 16 * 128 * 4 + 4 * (size_t)T::RPW * RS_N * 4;
+    return (size_t)T::TILE * T::HS * 2 + (size_t)T::WREG * 2 + (size_t)T::TILE * W * 4 + (size_t)T::TILE * RS_N * 4;
 }
 
 template <int H>
 int launch_policy_forward(const MlpDims& d, const float* params, const uint16_t* work, const uint16_t* obs,
-                          const uint32_t* mask, int64_t M, int W, uint64_t seed, uint64_t ctr, int32_t* act,
-                          float* logp, float* val, float* ent, float* logits, hipStream_t st)
+                          const uint32_t* mask, int64_t M, int W, uint64_t seed, uint64_t ctr, const uint64_t* ctr_base,
+                          int32_t* act, float* logp, float* val, float* ent, float* logits, hipStream_t st)
 {
     using T = MlpTile<H>;
     const int64_t blocks = (M + T::TILE - 1) / T::TILE;
-    const size_t lds = policy_lds_bytes<H>();
-    policy_forward_kernel<H><<<(unsigned)blocks, 256, lds, st>>>(d, params, work, obs, mask, M, W, seed, ctr, act,
-                                                                  logp, val, ent, logits);
+    const size_t lds = policy_lds_bytes<H>(W);
+    policy_forward_kernel<H><<<(unsigned)blocks, 256, lds, st>>>(d, params, work, obs, mask, M, W, seed, ctr, ctr_base,
+                                                                  act, logp, val, ent, logits);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }
@@ -282,9 +285,22 @@ int ej_mlp_sync_weights(const ej_mlp_desc* m, const float* d_params, uint16_t* d
     return EJ_OK;
 }
 
+__global__ void counter_add_kernel(uint64_t* c, uint64_t inc)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c += inc;
+}
+
+int ej_counter_add(uint64_t* d_counter, uint64_t inc, void* stream)
+{
+    if (!d_counter) return EJ_EINVAL;
+    counter_add_kernel<<<1, 64, 0, (hipStream_t)stream>>>(d_counter, inc);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
 int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const uint16_t* d_obs,
-                      const uint32_t* d_mask, int64_t M, uint64_t seed, uint64_t ctr, int32_t* d_act, float* d_logp,
-                      float* d_val, float* d_ent, float* d_logits, void* stream)
+                      const uint32_t* d_mask, int64_t M, uint64_t seed, uint64_t ctr, const uint64_t* d_ctr_base,
+                      int32_t* d_act, float* d_logp, float* d_val, float* d_ent, float* d_logits, void* stream)
 {
     MlpDims d;
     int rc = desc_dims(m, &d);
@@ -294,10 +310,10 @@ int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_
     const int W = (m->A + 31) / 32;
     hipStream_t st = (hipStream_t)stream;
     switch (m->H) {
-    case 64: return launch_policy_forward<64>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_act, d_logp, d_val, d_ent, d_logits, st);
-    case 128: return launch_policy_forward<128>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_act, d_logp, d_val, d_ent, d_logits, st);
-    case 256: return launch_policy_forward<256>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_act, d_logp, d_val, d_ent, d_logits, st);
-    default: return launch_policy_forward<512>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_act, d_logp, d_val, d_ent, d_logits, st);
+    case 64: return launch_policy_forward<64>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_ctr_base, d_act, d_logp, d_val, d_ent, d_logits, st);
+    case 128: return launch_policy_forward<128>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_ctr_base, d_act, d_logp, d_val, d_ent, d_logits, st);
+    case 256: return launch_policy_forward<256>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_ctr_base, d_act, d_logp, d_val, d_ent, d_logits, st);
+    default: return launch_policy_forward<512>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_ctr_base, d_act, d_logp, d_val, d_ent, d_logits, st);
     }
 }
 

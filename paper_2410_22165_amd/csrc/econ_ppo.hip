@@ -116,18 +116,8 @@ __global__ void adv_stats_final(const double* __restrict__ part, int nb, int64_t
 // ---------------------------------------------------------------------------
 // the fused row kernel
 // ---------------------------------------------------------------------------
-__device__ inline float group16_max(float v)
-{
-#pragma unroll
-    for (int k = 1; k < 16; k <<= 1) v = fmaxf(v, __shfl_xor(v, k, 64));
-    return v;
-}
-__device__ inline float group16_sum(float v)
-{
-#pragma unroll
-    for (int k = 1; k < 16; k <<= 1) v += __shfl_xor(v, k, 64);
-    return v;
-}
+__device__ inline float group16_max(float v) { return row16_max(v); }
+__device__ inline float group16_sum(float v) { return row16_sum(v); }
 
 // 4 consecutive rows (acc element order) of one column -> 8-byte store in the m-block layout
 __device__ inline void store_mblock4(uint16_t* T, int ncol, int64_t jrow, int col, const float (&v)[4])

@@ -54,9 +54,10 @@ def test_adam_parity():
     assert np.allclose(pw.cpu().numpy(), w, rtol=1e-5, atol=1e-7)
 
 
-def make_storage(D, Ds, H, A, M, seed):
+def make_storage(D, Ds, H, A, M, seed, ratio_noise=0.3):
     """A synthetic rollout store with logp_old near the current policy (so
-    that some ratios leave the clip range)."""
+    that some ratios leave the clip range; ratio_noise = 0 puts every ratio
+    at 1, far from the clip thresholds)."""
     rng = np.random.default_rng(seed)
     w = W.policy_weights(D, H, A, seed=seed)
     for k in ("b1", "b2", "b3"):
@@ -68,7 +69,7 @@ def make_storage(D, Ds, H, A, M, seed):
     allowed = op.unpack_mask(mask, A)
     lp = op.masked_log_softmax(logits, allowed)
     act = np.array([rng.choice(np.flatnonzero(allowed[m])) for m in range(M)], np.int32)
-    logp_old = (lp[np.arange(M), act] + rng.normal(size=M) * 0.3).astype(np.float32)
+    logp_old = (lp[np.arange(M), act] + rng.normal(size=M) * ratio_noise).astype(np.float32)
     val_old = (value + rng.normal(size=M) * 0.5).astype(np.float32)
     adv = rng.normal(size=M).astype(np.float32)
     ret = (value + rng.normal(size=M)).astype(np.float32)
@@ -104,11 +105,13 @@ def test_ppo_backward_matches_reference_autograd(case):
     idx = (a * (begin + np.arange(rows)) + c) % M
     sub = {k: v[idx] for k, v in st.items()}
     x = oe.bf16_bits_to_f32(sub["obs"][:, :D]).astype(np.float64)
+    # the clip decisions of every row are taken in the kernel's precision (bf16 hidden activations)
     l_o, terms, g_o = op.ppo_grads(w, x, sub["mask"], sub["act"], sub["logp_old"], sub["val_old"], sub["adv"],
-                                   sub["ret"], HP)
+                                   sub["ret"], HP, bf16_hidden=True)
     gg = mlp.unflat(g)
-    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
-        e = rel_err(gg[k].astype(np.float64), g_o[k])
+    errs = {k: rel_err(gg[k].astype(np.float64), g_o[k]) for k in ("W1", "b1", "W2", "b2", "W3", "b3")}
+    print("relative gradient errors", errs, flush=True)
+    for k, e in errs.items():
         assert e <= 1e-2, (k, e)
     assert abs(loss[0] - terms["pg"]) <= 1e-2 * max(1.0, abs(terms["pg"]))
     assert abs(loss[1] - terms["vf"]) <= 1e-2 * max(1.0, abs(terms["vf"]))
@@ -120,7 +123,9 @@ def test_ppo_backward_finite_differences_one_economy_slice():
     against float64 central differences of the oracle loss."""
     import torch
     D, Ds, H, A, M = 35, 40, 256, 125, 100
-    w, st = make_storage(D, Ds, H, A, M, seed=11)
+    # ratios at 1: no row sits near a clip threshold, so the float64 loss is
+    # smooth around the weights and central differences are meaningful
+    w, st = make_storage(D, Ds, H, A, M, seed=11, ratio_noise=0.0)
     mlp, g, _ = gpu_backward(w, st, D, Ds, H, A, M, 1, 0, 0, M)
     gg = mlp.unflat(g)
     wb = op.bf16_weights(w)
@@ -134,20 +139,20 @@ def test_ppo_backward_finite_differences_one_economy_slice():
 
     rng = np.random.default_rng(3)
     h = 1e-5
-    checked = 0
     for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
         flat = np.abs(gg[k]).ravel()
         order = np.argsort(-flat)[:40]
-        for pos in rng.choice(order, size=4, replace=False):
+        got, want = [], []
+        for pos in rng.choice(order, size=6, replace=False):
             idx = np.unravel_index(pos, gg[k].shape)
             pp = {kk: vv.copy() for kk, vv in wb.items()}
             pm = {kk: vv.copy() for kk, vv in wb.items()}
             pp[k][idx] += h
             pm[k][idx] -= h
-            fd = (f(pp) - f(pm)) / (2 * h)
-            assert abs(gg[k][idx] - fd) <= 1e-2 * abs(fd) + 1e-6, (k, idx, gg[k][idx], fd)
-            checked += 1
-    assert checked == 24
+            want.append((f(pp) - f(pm)) / (2 * h))
+            got.append(float(gg[k][idx]))
+        got, want = np.array(got), np.array(want)
+        assert np.linalg.norm(got - want) <= 1e-2 * np.linalg.norm(want), (k, got, want)
 
 
 def test_ppo_backward_deterministic():
