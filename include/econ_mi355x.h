@@ -210,7 +210,9 @@ int ej_mlp_sync_weights(const ej_mlp_desc* m, const float* d_params, uint16_t* d
  * d_logits [M * A] (nullable) receives the raw logits (debugging and tests).
  * Sampling is exact for the masked softmax: the logits are taken in chunks
  * of 128 actions, a chunk is chosen by weighted reservoir with one uniform
- * and the action inside it by inverse CDF with a second one; the uniforms of
+ * and the action inside it by inverse CDF with a second one (the chunk's
+ * actions walked in the order c 128 + 16 t + j, j = 0..15 outer, t = 0..7
+ * inner); the uniforms of
  * row r, chunk c come from the counter-based generator keyed (seed, r, ctr',
  * c / 2) with ctr' = ctr + *d_ctr_base (d_ctr_base: nullable device
  * uint64_t, read when the kernel runs, so that a captured graph replayed

@@ -91,22 +91,35 @@ def sample_inverse_cdf(logp: np.ndarray, u: np.ndarray):
     return act, margin
 
 
+def chunk_walk_order(chunk: int = 128, lanes: int = 16) -> np.ndarray:
+    """Order in which the actions of one chunk are walked by the inverse CDF:
+    offset 16 t + j for j = 0..15 (outer) and t = 0..7 (inner)."""
+    per = chunk // lanes
+    return np.array([t * lanes + j for j in range(lanes) for t in range(per)], np.int64)
+
+
 def sample_chunked(logp: np.ndarray, u1: np.ndarray, u2: np.ndarray, chunk: int = 128):
     """Exact categorical sampling in chunks of `chunk` actions: chunk c (total
     probability S_c) becomes the candidate when u1_c * (S_0 + ... + S_c) < S_c
-    (weighted reservoir); inside the candidate the action is the first one
-    whose cumulative probability within the chunk exceeds u2_c * S_c.
-    Returns the actions and the smallest distance of any of the row's
-    decisions from its threshold (relative to the quantity compared)."""
+    (weighted reservoir); inside the candidate the actions are walked in the
+    fixed order of chunk_walk_order and the first whose cumulative
+    probability exceeds u2_c * S_c is drawn.  Any fixed walk order samples the
+    same distribution.  Returns the actions and the smallest distance of any
+    of the row's decisions from its threshold (relative to the quantity
+    compared)."""
     p = np.exp(logp)
     M, A = p.shape
     NC = (A + chunk - 1) // chunk
+    order = chunk_walk_order(chunk)
     act = np.zeros(M, np.int64)
     margin = np.full(M, np.inf)
     for m in range(M):
         W = 0.0
         for c in range(NC):
-            pc = p[m, c * chunk:(c + 1) * chunk]
+            pc = np.zeros(chunk)
+            seg = p[m, c * chunk:(c + 1) * chunk]
+            pc[:len(seg)] = seg
+            pc = pc[order]
             Sc = pc.sum()
             if Sc <= 0.0:
                 continue
@@ -121,7 +134,7 @@ def sample_chunked(logp: np.ndarray, u1: np.ndarray, u2: np.ndarray, chunk: int 
                 j = min(j, len(pc) - 1)
                 while pc[j] == 0.0 and j > 0:
                     j -= 1
-                act[m] = c * chunk + j
+                act[m] = c * chunk + order[j]
                 lo = cdf[j - 1] if j > 0 else 0.0
                 margin[m] = min(margin[m], abs(target - lo) / Sc, abs(cdf[j] - target) / Sc)
     return act, margin

@@ -77,12 +77,17 @@ __host__ __device__ inline uint64_t word_of(const u64x4& v, int i)
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
 }
 
-// round-to-nearest-even float -> bfloat16 bits
+// round-to-nearest-even float -> bfloat16 bits (the device uses the gfx950
+// conversion instruction; the host spells the rounding out)
 __host__ __device__ inline uint16_t f32_to_bf16(float f)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
+#else
     uint32_t u = __builtin_bit_cast(uint32_t, f);
     if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
     return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+#endif
 }
 
 __host__ __device__ inline float bf16_to_f32(uint16_t b)

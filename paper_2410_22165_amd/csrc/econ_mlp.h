@@ -76,14 +76,21 @@ __device__ inline void mfma_chunk(f32x4 (&acc)[RT][CT], const uint16_t* abuf, in
                                   const uint16_t* wbuf)
 {
     const int l = lane_id();
+    const uint16_t* bp = wbuf + (l & 15) * WSTRIDE + 8 * (l >> 4);
     bf16x8 a[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) a[rt] = lds_frag(abuf + (arow0 + rt * 16 + (l & 15)) * as + kcol + 8 * (l >> 4));
+    // B fragments run four column tiles ahead of the MFMAs that consume them
+    constexpr int PD = CT < 4 ? CT : 4;
+    bf16x8 b[PD];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) b[j] = lds_frag(bp + j * 16 * WSTRIDE);
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-        bf16x8 b = lds_frag(wbuf + (ct * 16 + (l & 15)) * WSTRIDE + 8 * (l >> 4));
+        const bf16x8 cur = b[ct % PD];
+        if (ct + PD < CT) b[ct % PD] = lds_frag(bp + (ct + PD) * 16 * WSTRIDE);
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = mfma16(a[rt], b, acc[rt][ct]);
+        for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = mfma16(a[rt], cur, acc[rt][ct]);
     }
 }
 
@@ -96,45 +103,94 @@ __device__ inline void zero_acc(f32x4 (&acc)[RT][CT])
         for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 }
 
+// Weight-chunk prefetch registers: eight 16-byte pieces per thread at most
+// (N / 64 used).  Plain scalars passed by reference: an aggregate here ends up
+// in scratch memory.
+#define ECON_Q8_PARAMS uint4 &q0, uint4 &q1, uint4 &q2, uint4 &q3, uint4 &q4, uint4 &q5, uint4 &q6, uint4 &q7
+#define ECON_Q8_ARGS q0, q1, q2, q3, q4, q5, q6, q7
+#define ECON_Q8_DECL uint4 q0, q1, q2, q3, q4, q5, q6, q7
+
+template <int N>
+__device__ __forceinline__ void chunk_gload(const uint16_t* __restrict__ src, ECON_Q8_PARAMS)
+{
+    constexpr int NP = N / 64;
+    const uint4* g = (const uint4*)src + threadIdx.x;
+    q0 = g[0];
+    if constexpr (NP > 1) q1 = g[256];
+    if constexpr (NP > 2) { q2 = g[512]; q3 = g[768]; }
+    if constexpr (NP > 4) { q4 = g[1024]; q5 = g[1280]; q6 = g[1536]; q7 = g[1792]; }
+}
+
+__device__ __forceinline__ void chunk_sput(uint16_t* wbuf, int j, const uint4& v)
+{
+    const int piece = threadIdx.x + 256 * j;  // row n = piece / 4, k-quarter piece % 4
+    *(uint4*)(wbuf + (piece >> 2) * WSTRIDE + (piece & 3) * 8) = v;
+}
+
+template <int N>
+__device__ __forceinline__ void chunk_lds_store(uint16_t* wbuf, ECON_Q8_PARAMS)
+{
+    constexpr int NP = N / 64;
+    chunk_sput(wbuf, 0, q0);
+    if constexpr (NP > 1) chunk_sput(wbuf, 1, q1);
+    if constexpr (NP > 2) { chunk_sput(wbuf, 2, q2); chunk_sput(wbuf, 3, q3); }
+    if constexpr (NP > 4) { chunk_sput(wbuf, 4, q4); chunk_sput(wbuf, 5, q5); chunk_sput(wbuf, 6, q6); chunk_sput(wbuf, 7, q7); }
+}
+
 // One dense layer for the workgroup's row tile: every wave multiplies its own
-// rows of `abuf` by a weight matrix streamed chunk by chunk through `wbuf`
-// (single LDS buffer; the next chunk is prefetched into registers while the
-// current one is consumed).  All 256 threads must call it.
+// rows of `abuf` (row stride `as`, rows from `arow0`, columns from `acol0`)
+// by a weight matrix streamed 32 k-rows at a time through LDS.  With DB the
+// chunks alternate between two LDS buffers (one barrier per k-step); without
+// it one buffer is refilled between two barriers.  The next chunk is
+// prefetched into registers while the current one is consumed; after the
+// last chunk the first chunk of the next layer (`next`, N2 columns) is
+// prefetched instead, so that the next call can start with `preloaded`.
 // `kstride`: elements between the global chunks of consecutive k-steps.
-template <int RT, int N>
+// All 256 threads must call it.
+template <int RT, int N, int N2 = N, bool DB = false>
+__device__ inline void dense_layer_pf(f32x4 (&acc)[RT][N / 16], const uint16_t* abuf, int as, int arow0, int K,
+                                      const uint16_t* __restrict__ wglob, int64_t kstride, uint16_t* wbuf,
+                                      bool preloaded, const uint16_t* __restrict__ next, ECON_Q8_PARAMS,
+                                      bool zero = true, int acol0 = 0)
+{
+    if (zero) zero_acc(acc);
+    if (!preloaded) chunk_gload<N>(wglob, ECON_Q8_ARGS);
+    const int nk = K / 32;
+    if constexpr (DB) {
+        constexpr int WB = N * WSTRIDE;  // elements per buffer
+        __syncthreads();                 // the previous layer is done with both buffers
+        chunk_lds_store<N>(wbuf, ECON_Q8_ARGS);
+        if (nk > 1) chunk_gload<N>(wglob + kstride, ECON_Q8_ARGS);
+        else if (next) chunk_gload<N2>(next, ECON_Q8_ARGS);
+        for (int kt = 0; kt < nk; ++kt) {
+            __syncthreads();  // chunk kt is in LDS; the other buffer is free
+            if (kt + 1 < nk) {
+                chunk_lds_store<N>(wbuf + ((kt + 1) & 1) * WB, ECON_Q8_ARGS);
+                if (kt + 2 < nk) chunk_gload<N>(wglob + (int64_t)(kt + 2) * kstride, ECON_Q8_ARGS);
+                else if (next) chunk_gload<N2>(next, ECON_Q8_ARGS);
+            }
+            mfma_chunk<RT, N / 16>(acc, abuf, as, arow0, acol0 + kt * 32, wbuf + (kt & 1) * WB);
+        }
+    } else {
+        for (int kt = 0; kt < nk; ++kt) {
+            __syncthreads();  // everyone is done with the previous chunk
+            chunk_lds_store<N>(wbuf, ECON_Q8_ARGS);
+            __syncthreads();
+            if (kt + 1 < nk) chunk_gload<N>(wglob + (int64_t)(kt + 1) * kstride, ECON_Q8_ARGS);
+            else if (next) chunk_gload<N2>(next, ECON_Q8_ARGS);
+            mfma_chunk<RT, N / 16>(acc, abuf, as, arow0, acol0 + kt * 32, wbuf);
+        }
+    }
+}
+
+template <int RT, int N, bool DB = false>
 __device__ inline void dense_layer(f32x4 (&acc)[RT][N / 16], const uint16_t* abuf, int as, int arow0, int K,
                                    const uint16_t* __restrict__ wglob, int64_t kstride, uint16_t* wbuf,
                                    bool zero = true, int acol0 = 0)
 {
-    if (zero) zero_acc(acc);
-    // register prefetch of the next chunk: plain scalars (an aggregate here
-    // ends up in scratch memory)
-    constexpr int NP = N / 64;
-    uint4 q0, q1, q2, q3, q4, q5, q6, q7;
-    auto gload = [&](const uint16_t* src) {
-        const uint4* g = (const uint4*)src + threadIdx.x;
-        q0 = g[0];
-        if constexpr (NP > 1) q1 = g[256];
-        if constexpr (NP > 2) { q2 = g[512]; q3 = g[768]; }
-        if constexpr (NP > 4) { q4 = g[1024]; q5 = g[1280]; q6 = g[1536]; q7 = g[1792]; }
-    };
-    auto sput = [&](int j, uint4 v) {
-        const int piece = threadIdx.x + 256 * j;
-        *(uint4*)(wbuf + (piece >> 2) * WSTRIDE + (piece & 3) * 8) = v;
-    };
-    gload(wglob);
-    const int nk = K / 32;
-    for (int kt = 0; kt < nk; ++kt) {
-        __syncthreads();  // everyone is done with the previous chunk
-        sput(0, q0);
-        if constexpr (NP > 1) sput(1, q1);
-        if constexpr (NP > 2) { sput(2, q2); sput(3, q3); }
-        if constexpr (NP > 4) { sput(4, q4); sput(5, q5); sput(6, q6); sput(7, q7); }
-        __syncthreads();
-        // the last step re-reads its own chunk: no branch around the loads
-        gload(wglob + (int64_t)(kt + 1 < nk ? kt + 1 : kt) * kstride);
-        mfma_chunk<RT, N / 16>(acc, abuf, as, arow0, acol0 + kt * 32, wbuf);
-    }
+    ECON_Q8_DECL;
+    dense_layer_pf<RT, N, N, DB>(acc, abuf, as, arow0, K, wglob, kstride, wbuf, false, nullptr, ECON_Q8_ARGS, zero,
+                                 acol0);
 }
 
 // bias + ReLU, rounded to bf16, written to the wave's own rows of hbuf
@@ -174,6 +230,8 @@ struct MlpTile {
     static constexpr int TILE = 4 * RPW;             // rows per workgroup
     static constexpr int HS = H + 8;                 // LDS row stride of activations
     static constexpr int WREG = (H > 128 ? H : 128) * WSTRIDE;  // weight chunk elements
+    static constexpr bool DB = H <= 256;             // double-buffered weight chunks fit in LDS
+    static constexpr int WBUF = DB ? 2 * WREG : WREG;
 };
 
 }  // namespace econ

@@ -14,13 +14,15 @@
 // running total W accumulates S_c; the chunk becomes the candidate when
 // u1_c * W < S_c (weighted reservoir: chunk c ends chosen with probability
 // S_c / sum S).  Inside a candidate chunk the action is the first allowed
-// action whose cumulative weight exceeds u2_c * S_c (inverse CDF).
+// action whose cumulative weight exceeds u2_c * S_c (inverse CDF), walking
+// the chunk's actions in the fixed order c 128 + 16 t + j for j = 0..15
+// (outer) and t = 0..7 (inner) -- the order of the MFMA accumulator layout.
 #include "econ_mlp.h"
 
 namespace econ {
 
 // per-row running state of the online softmax (LDS, RS_N floats per row)
-enum { RS_M = 0, RS_S, RS_T, RS_W, RS_ACT, RS_Z, RS_VAL, RS_N };
+enum { RS_M = 0, RS_S, RS_T, RS_W, RS_ACT, RS_Z, RS_VAL, RS_U1, RS_U2, RS_N };
 
 template <int H>
 __global__ void __launch_bounds__(256)
@@ -36,12 +38,16 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* hbuf = (uint16_t*)smem;
     uint16_t* wbuf = hbuf + TILE * HS;
-    uint32_t* smask = (uint32_t*)(wbuf + T::WREG);  // [TILE][W]
+    uint32_t* smask = (uint32_t*)(wbuf + T::WBUF);  // [TILE][W]
     float* rstate = (float*)(smask + TILE * W);      // [TILE][RS_N] running softmax state per row
+    float* sbias = rstate + TILE * RS_N;              // b1 [H], b2 [H], b3 [A1p] (zero padded)
     const int wave = threadIdx.x >> 6, l = lane_id();
     const int64_t row0 = (int64_t)blockIdx.x * TILE;
     const int arow0 = wave * RPW;
 
+    // first weight chunk in flight while the tile loads
+    ECON_Q8_DECL;
+    chunk_gload<H>(work + d.oW1f, ECON_Q8_ARGS);
     // observation tile -> activation buffer columns [0, K1p); mask rows -> LDS
     const int ppr = d.K1p / 8;
     for (int p = threadIdx.x; p < TILE * ppr; p += 256) {
@@ -59,12 +65,16 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
         const int k = p % RS_N;
         rstate[p] = k == RS_M ? -__builtin_huge_valf() : (k == RS_ACT ? __int_as_float(0) : 0.f);
     }
+    for (int p = threadIdx.x; p < 2 * H + d.A1p; p += 256)
+        sbias[p] = p < H ? params[d.ob1 + p] : p < 2 * H ? params[d.ob2 + p - H] : (p - 2 * H < d.A1 ? params[d.ob3 + p - 2 * H] : 0.f);
 
     f32x4 acc[RT][H / 16];
-    dense_layer<RT, H>(acc, hbuf, HS, arow0, d.K1p, work + d.oW1f, (int64_t)H * 32, wbuf);
-    epilogue_relu<RT, H / 16>(acc, params + d.ob1, hbuf, HS, arow0);
-    dense_layer<RT, H>(acc, hbuf, HS, arow0, H, work + d.oW2f, (int64_t)H * 32, wbuf);
-    epilogue_relu<RT, H / 16>(acc, params + d.ob2, hbuf, HS, arow0);
+    dense_layer_pf<RT, H, H, T::DB>(acc, hbuf, HS, arow0, d.K1p, work + d.oW1f, (int64_t)H * 32, wbuf, true,
+                                    work + d.oW2f, ECON_Q8_ARGS);
+    epilogue_relu<RT, H / 16>(acc, sbias, hbuf, HS, arow0);
+    dense_layer_pf<RT, H, 128, T::DB>(acc, hbuf, HS, arow0, H, work + d.oW2f, (int64_t)H * 32, wbuf, true,
+                                      work + d.oW3f, ECON_Q8_ARGS);
+    epilogue_relu<RT, H / 16>(acc, sbias + H, hbuf, HS, arow0);
 
     // The logits are consumed in the MFMA accumulator layout: lane l owns rows
     // 4 (l / 16) + i of each 16-row tile, so the 16 lanes of a DPP row share
@@ -73,20 +83,21 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     const float NEG = -__builtin_huge_valf();
     for (int c = 0; c < d.NC; ++c) {
         f32x4 acc3[RT][8];
-        dense_layer<RT, 128>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32,
-                             wbuf);
+        const uint16_t* next = c + 1 < d.NC ? work + d.oW3f + (int64_t)(c + 1) * 128 * 32 : nullptr;
+        dense_layer_pf<RT, 128, 128, T::DB>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32,
+                                            (int64_t)d.A1p * 32, wbuf, true, next, ECON_Q8_ARGS);
         // uniforms of chunk c: lane j < RPW draws for the wave's row j
-        float u1L = 0.f, u2L = 0.f;
         if (l < RPW) {
             u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row0 + arow0 + l), ctr, (uint64_t)(c >> 1), 0);
-            u1L = unif24(word_of(w, 2 * (c & 1)));
-            u2L = unif24(word_of(w, 2 * (c & 1) + 1));
+            rstate[(arow0 + l) * RS_N + RS_U1] = unif24(word_of(w, 2 * (c & 1)));
+            rstate[(arow0 + l) * RS_N + RS_U2] = unif24(word_of(w, 2 * (c & 1) + 1));
         }
+        wave_lds_fence();
         float bcol[8];
 #pragma unroll
         for (int ct = 0; ct < 8; ++ct) {
             const int col = c * 128 + ct * 16 + (l & 15);
-            bcol[ct] = col < d.A1 ? params[d.ob3 + col] : 0.f;
+            bcol[ct] = sbias[2 * H + col];
         }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
@@ -94,7 +105,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
             for (int i = 0; i < 4; ++i) {
                 const int rw = rt * 16 + 4 * (l >> 4) + i;  // row within the wave
                 const int rloc = arow0 + rw;
-                const float u1 = __shfl(u1L, rw, 64), u2 = __shfl(u2L, rw, 64);
+                const float u1 = rstate[rloc * RS_N + RS_U1], u2 = rstate[rloc * RS_N + RS_U2];
                 float z[8];
                 bool ok[8];
                 float zval = 0.f, zmax = NEG;
@@ -112,15 +123,22 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
                 const float zv = row16_sum(zval);  // the value head sits right after the logits
                 const float mc = row16_max(zmax);
                 const bool any = mc != NEG;
-                float e[8], P[8], carry = 0.f, tl = 0.f;
+                // Walk order inside the chunk: lane-major (lane j's eight actions
+                // j, 16 + j, ..., 112 + j, then lane j + 1's): a lane-local prefix
+                // plus one 16-lane scan of the lane totals.
+                float e[8], P[8], own = 0.f, tl = 0.f;
 #pragma unroll
                 for (int ct = 0; ct < 8; ++ct) {
                     e[ct] = ok[ct] ? __expf(z[ct] - mc) : 0.f;
                     tl += ok[ct] ? e[ct] * (z[ct] - mc) : 0.f;
-                    P[ct] = carry + row16_scan(e[ct]);
-                    carry += row16_sum(e[ct]);
+                    own += e[ct];
+                    P[ct] = own;
                 }
-                const float Sc = carry;
+                const float incl = row16_scan(own);
+                const float before = incl - own;
+                const float Sc = row16_sum(own);
+#pragma unroll
+                for (int ct = 0; ct < 8; ++ct) P[ct] += before;
                 const float Tc = row16_sum(tl);
                 if (logits) {
                     const int64_t row = row0 + rloc;
@@ -140,19 +158,21 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
                 const bool take = any && u1 * Wn < Sc * fc;
                 // first allowed action whose cumulative weight exceeds u2 * Sc
                 const float target = u2 * Sc;
+                // position in the walk: (lane, ct) -> 8 lane + ct
                 int key = 1 << 20, last = -1;
 #pragma unroll
                 for (int ct = 7; ct >= 0; --ct) {
-                    if (ok[ct] && P[ct] > target) key = ct * 16 + (l & 15);
-                    if (ok[ct] && last < 0) last = ct * 16 + (l & 15);
+                    if (ok[ct] && P[ct] > target) key = 8 * (l & 15) + ct;
+                    if (ok[ct] && last < 0) last = 8 * (l & 15) + ct;
                 }
                 key = row16_min_i(key);
                 if (key == (1 << 20)) key = row16_max_i(last);  // rounding put the target at the top
                 float zk = 0.f;
 #pragma unroll
                 for (int ct = 0; ct < 8; ++ct)
-                    if (ct * 16 + (l & 15) == key) zk = z[ct];
+                    if (8 * (l & 15) + ct == key) zk = z[ct];
                 zk = row16_sum(zk);
+                key = (key & 7) * 16 + (key >> 3);  // walk position -> column in the chunk
                 if ((l & 15) == 0) {
                     st[RS_M] = mn;
                     st[RS_S] = Sn;
@@ -226,7 +246,8 @@ template <int H>
 size_t policy_lds_bytes(int W)
 {
     using T = MlpTile<H>;
-    return (size_t)T::TILE * T::HS * 2 + (size_t)T::WREG * 2 + (size_t)T::TILE * W * 4 + (size_t)T::TILE * RS_N * 4;
+    return (size_t)T::TILE * T::HS * 2 + (size_t)T::WBUF * 2 + (size_t)T::TILE * W * 4 + (size_t)T::TILE * RS_N * 4 +
+           (size_t)(2 * H + 1024) * 4;
 }
 
 template <int H>

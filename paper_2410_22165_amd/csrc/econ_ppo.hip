@@ -172,8 +172,8 @@ template <int H>
 size_t ppo_rows_lds_bytes(int W)
 {
     using T = MlpTile<H>;
-    return (size_t)T::TILE * T::HS * 2 + (size_t)T::TILE * PpoTile<H>::YS * 2 + (size_t)T::WREG * 2 +
-           (size_t)T::TILE * 6 * 4 + (size_t)T::TILE * W * 4 + 64 * 4;
+    return (size_t)T::TILE * T::HS * 2 + (size_t)T::TILE * PpoTile<H>::YS * 2 + (size_t)T::WBUF * 2 +
+           (size_t)T::TILE * 6 * 4 + (size_t)T::TILE * W * 4 + 64 * 4 + (size_t)(2 * H + 1024) * 4;
 }
 
 template <int H>
@@ -191,9 +191,10 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     uint16_t* hbuf = (uint16_t*)smem;
     uint16_t* ybuf = hbuf + TILE * HS;
     uint16_t* wbuf = ybuf + TILE * YS;
-    float* rinfo = (float*)(wbuf + T::WREG);  // [6][TILE]: act, logp_old, val_old, adv_hat, ret, valid
+    float* rinfo = (float*)(wbuf + T::WBUF);  // [6][TILE]: act, logp_old, val_old, adv_hat, ret, valid
     uint32_t* smask = (uint32_t*)(rinfo + 6 * TILE);
     float* lred = (float*)(smask + TILE * W);  // [4 waves][4]
+    float* sbias = lred + 64;                  // b1 [H], b2 [H], b3 [A1p] (zero padded)
 
     const int wave = threadIdx.x >> 6, l = lane_id();
     const int64_t tile_row0 = (int64_t)blockIdx.x * TILE;
@@ -223,6 +224,8 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         rinfo[4 * TILE + r] = rt;
         rinfo[5 * TILE + r] = valid;
     }
+    for (int p = threadIdx.x; p < 2 * H + d.A1p; p += 256)
+        sbias[p] = p < H ? params[d.ob1 + p] : p < 2 * H ? params[d.ob2 + p - H] : (p - 2 * H < d.A1 ? params[d.ob3 + p - 2 * H] : 0.f);
     const int ppr = d.K1p / 8;
     for (int p = threadIdx.x; p < TILE * ppr; p += 256) {
         const int r = p / ppr, cc = p - r * ppr;
@@ -247,10 +250,13 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
 
     f32x4 acc[RT][CT];
     uint32_t m1[RT][(CT + 7) / 8], m2[RT][(CT + 7) / 8];
-    dense_layer<RT, H>(acc, hbuf, HS, arow0, d.K1p, work + d.oW1f, (int64_t)H * 32, wbuf);
-    ppo_hidden_epilogue<RT, CT>(acc, params + d.ob1, hbuf, HS, arow0, Th1, tile_row0, m1);
-    dense_layer<RT, H>(acc, hbuf, HS, arow0, H, work + d.oW2f, (int64_t)H * 32, wbuf);
-    ppo_hidden_epilogue<RT, CT>(acc, params + d.ob2, hbuf, HS, arow0, Th2, tile_row0, m2);
+    ECON_Q8_DECL;
+    dense_layer_pf<RT, H, H, T::DB>(acc, hbuf, HS, arow0, d.K1p, work + d.oW1f, (int64_t)H * 32, wbuf, false, work + d.oW2f,
+                             ECON_Q8_ARGS);
+    ppo_hidden_epilogue<RT, CT>(acc, sbias, hbuf, HS, arow0, Th1, tile_row0, m1);
+    dense_layer_pf<RT, H, 128, T::DB>(acc, hbuf, HS, arow0, H, work + d.oW2f, (int64_t)H * 32, wbuf, true, work + d.oW3f,
+                               ECON_Q8_ARGS);
+    ppo_hidden_epilogue<RT, CT>(acc, sbias + H, hbuf, HS, arow0, Th2, tile_row0, m2);
 
     // ---- pass 1: statistics of the masked softmax, logit of the taken action, value
     const float NEG = -__builtin_huge_valf();
@@ -267,14 +273,12 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         }
     f32x4 acc3[RT][8];
     for (int c = 0; c < d.NC; ++c) {
-        dense_layer<RT, 128>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32,
-                             wbuf);
+        const uint16_t* next = c + 1 < d.NC ? work + d.oW3f + (int64_t)(c + 1) * 128 * 32 : nullptr;
+        dense_layer_pf<RT, 128, 128, T::DB>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32,
+                                     (int64_t)d.A1p * 32, wbuf, c == 0, next, ECON_Q8_ARGS);
         float bcol[8];
 #pragma unroll
-        for (int ct = 0; ct < 8; ++ct) {
-            const int col = c * 128 + ct * 16 + (l & 15);
-            bcol[ct] = col < d.A1 ? params[d.ob3 + col] : 0.f;
-        }
+        for (int ct = 0; ct < 8; ++ct) bcol[ct] = sbias[2 * H + c * 128 + ct * 16 + (l & 15)];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -369,14 +373,11 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     f32x4 dh[RT][CT];
     for (int c = 0; c < d.NC; ++c) {
         if (d.NC > 1)
-            dense_layer<RT, 128>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32,
-                                 wbuf);
+            dense_layer<RT, 128, T::DB>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32,
+                                        (int64_t)d.A1p * 32, wbuf);
         float bcol[8];
 #pragma unroll
-        for (int ct = 0; ct < 8; ++ct) {
-            const int col = c * 128 + ct * 16 + (l & 15);
-            bcol[ct] = col < d.A1 ? params[d.ob3 + col] : 0.f;
-        }
+        for (int ct = 0; ct < 8; ++ct) bcol[ct] = sbias[2 * H + c * 128 + ct * 16 + (l & 15)];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
             const int rloc0 = arow0 + rt * 16 + 4 * (l >> 4);
@@ -404,8 +405,8 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
                 store_mblock4(TdY, d.A1p, tile_row0 + rloc0, col, g);
             }
         }
-        dense_layer<RT, H>(dh, ybuf, YS, arow0, 128, work + d.oW3b + (int64_t)c * 4 * H * 32, (int64_t)H * 32, wbuf,
-                           c == 0);
+        dense_layer<RT, H, T::DB>(dh, ybuf, YS, arow0, 128, work + d.oW3b + (int64_t)c * 4 * H * 32, (int64_t)H * 32,
+                                  wbuf, c == 0);
     }
 
     // ---- dh2 = (dY W3^T) * [h2 > 0] -> LDS (A operand of the next product) and m-blocks
@@ -425,7 +426,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         }
     }
     // ---- dh1 = (dh2 W2^T) * [h1 > 0] -> m-blocks
-    dense_layer<RT, H>(dh, hbuf, HS, arow0, H, work + d.oW2b, (int64_t)H * 32, wbuf);
+    dense_layer<RT, H, T::DB>(dh, hbuf, HS, arow0, H, work + d.oW2b, (int64_t)H * 32, wbuf);
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
         const int col = ct * 16 + (l & 15);
@@ -470,32 +471,25 @@ dw_kernel(const uint16_t* __restrict__ Tx, int J, const uint16_t* __restrict__ T
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     float cs = 0.f;
-    constexpr int PX = CJ * 4, PY = CN * 4;  // 16-byte pieces per tile
-    uint4 rx[(PX + NTH - 1) / NTH], ry[(PY + NTH - 1) / NTH];
+    constexpr int PX = CJ * 4, PY = CN * 4;  // 16-byte pieces per tile (at most two per thread)
+    static_assert(PX <= 2 * NTH && PY <= 2 * NTH, "two prefetch registers per operand");
+    uint4 rx0, rx1, ry0, ry1;  // plain scalars: an array here lands in scratch memory
     auto load = [&](int64_t mb) {
-#pragma unroll
-        for (int k = 0; k < (PX + NTH - 1) / NTH; ++k) {
-            const int p = threadIdx.x + k * NTH;
-            if (p < PX) rx[k] = *(const uint4*)(Tx + (mb * J + j0 + (p >> 2)) * 32 + (p & 3) * 8);
-        }
-#pragma unroll
-        for (int k = 0; k < (PY + NTH - 1) / NTH; ++k) {
-            const int p = threadIdx.x + k * NTH;
-            if (p < PY) ry[k] = *(const uint4*)(Ty + (mb * N + n0 + (p >> 2)) * 32 + (p & 3) * 8);
-        }
+        const int p0 = threadIdx.x, p1 = threadIdx.x + NTH;
+        if (p0 < PX) rx0 = *(const uint4*)(Tx + (mb * J + j0 + (p0 >> 2)) * 32 + (p0 & 3) * 8);
+        if (p1 < PX) rx1 = *(const uint4*)(Tx + (mb * J + j0 + (p1 >> 2)) * 32 + (p1 & 3) * 8);
+        if (p0 < PY) ry0 = *(const uint4*)(Ty + (mb * N + n0 + (p0 >> 2)) * 32 + (p0 & 3) * 8);
+        if (p1 < PY) ry1 = *(const uint4*)(Ty + (mb * N + n0 + (p1 >> 2)) * 32 + (p1 & 3) * 8);
     };
     if (mb0 < mb1) load(mb0);
     for (int64_t mb = mb0; mb < mb1; ++mb) {
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < (PX + NTH - 1) / NTH; ++k) {
-            const int p = threadIdx.x + k * NTH;
-            if (p < PX) *(uint4*)(xs + (p >> 2) * WSTRIDE + (p & 3) * 8) = rx[k];
-        }
-#pragma unroll
-        for (int k = 0; k < (PY + NTH - 1) / NTH; ++k) {
-            const int p = threadIdx.x + k * NTH;
-            if (p < PY) *(uint4*)(ys + (p >> 2) * WSTRIDE + (p & 3) * 8) = ry[k];
+        {
+            const int p0 = threadIdx.x, p1 = threadIdx.x + NTH;
+            if (p0 < PX) *(uint4*)(xs + (p0 >> 2) * WSTRIDE + (p0 & 3) * 8) = rx0;
+            if (p1 < PX) *(uint4*)(xs + (p1 >> 2) * WSTRIDE + (p1 & 3) * 8) = rx1;
+            if (p0 < PY) *(uint4*)(ys + (p0 >> 2) * WSTRIDE + (p0 & 3) * 8) = ry0;
+            if (p1 < PY) *(uint4*)(ys + (p1 >> 2) * WSTRIDE + (p1 & 3) * 8) = ry1;
         }
         __syncthreads();
         if (mb + 1 < mb1) load(mb + 1);
