@@ -86,13 +86,55 @@ def cpu_baseline(cfg, weights, budget_s: float = 12.0):
                        f"(C economy step + float64 numpy policy and sampler), {dt:.1f} s, one thread")
 
 
+def ppo_benchmark(updates: int = 1):
+    """PPO samples/s on the 4096-economy x 100-agent workload (rollout of 128
+    steps as one captured graph + 4 epochs x 8 minibatches of the hand-written
+    backward and Adam): one warm-up update, then `updates` timed ones."""
+    import torch
+
+    from paper_2410_22165_amd.ppo import PPOTrainer
+
+    wl = W.workload(POLICY_WORKLOAD)
+    cfg = wl["env"]
+    tr = PPOTrainer(cfg, W.obs_scales(cfg), hidden=wl["hidden"], rollout=wl["rollout"], epochs=wl["epochs"],
+                    minibatches=wl["minibatches"], gamma=wl["gamma"], lam=wl["lam"], clip=wl["clip"],
+                    vf_coef=wl["vf_coef"], vclip=wl["vclip"], ent_coef=wl["ent_coef"], lr=wl["lr"], seed=0,
+                    total_updates=updates + 1)
+    tr.collect(graph=True)
+    tr.update()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_roll = t_upd = 0.0
+    for _ in range(updates):
+        ev[0].record(s)
+        tr.collect(graph=True)
+        ev[1].record(s)
+        tr.update()
+        ev[2].record(s)
+        torch.cuda.synchronize()
+        t_roll += ev[0].elapsed_time(ev[1])
+        t_upd += ev[1].elapsed_time(ev[2])
+    samples = tr.M_total * updates
+    terms = tr.loss_terms.cpu().numpy().tolist()
+    tr.close()
+    return {"value": round(samples / ((t_roll + t_upd) / 1e3), 1), "unit": "samples/s",
+            "update_only": round(samples / (t_upd / 1e3), 1), "rollout_ms": round(t_roll / updates, 3),
+            "update_ms": round(t_upd / updates, 3), "samples_per_update": tr.M_total,
+            "workload": f"{POLICY_WORKLOAD}: E={cfg['E']} N={cfg['N']} T={wl['rollout']} "
+                        f"{wl['epochs']}x{wl['minibatches']} minibatches, hidden {wl['hidden']}",
+            "last_loss_terms": [round(x, 5) for x in terms]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ppo", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--graph-steps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (one process, one MI355X)",
@@ -101,7 +143,7 @@ def main():
 
     import torch
 
-    from paper_2410_22165_amd import binding
+    from paper_2410_22165_amd import autotune, binding
 
     torch.cuda.set_device(0)
     wl = W.workload(WORKLOAD)
@@ -115,33 +157,58 @@ def main():
     dev = torch.device("cuda")
     act = torch.zeros(M, dtype=torch.int32, device=dev)
     logp, val, ent = (torch.zeros(M, device=dev) for _ in range(3))
+    ctr_base = torch.zeros(1, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
     env.observe(b["obs"], b["mask"])
 
     def policy(i):
-        mlp.forward(b["obs"], b["mask"], M, 1, i, act, logp, val, ent)
+        mlp.forward(b["obs"], b["mask"], M, 1, i, act, logp, val, ent, ctr_base=ctr_base)
 
-    def economy(i):
+    def economy():
         env.random_actions(2, None, b["gov"])
         env.step(act, b["gov"], b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
 
+    # launch shapes chosen by the autotuner (state restored afterwards)
+    tuned_env = autotune.tune_env(env, dict(b, act=act), use_cache=False)
+    tuned_pol = autotune.tune_policy(mlp, b["obs"], b["mask"], M, (act, logp, val, ent), use_cache=False)
+
     for i in range(args.warmup):
         policy(i)
-        economy(i)
+        economy()
     torch.cuda.synchronize()
 
-    # timed region: exactly K steps
+    # plain: one launch per kernel per step from the host
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
     for i in range(args.steps):
-        policy(args.warmup + i)
-        economy(args.warmup + i)
+        policy(i)
+        economy()
     stop.record(stream)
     torch.cuda.synchronize()
-    ms_total = start.elapsed_time(stop)
-    ms_step = ms_total / args.steps
-    value = M * args.steps / (ms_total / 1e3)
+    ms_plain = start.elapsed_time(stop) / args.steps
+
+    # graph: G steps captured once and replayed (the sampling counter lives on the device)
+    G = max(1, min(args.graph_steps, args.steps))
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for i in range(G):
+            policy(i)
+            economy()
+        binding.counter_add(ctr_base, G)
+    graph.replay()
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // G)
+    start.record(stream)
+    for _ in range(reps):
+        graph.replay()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = start.elapsed_time(stop) / (reps * G)
+    timed_steps = reps * G
+
+    ms_step = min(ms_plain, ms_graph)
+    value = M / (ms_step / 1e3)
 
     # per-kernel durations with HIP events on the launch stream
     n_k = min(args.steps, 100)
@@ -190,15 +257,25 @@ def main():
         "data": "synthetic (seed-generated economies; random-init policy weights)",
         "config": {"workload": WORKLOAD, "E": cfg["E"], "N": cfg["N"], "R": cfg["R"], "P": cfg["P"],
                    "X": cfg["X"], "P_tax": cfg["P_tax"], "K": cfg["K"], "T": cfg["T"],
-                   "policy": f"{D}->{H}->{H}->{A}+1", "parallelism": "one workgroup per economy"},
+                   "policy": f"{D}->{H}->{H}->{A}+1", "parallelism": "one workgroup per economy",
+                   "launch": f"hipGraph of {G} steps" if ms_graph <= ms_plain else "per-step launches",
+                   "env_launch": {"mode": tuned_env["mode"], "workgroups": tuned_env["workgroups"]},
+                   "policy_tile_rows": tuned_pol["tile_rows"]},
+        "x_vs_plain": round(ms_plain / ms_graph, 4),
+        "plain_ms_per_step": round(ms_plain, 5),
+        "graph_ms_per_step": round(ms_graph, 5),
+        "graph_timed_steps": timed_steps,
         "roofline": roofline,
         "kernels": {n: {kk: (round(v, 5) if isinstance(v, float) else v) for kk, v in d.items()}
                     for n, d in kernels.items()},
     }
+    env.close()
+    del graph
+    if not args.no_ppo:
+        out["ppo"] = ppo_benchmark()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, weights, args.cpu_budget)
         out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)
-    env.close()
     print(json.dumps(out), flush=True)
 
 

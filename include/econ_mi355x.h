@@ -152,6 +152,13 @@ int ej_env_reset(ej_env* env, int32_t episode, void* stream);
 int ej_env_step(ej_env* env, const int32_t* d_act, const int32_t* d_gov, float* d_rew, float* d_gov_rew,
                 uint8_t* d_done, uint16_t* d_obs, uint32_t* d_mask, void* stream);
 
+/* Launch shape of ej_env_step.  mode 0: one workgroup per economy (one
+ * launch per step).  mode 1: `workgroups` persistent workgroups (0: two per
+ * compute unit) take economies from a work queue, largest populations first;
+ * the queue resets itself at the end of every launch, so the call can be
+ * captured in a graph and replayed.  Results are identical in both modes. */
+int ej_env_set_launch(ej_env* env, int32_t mode, int32_t workgroups);
+
 /* Observation of the current state.  d_obs / d_mask as in ej_env_step (both
  * required); d_gov_obs [E * D_gov] float, nullable: per-feature mean, std and
  * lower median over the population of (coin, period income, labor, each
@@ -190,6 +197,8 @@ int ej_env_status(ej_env* env, int64_t* h_invalid_actions, int64_t* h_invalid_go
  * ------------------------------------------------------------------------ */
 typedef struct ej_mlp_desc {
     int32_t D, D_stride, H, A;
+    int32_t tile_rows; /* rows per workgroup of the policy forward: 0 (default: 128 for H <= 256,
+                          64 for H = 512), 64 or 128 (H <= 256); chosen by the autotuner */
 } ej_mlp_desc;
 
 typedef struct ej_mlp_layout_t {

@@ -45,7 +45,8 @@ class EjStateView(C.Structure):
 
 
 class EjMlpDesc(C.Structure):
-    _fields_ = [("D", C.c_int32), ("D_stride", C.c_int32), ("H", C.c_int32), ("A", C.c_int32)]
+    _fields_ = [("D", C.c_int32), ("D_stride", C.c_int32), ("H", C.c_int32), ("A", C.c_int32),
+                ("tile_rows", C.c_int32)]
 
 
 class EjMlpLayout(C.Structure):
@@ -92,6 +93,7 @@ def lib():
     L.ej_env_get_state.argtypes = [vp, C.POINTER(EjStateView), vp]
     L.ej_env_set_state.argtypes = [vp, C.POINTER(EjStateView), vp]
     L.ej_env_status.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), vp]
+    L.ej_env_set_launch.argtypes = [vp, i32, i32]
     _declare_learner(L)
     _lib = L
     return L
@@ -217,6 +219,10 @@ class Env:
         check(lib().ej_env_random_actions(self._h, act_seed, ptr(act), ptr(gov), stream_ptr(stream)),
               "ej_env_random_actions")
 
+    def set_launch(self, mode: int, workgroups: int = 0):
+        """mode 0: one workgroup per economy; 1: persistent work queue."""
+        check(lib().ej_env_set_launch(self._h, mode, workgroups), "ej_env_set_launch")
+
     def status(self, stream=None):
         a, g = C.c_int64(), C.c_int64()
         check(lib().ej_env_status(self._h, C.byref(a), C.byref(g), stream_ptr(stream)), "ej_env_status")
@@ -265,9 +271,9 @@ class Mlp:
     """Shared policy network parameters on the GPU: the flat fp32 vector and
     its bf16 work copy (both torch tensors; the kernels own the layouts)."""
 
-    def __init__(self, D: int, D_stride: int, H: int, A: int, weights: dict | None = None):
+    def __init__(self, D: int, D_stride: int, H: int, A: int, weights: dict | None = None, tile_rows: int = 0):
         import torch
-        self.desc = EjMlpDesc(D, D_stride, H, A)
+        self.desc = EjMlpDesc(D, D_stride, H, A, tile_rows)
         lay = EjMlpLayout()
         check(lib().ej_mlp_layout(C.byref(self.desc), C.byref(lay)), "ej_mlp_layout")
         self.layout = {n: int(getattr(lay, n)) for n, _ in EjMlpLayout._fields_}
@@ -294,6 +300,10 @@ class Mlp:
         import torch
         self.params.copy_(torch.from_numpy(self.flat(weights)))
         self.sync(stream)
+
+    def set_tile_rows(self, rows: int):
+        """Row tile of the policy forward (0: default, 64 or 128)."""
+        self.desc.tile_rows = rows
 
     def sync(self, stream=None):
         check(lib().ej_mlp_sync_weights(C.byref(self.desc), ptr(self.params), ptr(self.work), stream_ptr(stream)),

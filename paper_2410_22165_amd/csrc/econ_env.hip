@@ -56,6 +56,9 @@ struct EnvState {
     const int32_t* env_row;  // [E+1] first row of the economy
     int64_t* invalid;        // [E][2] rejected population actions / government levels
     double* ug;              // [E]   social welfare of the current state (NaN: not known)
+    unsigned int* queue;     // [2]   persistent launch: next queue slot, finished workgroups
+    const int32_t* order;    // [E]   persistent launch: economies by decreasing population
+    int32_t E;
 };
 
 // state field indices
@@ -582,13 +585,12 @@ __device__ inline void write_mask_row(const EnvParams& P, const Lds& L, const Ag
 // the step kernel: one workgroup per economy
 // ---------------------------------------------------------------------------
 template <int RM, int XM, int APT>
-__global__ void __launch_bounds__(1024 / APT)
-env_step_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__ act,
-                const int32_t* __restrict__ gov, float* __restrict__ rew, float* __restrict__ gov_rew,
-                uint8_t* __restrict__ done_out, uint16_t* __restrict__ obs, uint32_t* __restrict__ mask)
+__device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState& S, const int e,
+                                             const int32_t* __restrict__ act, const int32_t* __restrict__ gov,
+                                             float* __restrict__ rew, float* __restrict__ gov_rew,
+                                             uint8_t* __restrict__ done_out, uint16_t* __restrict__ obs,
+                                             uint32_t* __restrict__ mask, unsigned char* smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int e = blockIdx.x;
     const int NT = blockDim.x, tid = threadIdx.x;
     const int NL = NT * APT;
     Lds L;
@@ -961,6 +963,48 @@ env_step_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__
     }
 }
 
+// plain launch: one workgroup per economy
+template <int RM, int XM, int APT>
+__global__ void __launch_bounds__(1024 / APT)
+env_step_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__ act,
+                const int32_t* __restrict__ gov, float* __restrict__ rew, float* __restrict__ gov_rew,
+                uint8_t* __restrict__ done_out, uint16_t* __restrict__ obs, uint32_t* __restrict__ mask)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    env_step_one<RM, XM, APT>(P, S, blockIdx.x, act, gov, rew, gov_rew, done_out, obs, mask, smem);
+}
+
+// Persistent launch: a fixed set of workgroups takes economies from a work
+// queue (largest populations first).  The last workgroup to run dry resets
+// the queue, so consecutive launches (and replays of a captured graph) need
+// no host-side reset.
+template <int RM, int XM, int APT>
+__global__ void __launch_bounds__(1024 / APT)
+env_step_persistent_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__ act,
+                           const int32_t* __restrict__ gov, float* __restrict__ rew, float* __restrict__ gov_rew,
+                           uint8_t* __restrict__ done_out, uint16_t* __restrict__ obs,
+                           uint32_t* __restrict__ mask)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_slot;
+    for (;;) {
+        __syncthreads();  // everyone has read the previous slot
+        if (threadIdx.x == 0) s_slot = (int)atomicAdd(&S.queue[0], 1u);
+        __syncthreads();
+        const int k = s_slot;
+        if (k >= S.E) break;
+        env_step_one<RM, XM, APT>(P, S, S.order[k], act, gov, rew, gov_rew, done_out, obs, mask, smem);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned int finished = atomicAdd(&S.queue[1], 1u);
+        if (finished + 1 == gridDim.x) {  // every workgroup has drained the queue
+            atomicExch(&S.queue[0], 0u);
+            atomicExch(&S.queue[1], 0u);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // observation of the current state (population rows, masks, government)
 // ---------------------------------------------------------------------------
@@ -1118,10 +1162,13 @@ struct ej_env {
     int32_t* d_row = nullptr;
     int64_t* d_invalid = nullptr;
     double* d_ug = nullptr;
+    unsigned int* d_queue = nullptr;
+    int32_t* d_order = nullptr;
+    int mode = 0, persistent_wg = 0;  // mode 0: one workgroup per economy; 1: persistent work queue
     size_t lds = 0;
     EnvState state() const
     {
-        return EnvState{d_field, d_t, d_ep, d_rates, d_n, d_off, d_row, d_invalid, d_ug};
+        return EnvState{d_field, d_t, d_ep, d_rates, d_n, d_off, d_row, d_invalid, d_ug, d_queue, d_order, E};
     }
 };
 
@@ -1244,7 +1291,8 @@ int ej_env_create(const ej_env_config* cfg, const int32_t* h_n_per_env, ej_env**
               hipMalloc(&h->d_n, 4 * (size_t)h->E) == hipSuccess && hipMalloc(&h->d_off, 4 * (size_t)h->E) == hipSuccess &&
               hipMalloc(&h->d_row, 4 * (size_t)(h->E + 1)) == hipSuccess &&
               hipMalloc(&h->d_invalid, 16 * (size_t)h->E) == hipSuccess &&
-              hipMalloc(&h->d_ug, 8 * (size_t)h->E) == hipSuccess;
+              hipMalloc(&h->d_ug, 8 * (size_t)h->E) == hipSuccess &&
+              hipMalloc(&h->d_queue, 8) == hipSuccess && hipMalloc(&h->d_order, 4 * (size_t)h->E) == hipSuccess;
     if (!ok) {
         ej_env_destroy(h);
         return EJ_ENOMEM;
@@ -1252,11 +1300,22 @@ int ej_env_create(const ej_env_config* cfg, const int32_t* h_n_per_env, ej_env**
     if (hipMemcpy(h->d_n, h->n.data(), 4 * (size_t)h->E, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->d_off, h->off.data(), 4 * (size_t)h->E, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->d_row, h->row.data(), 4 * (size_t)(h->E + 1), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(h->d_invalid, 0, 16 * (size_t)h->E) != hipSuccess ||
+        hipMemset(h->d_invalid, 0, 16 * (size_t)h->E) != hipSuccess || hipMemset(h->d_queue, 0, 8) != hipSuccess ||
         hipMemset(h->d_field, 0, nf * (size_t)slots * 4) != hipSuccess) {
         set_last_hip_error(hipGetLastError());
         ej_env_destroy(h);
         return EJ_EHIP;
+    }
+    {
+        // persistent-launch order: largest populations first (stable by index)
+        std::vector<int32_t> order(h->E);
+        for (int e = 0; e < h->E; ++e) order[e] = e;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h->n[a] > h->n[b]; });
+        if (hipMemcpy(h->d_order, order.data(), 4 * (size_t)h->E, hipMemcpyHostToDevice) != hipSuccess) {
+            set_last_hip_error(hipGetLastError());
+            ej_env_destroy(h);
+            return EJ_EHIP;
+        }
     }
     rc = ej_env_reset(h, 0, nullptr);
     if (rc == EJ_OK && hipDeviceSynchronize() != hipSuccess) rc = EJ_EHIP;
@@ -1280,6 +1339,8 @@ int ej_env_destroy(ej_env* h)
     (void)hipFree(h->d_row);
     (void)hipFree(h->d_invalid);
     (void)hipFree(h->d_ug);
+    (void)hipFree(h->d_queue);
+    (void)hipFree(h->d_order);
     delete h;
     return EJ_OK;
 }
@@ -1316,8 +1377,33 @@ int ej_env_step(ej_env* h, const int32_t* d_act, const int32_t* d_gov, float* d_
     if (h->P.K > 0 && !d_gov) return EJ_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     EnvState S = h->state();
-    EJ_DISPATCH(h, env_step_kernel, h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs, d_mask);
+    if (h->mode == 1) {
+        const unsigned G = (unsigned)h->persistent_wg;
+        if (h->variant == 0)
+            env_step_persistent_kernel<4, 16, 1><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew,
+                                                                         d_done, d_obs, d_mask);
+        else
+            env_step_persistent_kernel<8, 32, 1><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew,
+                                                                         d_done, d_obs, d_mask);
+    } else {
+        EJ_DISPATCH(h, env_step_kernel, h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs, d_mask);
+    }
     EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+int ej_env_set_launch(ej_env* h, int32_t mode, int32_t workgroups)
+{
+    if (!h || mode < 0 || mode > 1 || workgroups < 0) return EJ_EINVAL;
+    if (mode == 1) {
+        int dev = 0, cus = 0;
+        EJ_HIP(hipGetDevice(&dev));
+        EJ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        int g = workgroups > 0 ? workgroups : 2 * cus;
+        if (g > h->E) g = h->E;
+        h->persistent_wg = g;
+    }
+    h->mode = mode;
     return EJ_OK;
 }
 

@@ -223,14 +223,18 @@ __device__ inline void wave_lds_fence()
 // uniform in (0, 1) from the top 24 bits of a word: (top + 1/2) / 2^24
 __device__ inline float unif24(uint64_t w) { return ((float)(uint32_t)(w >> 40) + 0.5f) * (1.0f / 16777216.0f); }
 
-template <int H>
+// Row tile of the MLP kernels: RPW_ rows per wave, four waves.  128-row tiles
+// (H <= 256) reuse every weight fragment for two 16-row MFMA tiles and
+// double-buffer the weight chunks (one workgroup per CU); 64-row tiles halve
+// the LDS footprint so that two workgroups share a CU.
+template <int H, int RPW_ = (H <= 256 ? 32 : 16)>
 struct MlpTile {
-    static constexpr int RPW = H <= 256 ? 32 : 16;  // rows per wave
+    static constexpr int RPW = RPW_;                 // rows per wave
     static constexpr int RT = RPW / 16;
     static constexpr int TILE = 4 * RPW;             // rows per workgroup
     static constexpr int HS = H + 8;                 // LDS row stride of activations
     static constexpr int WREG = (H > 128 ? H : 128) * WSTRIDE;  // weight chunk elements
-    static constexpr bool DB = H <= 256;             // double-buffered weight chunks fit in LDS
+    static constexpr bool DB = H <= 256 && RPW == 32;  // double-buffered weight chunks fit in LDS
     static constexpr int WBUF = DB ? 2 * WREG : WREG;
 };
 

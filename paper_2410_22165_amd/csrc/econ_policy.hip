@@ -24,7 +24,7 @@ namespace econ {
 // per-row running state of the online softmax (LDS, RS_N floats per row)
 enum { RS_M = 0, RS_S, RS_T, RS_W, RS_ACT, RS_Z, RS_VAL, RS_U1, RS_U2, RS_N };
 
-template <int H>
+template <int H, int RPW_>
 __global__ void __launch_bounds__(256)
 policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
                       const uint16_t* __restrict__ obs, const uint32_t* __restrict__ mask, int64_t M, int W,
@@ -33,7 +33,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
                       float* __restrict__ ent, float* __restrict__ logits)
 {
     const uint64_t ctr = ctr_arg + (ctr_base ? *ctr_base : 0ull);
-    using T = MlpTile<H>;
+    using T = MlpTile<H, RPW_>;
     constexpr int RT = T::RT, RPW = T::RPW, TILE = T::TILE, HS = T::HS;
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* hbuf = (uint16_t*)smem;
@@ -242,23 +242,23 @@ __global__ void mlp_sync_kernel(const MlpDims d, const float* __restrict__ p, ui
     }
 }
 
-template <int H>
+template <int H, int RPW>
 size_t policy_lds_bytes(int W)
 {
-    using T = MlpTile<H>;
+    using T = MlpTile<H, RPW>;
     return (size_t)T::TILE * T::HS * 2 + (size_t)T::WBUF * 2 + (size_t)T::TILE * W * 4 + (size_t)T::TILE * RS_N * 4 +
            (size_t)(2 * H + 1024) * 4;
 }
 
-template <int H>
+template <int H, int RPW>
 int launch_policy_forward(const MlpDims& d, const float* params, const uint16_t* work, const uint16_t* obs,
                           const uint32_t* mask, int64_t M, int W, uint64_t seed, uint64_t ctr, const uint64_t* ctr_base,
                           int32_t* act, float* logp, float* val, float* ent, float* logits, hipStream_t st)
 {
-    using T = MlpTile<H>;
+    using T = MlpTile<H, RPW>;
     const int64_t blocks = (M + T::TILE - 1) / T::TILE;
-    const size_t lds = policy_lds_bytes<H>(W);
-    policy_forward_kernel<H><<<(unsigned)blocks, 256, lds, st>>>(d, params, work, obs, mask, M, W, seed, ctr, ctr_base,
+    const size_t lds = policy_lds_bytes<H, RPW>(W);
+    policy_forward_kernel<H, RPW><<<(unsigned)blocks, 256, lds, st>>>(d, params, work, obs, mask, M, W, seed, ctr, ctr_base,
                                                                   act, logp, val, ent, logits);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
@@ -271,6 +271,7 @@ using namespace econ;
 static int desc_dims(const ej_mlp_desc* m, MlpDims* d)
 {
     if (!m) return EJ_EINVAL;
+    if (m->tile_rows != 0 && m->tile_rows != 64 && !(m->tile_rows == 128 && m->H <= 256)) return EJ_EUNSUPPORTED;
     return mlp_dims(m->D, m->D_stride, m->H, m->A, d);
 }
 
@@ -330,12 +331,17 @@ int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_
     if (M == 0) return EJ_OK;
     const int W = (m->A + 31) / 32;
     hipStream_t st = (hipStream_t)stream;
+    const bool small = m->tile_rows == 64 || m->H == 512;
+#define EJ_POLICY(HH, RR) \
+    launch_policy_forward<HH, RR>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_ctr_base, d_act, d_logp, d_val, \
+                                  d_ent, d_logits, st)
     switch (m->H) {
-    case 64: return launch_policy_forward<64>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_ctr_base, d_act, d_logp, d_val, d_ent, d_logits, st);
-    case 128: return launch_policy_forward<128>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_ctr_base, d_act, d_logp, d_val, d_ent, d_logits, st);
-    case 256: return launch_policy_forward<256>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_ctr_base, d_act, d_logp, d_val, d_ent, d_logits, st);
-    default: return launch_policy_forward<512>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_ctr_base, d_act, d_logp, d_val, d_ent, d_logits, st);
+    case 64: return small ? EJ_POLICY(64, 16) : EJ_POLICY(64, 32);
+    case 128: return small ? EJ_POLICY(128, 16) : EJ_POLICY(128, 32);
+    case 256: return small ? EJ_POLICY(256, 16) : EJ_POLICY(256, 32);
+    default: return EJ_POLICY(512, 16);
     }
+#undef EJ_POLICY
 }
 
 }  // extern "C"

@@ -95,27 +95,48 @@ class PPOTrainer:
         self.mb_rows = self.M_total // minibatches
         self.workspace = torch.zeros(binding.ppo_workspace_bytes(self.mlp, self.mb_rows), dtype=torch.uint8,
                                      device="cuda")
-        self.step_ctr = 0
+        # sampling counter on the device: a step's uniforms use (base + t); the
+        # base moves by T + 1 after each rollout, so a replayed graph draws fresh ones
+        self.ctr_base = torch.zeros(1, dtype=torch.int64, device="cuda")
         self.updates = 0
         self.adam_step = 0
+        self.graph = None
         self.env.observe(self.store.obs[0], self.store.mask[0])
 
     # ---- rollout ----
     def rollout_step(self, t: int):
         s = self.store
-        self.mlp.forward(s.obs[t], s.mask[t], self.M, self.seed, self.step_ctr, s.act[t], s.logp[t], s.val[t],
-                         s.ent[t])
+        self.mlp.forward(s.obs[t], s.mask[t], self.M, self.seed, t, s.act[t], s.logp[t], s.val[t], s.ent[t],
+                         ctr_base=self.ctr_base)
         self.env.random_actions(self.seed + 1, None, self.gov)
         self.env.step(s.act[t], self.gov, s.rew[t], self.gov_rew, s.done[t], s.obs[t + 1], s.mask[t + 1])
-        self.step_ctr += 1
 
-    def collect(self):
+    def _collect_launches(self):
         for t in range(self.T):
             self.rollout_step(t)
         s = self.store
-        self.mlp.forward(s.obs[self.T], s.mask[self.T], self.M, self.seed, self.step_ctr, s.scratch_act,
-                         s.scratch[0], s.last_val, s.scratch[1])
+        self.mlp.forward(s.obs[self.T], s.mask[self.T], self.M, self.seed, self.T, s.scratch_act, s.scratch[0],
+                         s.last_val, s.scratch[1], ctr_base=self.ctr_base)
         binding.gae(s.rew, s.val, s.done, s.last_val, self.T, self.M, self.gamma, self.lam, s.adv, s.ret)
+        binding.counter_add(self.ctr_base, self.T + 1)
+
+    def collect(self, graph: bool = False):
+        """One rollout of T steps, then GAE.  graph=True replays the whole
+        rollout as one captured HIP graph (captured on first use; the kernels
+        must have run once before, so the first call with graph=True runs the
+        plain launches and captures afterwards)."""
+        if not graph:
+            self._collect_launches()
+            return
+        if self.graph is None:
+            self._collect_launches()
+            torch.cuda.synchronize()
+            # record the rollout for the following calls (capture executes nothing)
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph):
+                self._collect_launches()
+        else:
+            self.graph.replay()
 
     # ---- update ----
     def schedules(self):
@@ -138,7 +159,10 @@ class PPOTrainer:
                 binding.adam(self.mlp.params, self.grads, self.adam_m, self.adam_v, self.adam_step, max(lr, 1e-12))
                 self.mlp.sync()
         self.updates += 1
-        # the next rollout starts from the state after this one
+        self.next_rollout()
+
+    def next_rollout(self):
+        """The next rollout starts from the state after this one."""
         self.store.obs[0].copy_(self.store.obs[self.T])
         self.store.mask[0].copy_(self.store.mask[self.T])
 

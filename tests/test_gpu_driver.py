@@ -81,3 +81,46 @@ def test_update_lowers_the_minibatch_loss():
     tr.collect()
     torch.cuda.synchronize()
     tr.close()
+
+
+def test_graph_rollout_equals_plain_launches():
+    """The rollout replayed as a captured HIP graph produces exactly the
+    storage of the plain per-step launches (same seeds, same counters)."""
+    import torch
+    a = small_trainer()
+    b = small_trainer()
+    for k in range(3):
+        a.collect(graph=False)
+        b.collect(graph=True)
+        torch.cuda.synchronize()
+        for name in ("obs", "mask", "act", "logp", "val", "rew", "done", "adv", "ret"):
+            assert torch.equal(getattr(a.store, name), getattr(b.store, name)), (k, name)
+        a.next_rollout()
+        b.next_rollout()
+    a.close()
+    b.close()
+
+
+def test_persistent_launch_equals_plain_launch():
+    """The persistent work-queue launch of the economy step (uneven
+    populations) gives the same state, rewards and observations as one
+    workgroup per economy, and survives back-to-back launches."""
+    import torch
+    from paper_2410_22165_amd import binding
+    cfg = W.env_config(E=37, N=300, R=3, P=20, X=10, P_tax=20, K=7, T=60, seed=2)
+    ns = W.uneven_populations(37, 10, 300, seed=4)
+    envs = [binding.Env(cfg, W.obs_scales(cfg), ns) for _ in range(2)]
+    envs[1].set_launch(1, 8)
+    bufs = [e.buffers() for e in envs]
+    for step in range(70):
+        for e, b in zip(envs, bufs):
+            e.random_actions(9, b["act"], b["gov"])
+            e.step(b["act"], b["gov"], b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
+        torch.cuda.synchronize()
+        for k in ("rew", "gov_rew", "done", "obs", "mask"):
+            assert torch.equal(bufs[0][k], bufs[1][k]), (step, k)
+    s0, s1 = envs[0].get_state(), envs[1].get_state()
+    for k in s0:
+        assert np.array_equal(s0[k], s1[k]), k
+    for e in envs:
+        e.close()

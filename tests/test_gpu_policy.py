@@ -131,3 +131,21 @@ def test_sampler_multi_chunk_distribution():
         frac = ((a >= 128 * c) & (a < 128 * (c + 1))).mean()
         pc = p[128 * c:128 * (c + 1)].sum()
         assert abs(frac - pc) < 5 * np.sqrt(pc * (1 - pc) / M) + 1e-3, (c, frac, pc)
+
+
+def test_row_tile_variants_are_bit_identical():
+    """64-row and 128-row tiles compute every row with the same k order:
+    actions, log-probabilities, values and entropies agree bit for bit."""
+    import torch
+    from paper_2410_22165_amd import binding
+    D, Ds, H, A, M = 35, 40, 256, 125, 777
+    w = W.policy_weights(D, H, A, seed=8)
+    outs = []
+    for rows in (128, 64):
+        mlp = binding.Mlp(D, Ds, H, A, w, tile_rows=rows)
+        o = [torch.zeros(M, dtype=torch.int32, device="cuda")] + [torch.zeros(M, device="cuda") for _ in range(3)]
+        mlp.forward(torch.from_numpy(W.synthetic_obs(M, D, Ds, 8).view(np.int16)).cuda(),
+                    torch.from_numpy(W.synthetic_masks(M, A, 8).view(np.int32)).cuda(), M, 3, 4, *o)
+        outs.append([t.cpu() for t in o])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
