@@ -46,6 +46,9 @@ struct EnvParams {
     ej_obs_scales sc;
 };
 
+// longest observation row (bf16 features, padded to a multiple of 8)
+constexpr int EJ_MAX_DS = 8 * ((7 + 7 * EJ_MAX_R + EJ_MAX_K + 7) / 8);
+
 struct EnvState {
     int32_t* field;          // [NF][Ntot]
     int32_t* env_t;          // [E]
@@ -311,12 +314,14 @@ __device__ inline void seg_exclusive_scan(const int32_t* src, int32_t* dst, int 
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = lane_id();
     for (int s = w; s < nseg; s += nw) {
         int32_t carry = 0;
+        int32_t v = lane < len ? src[s * len + lane] : 0;
         for (int c = 0; c < len; c += 64) {
-            int j = c + lane;
-            int32_t v = j < len ? src[s * len + j] : 0;
-            int32_t inc = wave_scan_i(v);
+            const int j = c + lane;
+            const int32_t vn = j + 64 < len ? src[s * len + j + 64] : 0;  // next chunk in flight
+            const int32_t inc = wave_scan_i(v);
             if (j < len) dst[s * len + j] = carry + inc - v;
             carry += __builtin_amdgcn_readlane(inc, 63);
+            v = vn;
         }
     }
 }
@@ -359,6 +364,7 @@ struct Lds {
     uint32_t* nkey;                  // [NL] new-order tie key
     int64_t* sortbuf;                // [S2]
     int32_t *prices, *cutoffs, *rates, *kr, *mstat, *misc;
+    uint32_t* tmpl;                  // [EJ_MAX_DS / 2] economy-wide words of an observation row
     int64_t* red;                    // [32]
     double* dred;                    // [4]
 };
@@ -385,7 +391,8 @@ __host__ __device__ __forceinline__ size_t lds_layout(const EnvParams& P, int NL
     const size_t o_kr = align16(o_rates + 4 * EJ_MAX_K);
     const size_t o_mstat = align16(o_kr + 4 * EJ_MAX_R);
     const size_t o_misc = align16(o_mstat + 16 * EJ_MAX_R);
-    const size_t o_red = align16(o_misc + 4 * 16);
+    const size_t o_tmpl = align16(o_misc + 4 * 16);
+    const size_t o_red = align16(o_tmpl + 2 * EJ_MAX_DS);
     const size_t o_dred = align16(o_red + 8 * 32);
     const size_t total = align16(o_dred + 8 * 4);
     if (base) {
@@ -404,6 +411,7 @@ __host__ __device__ __forceinline__ size_t lds_layout(const EnvParams& P, int NL
         L->kr = (int32_t*)(base + o_kr);
         L->mstat = (int32_t*)(base + o_mstat);
         L->misc = (int32_t*)(base + o_misc);
+        L->tmpl = (uint32_t*)(base + o_tmpl);
         L->red = (int64_t*)(base + o_red);
         L->dred = (double*)(base + o_dred);
     }
@@ -421,16 +429,30 @@ __device__ inline int bucket_pos(const EnvParams& P, int side, int p, int age)
 // then the social welfare.  Small economies take each value's rank by
 // counting (ties ordered by index: any order of equal values gives the same
 // sum); larger ones sort in LDS.
+// sort-buffer entry of agent li holding coin C: unique keys while the
+// welfare ranks by counting (n <= 256), the plain value for the sort
+__device__ inline int64_t welfare_key(int64_t C, int li, int n) { return n <= 256 ? C * 256 + li : C; }
+
 __device__ inline double social_welfare_block(const EnvParams& P, const Lds& L, int n, int S2)
 {
     int64_t num = 0, sum = 0;
     if (n <= 256) {
+        // The buffer holds unique keys 256 C + agent (welfare_key), so a
+        // value's rank in the sorted order (ties by agent) is the number of
+        // smaller keys.  Entries n.. hold INT64_MAX, so the count runs over
+        // whole groups of 8 (S2 >= that).
+        const int n8 = (n + 7) & ~7;
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const int64_t x = L.sortbuf[i];
+            const int64_t key = L.sortbuf[i];
+            const int64_t x = key >> 8;
             int rank = 0;
-            for (int j = 0; j < n; ++j) {
-                const int64_t y = L.sortbuf[j];
-                rank += (y < x) || (y == x && j < i);
+#pragma unroll 2
+            for (int j = 0; j < n8; j += 8) {
+                int64_t y[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) y[q] = L.sortbuf[j + q];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) rank += y[q] < key;
             }
             num += (int64_t)(2 * rank - n + 1) * x;
             sum += x;
@@ -549,6 +571,62 @@ __device__ inline uint32_t range_bits(int wd, int lo, int hi)
     return hi_mask & ~((1u << a) - 1u);
 }
 
+// Features 0 .. 6 + 3R - 1 of an observation row belong to the agent; the
+// rest (tax rates, phase, market statistics, zero padding) are the same for
+// every agent of the economy.
+__host__ __device__ inline int obs_own_features(int R) { return 6 + 3 * R; }
+
+// bf16 bits of row feature f >= obs_own_features(R)
+__device__ inline uint32_t obs_shared_bits(const EnvParams& P, const Lds& L, int f, int t)
+{
+    const ej_obs_scales& s = P.sc;
+    const int q = f - obs_own_features(P.R);
+    float v;
+    if (q < P.K) {
+        v = (float)L.rates[q] * s.rate;
+    } else if (q == P.K) {
+        v = (float)(t % P.P_tax) * s.phase;
+    } else if (q < P.K + 1 + 4 * P.R) {
+        const int m = q - P.K - 1;
+        v = (float)L.mstat[m] * ((m & 3) < 2 ? s.price : s.count);
+    } else {
+        return 0u;
+    }
+    return f32_to_bf16(v);
+}
+
+// 32-bit word c of a row that holds no agent feature
+__device__ inline uint32_t obs_shared_word(const EnvParams& P, const Lds& L, int c, int t)
+{
+    return obs_shared_bits(P, L, 2 * c, t) | (obs_shared_bits(P, L, 2 * c + 1, t) << 16);
+}
+
+// the words of a row that hold the agent's own features (the last one may
+// also hold the first economy-wide feature)
+template <int RM, int XM>
+__device__ inline void write_obs_own_words(const EnvParams& P, const Lds& L, const Agent<RM, XM>& ag, int t,
+                                           uint32_t* row)
+{
+    const ej_obs_scales& s = P.sc;
+    RowWriter w{row, 0u, 0};
+    w.put((float)ag.coin_inv * s.coin);
+    w.put((float)ag.coin_esc * s.coin);
+    w.put((float)ag.labor * s.labor);
+    w.put((float)n_active(ag, P.X) * s.orders);
+    w.put((float)(ag.coin_inv + ag.coin_esc - ag.snap) * s.coin);
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+        if (r < P.R) w.put((float)ag.res_inv[r] * s.res);
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+        if (r < P.R) w.put((float)ag.res_esc[r] * s.res);
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+        if (r < P.R) w.put((float)ag.sg[r] * s.skill);
+    w.put((float)ag.sc * s.skill);
+    if (w.d & 1) row[w.d >> 1] = w.pend | (obs_shared_bits(P, L, w.d, t) << 16);
+}
+
 template <int RM, int XM>
 __device__ inline void write_mask_row(const EnvParams& P, const Lds& L, const Agent<RM, XM>& ag, uint32_t* row)
 {
@@ -638,7 +716,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             load_agent(P, S, off + li, ag[k]);
             const int64_t C = (int64_t)ag[k].coin_inv + ag[k].coin_esc;
             u0[k] = utility(C, ag[k].labor, P.eta);
-            L.sortbuf[li] = C;
+            L.sortbuf[li] = welfare_key(C, li, n);
             const int a = act[row0 + li];
             if (action_allowed(P, ag[k], n_active(ag[k], X), a, L.prices)) eff[k] = a;
             else ++invalid;
@@ -690,47 +768,50 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
                 radd(a.res_esc, d.r, 1);
             }
             a.labor += P.labor_trade;
-            L.ncode[li] = (side * R + d.r) * P.P + d.p;
+            const int code = (side * R + d.r) * P.P + d.p;
+            L.ncode[li] = code;
             L.nkey[li] = (uint32_t)(w.y >> 32);
+            my_rank[k] = atomicAdd(&L.nbcnt[code], 1);  // arrival position, ranked below
         }
-    }
-    __syncthreads();
-
-    // placement rank of each new order among this step's orders of the same
-    // (side, r, p): by tie key, then agent id
-#pragma unroll
-    for (int k = 0; k < APT; ++k) {
-        const int li = tid + k * NT;
-        if (li >= n) continue;
-        const int code = L.ncode[li];
-        if (code < 0) continue;
-        const uint32_t key = L.nkey[li];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            int cj = L.ncode[j];
-            if (cj == code) {
-                uint32_t kj = L.nkey[j];
-                rank += (kj < key) || (kj == key && j < li);
-            }
-        }
-        my_rank[k] = rank;
-        atomicAdd(&L.nbcnt[code], 1);
-        Act d = decode_action(P, eff[k]);
-#pragma unroll
-        for (int s = 0; s < XM; ++s)
-            if (s == slot_new) ag[k].slot[s] = slot_pack(d.type == 4, d.r, d.p, rank);
     }
     __syncthreads();
     seg_exclusive_scan(L.nbcnt, L.nboff, 1, 2 * R * P.P);
     __syncthreads();
+    // this step's orders listed per (side, r, p) in arrival order; the
+    // welfare sort buffer is free until the rewards
+    int32_t* ntmp = (int32_t*)L.sortbuf;
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        if (li < n && L.ncode[li] >= 0) ntmp[L.nboff[L.ncode[li]] + my_rank[k]] = li;
+    }
+    __syncthreads();
 
-    // new-order table and the bucket histogram of every live order
+    // placement rank of each new order within its (side, r, p) list: by tie
+    // key, then agent id; the new-order table lists the orders by rank.  Then
+    // the bucket histogram of every live order.
     const int tX = t % X;
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
         const int li = tid + k * NT;
         if (li >= n) continue;
-        if (L.ncode[li] >= 0) L.ntab[L.nboff[L.ncode[li]] + my_rank[k]] = li;
+        const int code = L.ncode[li];
+        if (code >= 0) {
+            const uint32_t key = L.nkey[li];
+            const int base = L.nboff[code], cnt = L.nbcnt[code];
+            int rank = 0;
+            for (int q = 0; q < cnt; ++q) {
+                const int j = ntmp[base + q];
+                const uint32_t kj = L.nkey[j];
+                rank += (kj < key) || (kj == key && j < li);
+            }
+            my_rank[k] = rank;
+            L.ntab[base + rank] = li;
+            Act d = decode_action(P, eff[k]);
+#pragma unroll
+            for (int s = 0; s < XM; ++s)
+                if (s == slot_new) ag[k].slot[s] = slot_pack(d.type == 4, d.r, d.p, rank);
+        }
 #pragma unroll
         for (int s = 0; s < XM; ++s) {
             uint32_t sl = ag[k].slot[s];
@@ -884,7 +965,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         const int64_t C = (int64_t)ag[k].coin_inv + ag[k].coin_esc;
         const double u1 = utility(C, ag[k].labor, P.eta);
         rew[row0 + li] = (float)(u1 - u0[k]);
-        L.sortbuf[li] = C;
+        L.sortbuf[li] = welfare_key(C, li, n);
     }
     __syncthreads();
     const double ug1 = social_welfare_block(P, L, n, S2);
@@ -937,35 +1018,57 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     }
     __syncthreads();
     // Rows go through LDS (the bucket arrays are free now) so that the whole
-    // economy's rows leave in coalesced 16-byte stores; direct stores when
-    // they do not fit.
-    const size_t obs_bytes = obs ? (size_t)n * P.Ds * 2 : 0, mask_bytes = mask ? (size_t)n * P.W * 4 : 0;
-    const bool staged = obs_bytes + mask_bytes <= (size_t)3 * P.HB * 4;
-    uint16_t* so = (uint16_t*)L.hcnt;
-    uint32_t* smk = (uint32_t*)((unsigned char*)L.hcnt + obs_bytes);
+    // economy's rows leave in coalesced stores; direct stores when they do
+    // not fit.  Staged, an agent writes only the 32-bit words that hold its
+    // own features (odd LDS stride: no bank conflicts); the words made of
+    // economy-wide features (tax rates, phase, market statistics) are the
+    // same in every row and are built once.
+    const int dw = P.Ds >> 1;                     // row length in 32-bit words
+    const int c_own = (obs_own_features(R) + 1) >> 1;
+    const int os = c_own | 1, ms = P.W | 1;
+    const size_t obs_lds = obs ? (size_t)n * os * 4 : 0, mask_lds = mask ? (size_t)n * ms * 4 : 0;
+    const bool staged = obs_lds + mask_lds <= (size_t)3 * P.HB * 4;
+    uint32_t* so = (uint32_t*)L.hcnt;
+    uint32_t* smk = so + (obs ? (size_t)n * os : 0);
+    if (staged && obs)
+        for (int c = c_own + tid; c < dw; c += NT) L.tmpl[c] = obs_shared_word(P, L, c, t_next);
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
         const int li = tid + k * NT;
         if (li >= n) continue;
-        if (obs) write_obs_row(P, L, ag[k], t_next, (staged ? so : obs + row0 * (int64_t)P.Ds) + li * (int64_t)P.Ds);
-        if (mask) write_mask_row(P, L, ag[k], (staged ? smk : mask + row0 * (int64_t)P.W) + li * (int64_t)P.W);
+        if (staged) {  // separate calls keep the LDS and global address spaces apart
+            if (obs) write_obs_own_words(P, L, ag[k], t_next, so + li * os);
+            if (mask) write_mask_row(P, L, ag[k], smk + li * ms);
+        } else {
+            if (obs) write_obs_row(P, L, ag[k], t_next, obs + (row0 + li) * (int64_t)P.Ds);
+            if (mask) write_mask_row(P, L, ag[k], mask + (row0 + li) * (int64_t)P.W);
+        }
     }
     if (!staged) return;
     __syncthreads();
     if (obs) {
-        const uint4* src = (const uint4*)so;
-        uint4* dst = (uint4*)(obs + row0 * (int64_t)P.Ds);
-        for (int j = tid; j < (int)(obs_bytes / 16); j += NT) dst[j] = src[j];
+        uint32_t* dst = (uint32_t*)(obs + row0 * (int64_t)P.Ds);
+        const uint32_t mg = 0xFFFFFFFFu / (uint32_t)dw + 1u;  // j / dw = umulhi(j, mg) for j < 2^16
+        for (int j = tid; j < n * dw; j += NT) {
+            const int row = (int)__umulhi((uint32_t)j, mg), c = j - row * dw;
+            dst[j] = c < c_own ? so[row * os + c] : L.tmpl[c];
+        }
     }
     if (mask) {
         uint32_t* dst = mask + row0 * (int64_t)P.W;
-        for (int j = tid; j < n * P.W; j += NT) dst[j] = smk[j];
+        const uint32_t mg = 0xFFFFFFFFu / (uint32_t)P.W + 1u;
+        for (int j = tid; j < n * P.W; j += NT) {
+            const int row = (int)__umulhi((uint32_t)j, mg);
+            dst[j] = smk[row * ms + (j - row * P.W)];
+        }
     }
 }
 
-// plain launch: one workgroup per economy
-template <int RM, int XM, int APT>
-__global__ void __launch_bounds__(1024 / APT)
+// plain launch: one workgroup per economy.  MAXT bounds the workgroup size:
+// 256 leaves the compiler 256 VGPRs per lane (no spills), 1024 allows
+// populations of up to 1024 agents with 128.
+template <int RM, int XM, int APT, int MAXT>
+__global__ void __launch_bounds__(MAXT)
 env_step_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__ act,
                 const int32_t* __restrict__ gov, float* __restrict__ rew, float* __restrict__ gov_rew,
                 uint8_t* __restrict__ done_out, uint16_t* __restrict__ obs, uint32_t* __restrict__ mask)
@@ -978,8 +1081,8 @@ env_step_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__
 // queue (largest populations first).  The last workgroup to run dry resets
 // the queue, so consecutive launches (and replays of a captured graph) need
 // no host-side reset.
-template <int RM, int XM, int APT>
-__global__ void __launch_bounds__(1024 / APT)
+template <int RM, int XM, int APT, int MAXT>
+__global__ void __launch_bounds__(MAXT)
 env_step_persistent_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__ act,
                            const int32_t* __restrict__ gov, float* __restrict__ rew, float* __restrict__ gov_rew,
                            uint8_t* __restrict__ done_out, uint16_t* __restrict__ obs,
@@ -1377,17 +1480,29 @@ int ej_env_step(ej_env* h, const int32_t* d_act, const int32_t* d_gov, float* d_
     if (h->P.K > 0 && !d_gov) return EJ_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     EnvState S = h->state();
+#define EJ_STEP_LAUNCH(KERNEL, G)                                                                           \
+    do {                                                                                                    \
+        const bool small = h->NT <= 256;                                                                    \
+        if (h->variant == 0 && small)                                                                       \
+            KERNEL<4, 16, 1, 256><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done,  \
+                                                            d_obs, d_mask);                                 \
+        else if (h->variant == 0)                                                                           \
+            KERNEL<4, 16, 1, 1024><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, \
+                                                             d_obs, d_mask);                                \
+        else if (small)                                                                                     \
+            KERNEL<8, 32, 1, 256><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done,  \
+                                                            d_obs, d_mask);                                 \
+        else                                                                                                \
+            KERNEL<8, 32, 1, 1024><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, \
+                                                             d_obs, d_mask);                                \
+    } while (0)
     if (h->mode == 1) {
         const unsigned G = (unsigned)h->persistent_wg;
-        if (h->variant == 0)
-            env_step_persistent_kernel<4, 16, 1><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew,
-                                                                         d_done, d_obs, d_mask);
-        else
-            env_step_persistent_kernel<8, 32, 1><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew,
-                                                                         d_done, d_obs, d_mask);
+        EJ_STEP_LAUNCH(env_step_persistent_kernel, G);
     } else {
-        EJ_DISPATCH(h, env_step_kernel, h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs, d_mask);
+        EJ_STEP_LAUNCH(env_step_kernel, (unsigned)h->E);
     }
+#undef EJ_STEP_LAUNCH
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }

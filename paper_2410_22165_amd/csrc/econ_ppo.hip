@@ -97,17 +97,39 @@ __global__ void adv_stats_partial(const PpoBatchDev B, double* __restrict__ part
     }
 }
 
-// stats[0] = mean, stats[1] = 1 / (population std + 1e-8)
-__global__ void adv_stats_final(const double* __restrict__ part, int nb, int64_t rows, float* __restrict__ stats)
+// sums of n records of C doubles-or-floats by one 256-thread workgroup: thread
+// t takes records t, t + 256, ...; then a fixed wave and LDS tree (the same
+// order on every call, so the result is deterministic)
+template <int C, typename T>
+__device__ inline void block_sum_records(const T* __restrict__ rec, int64_t n, double (&out)[C])
 {
-    if (threadIdx.x != 0) return;
-    double a = 0.0, b = 0.0;
-    for (int k = 0; k < nb; ++k) {
-        a += part[2 * k];
-        b += part[2 * k + 1];
+    __shared__ double red[C][4];
+    double s[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c] = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += 256) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) s[c] += (double)rec[k * C + c];
     }
-    const double mean = a / (double)rows;
-    double var = b / (double)rows - mean * mean;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        s[c] = wave_sum(s[c]);
+        if (lane_id() == 0) red[c][threadIdx.x >> 6] = s[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c] = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
+}
+
+// stats[0] = mean, stats[1] = 1 / (population std + 1e-8); one 256-thread workgroup
+__global__ void __launch_bounds__(256) adv_stats_final(const double* __restrict__ part, int nb, int64_t rows,
+                                                       float* __restrict__ stats)
+{
+    double t[2];
+    block_sum_records<2>(part, nb, t);
+    if (threadIdx.x != 0) return;
+    const double mean = t[0] / (double)rows;
+    double var = t[1] / (double)rows - mean * mean;
     if (var < 0.0) var = 0.0;
     stats[0] = (float)mean;
     stats[1] = (float)(1.0 / (sqrt(var) + 1e-8));
@@ -546,12 +568,16 @@ __global__ void dw_reduce_kernel(const float* __restrict__ part, const float* __
     }
 }
 
-__global__ void loss_final_kernel(const float* __restrict__ parts, int nparts, int64_t rows, float* __restrict__ out)
+// minibatch means of the four loss terms from the per-tile partial sums; one 256-thread workgroup
+__global__ void __launch_bounds__(256) loss_final_kernel(const float* __restrict__ parts, int nparts, int64_t rows,
+                                                         float* __restrict__ out)
 {
-    if (threadIdx.x >= 4) return;
-    double s = 0.0;
-    for (int k = 0; k < nparts; ++k) s += parts[4 * k + threadIdx.x];
-    out[threadIdx.x] = (float)(s / (double)rows);
+    double t[4];
+    block_sum_records<4>(parts, nparts, t);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) out[c] = (float)(t[c] / (double)rows);
+    }
 }
 
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -702,7 +728,7 @@ int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t*
     if (nb > 1024) nb = 1024;
     adv_stats_partial<<<nb, 256, 0, st>>>(B, advp);
     EJ_LAUNCH_CHECK();
-    adv_stats_final<<<1, 64, 0, st>>>(advp, nb, b->rows, stats);
+    adv_stats_final<<<1, 256, 0, st>>>(advp, nb, b->rows, stats);
     EJ_LAUNCH_CHECK();
     uint16_t* T[6] = {(uint16_t*)(ws + w.o_obs), (uint16_t*)(ws + w.o_h1), (uint16_t*)(ws + w.o_h2),
                       (uint16_t*)(ws + w.o_dy), (uint16_t*)(ws + w.o_dh2), (uint16_t*)(ws + w.o_dh1)};
@@ -730,7 +756,7 @@ int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t*
     dw_reduce_kernel<<<red_blocks((int64_t)d.H * d.A1p + d.A1p), 256, 0, st>>>(p3, c3, d.H, d.A1p, G, d.H, d.A1,
                                                                               d_grads, d.oW3, d.A1, d.ob3);
     EJ_LAUNCH_CHECK();
-    loss_final_kernel<<<1, 64, 0, st>>>(lparts, (int)w.ntiles, b->rows, d_loss);
+    loss_final_kernel<<<1, 256, 0, st>>>(lparts, (int)w.ntiles, b->rows, d_loss);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }
