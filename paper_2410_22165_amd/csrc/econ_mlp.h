@@ -193,6 +193,69 @@ __device__ inline void dense_layer(f32x4 (&acc)[RT][N / 16], const uint16_t* abu
                                  acol0);
 }
 
+// One dense layer split by columns: the wave multiplies ALL TR x 16 rows of
+// `abuf` (row stride `as`) by its own CTW x 16 columns of the weights,
+// starting at column `col0`.  B fragments come straight from global memory
+// (L2-resident weights in the K-chunk layout: lane l reads the 16 bytes of
+// column l % 16, k = 8 (l / 16) .. + 7), two k-steps ahead of the MFMAs;
+// A fragments come from LDS one k-step ahead.  Every A fragment feeds CTW
+// MFMAs and every B fragment TR, and no weight passes through LDS.  The
+// caller synchronises before (abuf complete) and after (before abuf is
+// overwritten).
+template <int TR, int CTW, int NK>
+__device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int as,
+                                const uint16_t* __restrict__ wglob, int64_t kstride, int col0)
+{
+    zero_acc(acc);
+    const int l = lane_id();
+    const uint16_t* bp = wglob + (int64_t)(col0 + (l & 15)) * 32 + 8 * (l >> 4);
+    const uint16_t* ap = abuf + (l & 15) * as + 8 * (l >> 4);
+    constexpr int PF = 2;
+    bf16x8 bq[NK][CTW];
+    bf16x8 aq[NK][TR];
+#pragma unroll
+    for (int p = 0; p < PF && p < NK; ++p)
+#pragma unroll
+        for (int ct = 0; ct < CTW; ++ct) bq[p][ct] = *(const bf16x8*)(bp + (int64_t)p * kstride + ct * 16 * 32);
+#pragma unroll
+    for (int rt = 0; rt < TR; ++rt) aq[0][rt] = lds_frag(ap + rt * 16 * as);
+#pragma unroll
+    for (int kt = 0; kt < NK; ++kt) {
+        if (kt + PF < NK)
+#pragma unroll
+            for (int ct = 0; ct < CTW; ++ct)
+                bq[kt + PF][ct] = *(const bf16x8*)(bp + (int64_t)(kt + PF) * kstride + ct * 16 * 32);
+        if (kt + 1 < NK)
+#pragma unroll
+            for (int rt = 0; rt < TR; ++rt) aq[kt + 1][rt] = lds_frag(ap + rt * 16 * as + (kt + 1) * 32);
+#pragma unroll
+        for (int ct = 0; ct < CTW; ++ct)
+#pragma unroll
+            for (int rt = 0; rt < TR; ++rt) acc[rt][ct] = mfma16(aq[kt][rt], bq[kt][ct], acc[rt][ct]);
+    }
+}
+
+// bias + ReLU of a column-split layer, rounded to bf16, written to hbuf
+template <int TR, int CTW>
+__device__ inline void epilogue_relu_cs(const f32x4 (&acc)[TR][CTW], const float* __restrict__ bias,
+                                        uint16_t* hbuf, int hs, int col0)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int ct = 0; ct < CTW; ++ct) {
+        const int col = col0 + ct * 16 + (l & 15);
+        const float b = bias[col];
+#pragma unroll
+        for (int rt = 0; rt < TR; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = acc[rt][ct][i] + b;
+                v = v > 0.f ? v : 0.f;
+                hbuf[(rt * 16 + 4 * (l >> 4) + i) * hs + col] = f32_to_bf16(v);
+            }
+    }
+}
+
 // bias + ReLU, rounded to bf16, written to the wave's own rows of hbuf
 template <int RT, int CT>
 __device__ inline void epilogue_relu(const f32x4 (&acc)[RT][CT], const float* __restrict__ bias, uint16_t* hbuf,

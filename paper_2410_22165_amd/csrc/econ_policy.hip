@@ -21,11 +21,17 @@
 
 namespace econ {
 
-// per-row running state of the online softmax (LDS, RS_N floats per row)
-enum { RS_M = 0, RS_S, RS_T, RS_W, RS_ACT, RS_Z, RS_VAL, RS_U1, RS_U2, RS_N };
+// per-row sampling uniforms of the current chunk (LDS, RS_N floats per row)
+enum { RS_U1 = 0, RS_U2, RS_N };
 
+// LDS weight staging: only the logit layer (128 columns at a time) goes
+// through LDS; double-buffered for 128-row tiles
+template <int H, int RPW>
+constexpr int policy_wbuf() { return (MlpTile<H, RPW>::DB ? 2 : 1) * 128 * WSTRIDE; }
+
+// 64-row tiles with H <= 256 take 47 KB of LDS: three workgroups per CU
 template <int H, int RPW_>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, (RPW_ == 16 && H <= 256) ? 3 : 1)
 policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
                       const uint16_t* __restrict__ obs, const uint32_t* __restrict__ mask, int64_t M, int W,
                       uint64_t seed, uint64_t ctr_arg, const uint64_t* __restrict__ ctr_base,
@@ -38,16 +44,16 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* hbuf = (uint16_t*)smem;
     uint16_t* wbuf = hbuf + TILE * HS;
-    uint32_t* smask = (uint32_t*)(wbuf + T::WBUF);  // [TILE][W]
-    float* rstate = (float*)(smask + TILE * W);      // [TILE][RS_N] running softmax state per row
+    uint32_t* smask = (uint32_t*)(wbuf + policy_wbuf<H, RPW_>());  // [TILE][W]
+    float* rstate = (float*)(smask + TILE * W);      // [TILE][RS_N] uniforms of the current chunk
     float* sbias = rstate + TILE * RS_N;              // b1 [H], b2 [H], b3 [A1p] (zero padded)
     const int wave = threadIdx.x >> 6, l = lane_id();
     const int64_t row0 = (int64_t)blockIdx.x * TILE;
     const int arow0 = wave * RPW;
 
-    // first weight chunk in flight while the tile loads
+    // first chunk of the logit layer's weights in flight while the tile loads
     ECON_Q8_DECL;
-    chunk_gload<H>(work + d.oW1f, ECON_Q8_ARGS);
+    chunk_gload<128>(work + d.oW3f, ECON_Q8_ARGS);
     // observation tile -> activation buffer columns [0, K1p); mask rows -> LDS
     const int ppr = d.K1p / 8;
     for (int p = threadIdx.x; p < TILE * ppr; p += 256) {
@@ -61,26 +67,43 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
         const int64_t row = row0 + p / W;
         smask[p] = row < M ? mask[row0 * W + p] : 0u;
     }
-    for (int p = threadIdx.x; p < TILE * RS_N; p += 256) {
-        const int k = p % RS_N;
-        rstate[p] = k == RS_M ? -__builtin_huge_valf() : (k == RS_ACT ? __int_as_float(0) : 0.f);
-    }
     for (int p = threadIdx.x; p < 2 * H + d.A1p; p += 256)
         sbias[p] = p < H ? params[d.ob1 + p] : p < 2 * H ? params[d.ob2 + p - H] : (p - 2 * H < d.A1 ? params[d.ob3 + p - 2 * H] : 0.f);
 
-    f32x4 acc[RT][H / 16];
-    dense_layer_pf<RT, H, H, T::DB>(acc, hbuf, HS, arow0, d.K1p, work + d.oW1f, (int64_t)H * 32, wbuf, true,
-                                    work + d.oW2f, ECON_Q8_ARGS);
-    epilogue_relu<RT, H / 16>(acc, sbias, hbuf, HS, arow0);
-    dense_layer_pf<RT, H, 128, T::DB>(acc, hbuf, HS, arow0, H, work + d.oW2f, (int64_t)H * 32, wbuf, true,
-                                      work + d.oW3f, ECON_Q8_ARGS);
-    epilogue_relu<RT, H / 16>(acc, sbias + H, hbuf, HS, arow0);
+    // hidden layers split by columns: wave w computes every row of the tile
+    // for columns [w H / 4, (w + 1) H / 4)
+    {
+        constexpr int TR = TILE / 16, CTW = H / 64;
+        const int col0 = wave * (H / 4);
+        f32x4 acc[TR][CTW];
+        __syncthreads();  // observation tile in LDS
+        dense_cs<TR, CTW, 2>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
+        __syncthreads();  // every wave is done reading the observations
+        epilogue_relu_cs<TR, CTW>(acc, sbias, hbuf, HS, col0);
+        __syncthreads();
+        dense_cs<TR, CTW, H / 32>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
+        __syncthreads();
+        epilogue_relu_cs<TR, CTW>(acc, sbias + H, hbuf, HS, col0);
+        // the logit layer's first barrier publishes these rows
+    }
 
     // The logits are consumed in the MFMA accumulator layout: lane l owns rows
     // 4 (l / 16) + i of each 16-row tile, so the 16 lanes of a DPP row share
-    // one matrix row.  The running state of each row lives in LDS between
-    // chunks (registers are taken by the accumulators).
+    // one matrix row.  Every lane of a DPP row keeps the running state of its
+    // rows in registers (the row reductions leave the result in all 16
+    // lanes); the row loop has no branches, so the reduction chains of the
+    // wave's rows interleave.
     const float NEG = -__builtin_huge_valf();
+    float sM[RT][4], sS[RT][4], sT[RT][4], sW[RT][4], sV[RT][4], sZ[RT][4];
+    int sA[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            sM[rt][i] = NEG;
+            sS[rt][i] = sT[rt][i] = sW[rt][i] = sV[rt][i] = sZ[rt][i] = 0.f;
+            sA[rt][i] = 0;
+        }
     for (int c = 0; c < d.NC; ++c) {
         f32x4 acc3[RT][8];
         const uint16_t* next = c + 1 < d.NC ? work + d.oW3f + (int64_t)(c + 1) * 128 * 32 : nullptr;
@@ -99,12 +122,25 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
             const int col = c * 128 + ct * 16 + (l & 15);
             bcol[ct] = sbias[2 * H + col];
         }
+        if (logits) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t row = row0 + arow0 + rt * 16 + 4 * (l >> 4) + i;
+                    if (row < M)
+#pragma unroll
+                        for (int ct = 0; ct < 8; ++ct) {
+                            const int col = c * 128 + ct * 16 + (l & 15);
+                            if (col < d.A) logits[row * d.A + col] = acc3[rt][ct][i] + bcol[ct];
+                        }
+                }
+        }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int rw = rt * 16 + 4 * (l >> 4) + i;  // row within the wave
-                const int rloc = arow0 + rw;
+                const int rloc = arow0 + rt * 16 + 4 * (l >> 4) + i;  // row within the tile
                 const float u1 = rstate[rloc * RS_N + RS_U1], u2 = rstate[rloc * RS_N + RS_U2];
                 float z[8];
                 bool ok[8];
@@ -116,10 +152,9 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
                     const uint32_t mw = wi < W ? smask[rloc * W + wi] : 0u;
                     z[ct] = acc3[rt][ct][i] + bcol[ct];
                     ok[ct] = col < d.A && ((mw >> (col & 31)) & 1u);
-                    if (col == d.A) zval = z[ct];
-                    if (ok[ct]) zmax = fmaxf(zmax, z[ct]);
+                    zval = col == d.A ? z[ct] : zval;
+                    zmax = ok[ct] ? fmaxf(zmax, z[ct]) : zmax;
                 }
-                float* st = rstate + rloc * RS_N;
                 const float zv = row16_sum(zval);  // the value head sits right after the logits
                 const float mc = row16_max(zmax);
                 const bool any = mc != NEG;
@@ -140,16 +175,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
 #pragma unroll
                 for (int ct = 0; ct < 8; ++ct) P[ct] += before;
                 const float Tc = row16_sum(tl);
-                if (logits) {
-                    const int64_t row = row0 + rloc;
-                    if (row < M)
-#pragma unroll
-                        for (int ct = 0; ct < 8; ++ct) {
-                            const int col = c * 128 + ct * 16 + (l & 15);
-                            if (col < d.A) logits[row * d.A + col] = z[ct];
-                        }
-                }
-                const float m = st[RS_M], S0 = st[RS_S], T0 = st[RS_T], W0 = st[RS_W];
+                const float m = sM[rt][i], S0 = sS[rt][i], T0 = sT[rt][i], W0 = sW[rt][i];
                 const float mn = any ? fmaxf(m, mc) : m;
                 const float fo = (m == NEG) ? 0.f : __expf(m - mn), fc = any ? __expf(mc - mn) : 0.f;
                 const float Tn = (m == NEG ? 0.f : fo * (T0 + (m - mn) * S0)) + (any ? fc * (Tc + (mc - mn) * Sc) : 0.f);
@@ -162,50 +188,49 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
                 int key = 1 << 20, last = -1;
 #pragma unroll
                 for (int ct = 7; ct >= 0; --ct) {
-                    if (ok[ct] && P[ct] > target) key = 8 * (l & 15) + ct;
-                    if (ok[ct] && last < 0) last = 8 * (l & 15) + ct;
+                    key = (ok[ct] && P[ct] > target) ? 8 * (l & 15) + ct : key;
+                    last = (ok[ct] && last < 0) ? 8 * (l & 15) + ct : last;
                 }
                 key = row16_min_i(key);
-                if (key == (1 << 20)) key = row16_max_i(last);  // rounding put the target at the top
+                const int top = row16_max_i(last);
+                key = key == (1 << 20) ? top : key;  // rounding put the target at the top
                 float zk = 0.f;
 #pragma unroll
-                for (int ct = 0; ct < 8; ++ct)
-                    if (8 * (l & 15) + ct == key) zk = z[ct];
+                for (int ct = 0; ct < 8; ++ct) zk = 8 * (l & 15) + ct == key ? z[ct] : zk;
                 zk = row16_sum(zk);
                 key = (key & 7) * 16 + (key >> 3);  // walk position -> column in the chunk
-                if ((l & 15) == 0) {
-                    st[RS_M] = mn;
-                    st[RS_S] = Sn;
-                    st[RS_T] = Tn;
-                    st[RS_W] = Wn;
-                    st[RS_VAL] += zv;
-                    if (take) {
-                        st[RS_ACT] = __int_as_float(c * 128 + key);
-                        st[RS_Z] = zk;
-                    }
-                }
+                sM[rt][i] = mn;
+                sS[rt][i] = Sn;
+                sT[rt][i] = Tn;
+                sW[rt][i] = Wn;
+                sV[rt][i] += zv;
+                sA[rt][i] = take ? c * 128 + key : sA[rt][i];
+                sZ[rt][i] = take ? zk : sZ[rt][i];
             }
     }
-    __syncthreads();
-    // outputs: sampled action, its log-probability, entropy, value
-    for (int r = threadIdx.x; r < TILE; r += 256) {
-        const int64_t row = row0 + r;
-        if (row >= M) continue;
-        const float* st = rstate + r * RS_N;
-        const float S = st[RS_S];
-        int a = __float_as_int(st[RS_ACT]);
-        float lp = 0.f, h = 0.f;
-        if (S > 0.f) {
-            const float lS = __logf(S);
-            lp = st[RS_Z] - st[RS_M] - lS;
-            h = lS - st[RS_T] / S;
-        } else {
-            a = 0;
-        }
-        act[row] = a;
-        logp[row] = lp;
-        ent[row] = h;
-        val[row] = st[RS_VAL];
+    // outputs: sampled action, its log-probability, entropy, value (lane 0 of each DPP row)
+    if ((l & 15) == 0) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t row = row0 + arow0 + rt * 16 + 4 * (l >> 4) + i;
+                if (row >= M) continue;
+                const float S = sS[rt][i];
+                int a = sA[rt][i];
+                float lp = 0.f, h = 0.f;
+                if (S > 0.f) {
+                    const float lS = __logf(S);
+                    lp = sZ[rt][i] - sM[rt][i] - lS;
+                    h = lS - sT[rt][i] / S;
+                } else {
+                    a = 0;
+                }
+                act[row] = a;
+                logp[row] = lp;
+                ent[row] = h;
+                val[row] = sV[rt][i];
+            }
     }
 }
 
@@ -243,11 +268,11 @@ __global__ void mlp_sync_kernel(const MlpDims d, const float* __restrict__ p, ui
 }
 
 template <int H, int RPW>
-size_t policy_lds_bytes(int W)
+size_t policy_lds_bytes(int W, int A1p)
 {
     using T = MlpTile<H, RPW>;
-    return (size_t)T::TILE * T::HS * 2 + (size_t)T::WBUF * 2 + (size_t)T::TILE * W * 4 + (size_t)T::TILE * RS_N * 4 +
-           (size_t)(2 * H + 1024) * 4;
+    return (size_t)T::TILE * T::HS * 2 + (size_t)policy_wbuf<H, RPW>() * 2 + (size_t)T::TILE * W * 4 +
+           (size_t)T::TILE * RS_N * 4 + (size_t)(2 * H + A1p) * 4;
 }
 
 template <int H, int RPW>
@@ -257,7 +282,7 @@ int launch_policy_forward(const MlpDims& d, const float* params, const uint16_t*
 {
     using T = MlpTile<H, RPW>;
     const int64_t blocks = (M + T::TILE - 1) / T::TILE;
-    const size_t lds = policy_lds_bytes<H, RPW>(W);
+    const size_t lds = policy_lds_bytes<H, RPW>(W, d.A1p);
     policy_forward_kernel<H, RPW><<<(unsigned)blocks, 256, lds, st>>>(d, params, work, obs, mask, M, W, seed, ctr, ctr_base,
                                                                   act, logp, val, ent, logits);
     EJ_LAUNCH_CHECK();
