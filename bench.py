@@ -49,6 +49,24 @@ def policy_flops_per_row(D, H, A) -> int:
     return 2 * (D * H + H * H + H * (A + 1))
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    counter passes (scaled by a 256 MiB copy), or None when the kernel's
+    sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{WORKLOAD}.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)["kernels"][kernel]
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def cpu_baseline(cfg, weights, budget_s: float = 12.0):
     """The oracle as it stands (C economy, float64 numpy policy with its own
     sampler), single-threaded, on a bounded sample: economies of the same
@@ -248,8 +266,10 @@ def main():
     }
     dom = env_kernel if ms_env >= ms_pol else "policy_forward_kernel"
     k = kernels[dom]
+    for name, kk in kernels.items():
+        kk["hbm_bytes_per_launch"] = measured_traffic(name)
     roofline = {"kernel": dom, "bound": k["bound"], "achieved": round(k["achieved"], 3), "peak": k["peak"],
-                "unit": k["unit"], "frac": round(k["frac"], 5), "traffic": None}
+                "unit": k["unit"], "frac": round(k["frac"], 5), "traffic": k["hbm_bytes_per_launch"]}
 
     out = {
         "metric": "agent-steps/sec (env+policy) at E×N=1024×100",
