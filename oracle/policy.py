@@ -91,11 +91,10 @@ def sample_inverse_cdf(logp: np.ndarray, u: np.ndarray):
     return act, margin
 
 
-def chunk_walk_order(chunk: int = 128, lanes: int = 16) -> np.ndarray:
+def chunk_walk_order(chunk: int = 128) -> np.ndarray:
     """Order in which the actions of one chunk are walked by the inverse CDF:
-    offset 16 t + j for j = 0..15 (outer) and t = 0..7 (inner)."""
-    per = chunk // lanes
-    return np.array([t * lanes + j for j in range(lanes) for t in range(per)], np.int64)
+    action order."""
+    return np.arange(chunk, dtype=np.int64)
 
 
 def sample_chunked(logp: np.ndarray, u1: np.ndarray, u2: np.ndarray, chunk: int = 128):

@@ -1244,6 +1244,17 @@ __global__ void env_random_actions_kernel(const EnvParams P, const EnvState S, u
     }
 }
 
+// government levels only: one thread per (economy, bracket)
+__global__ void env_random_gov_kernel(const EnvParams P, const EnvState S, uint64_t act_seed, int32_t* __restrict__ gov)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= S.E * P.K) return;
+    const int e = j / P.K, b = j - e * P.K;
+    const int t = S.env_t[e], ep = S.env_ep[e];
+    u64x4 w = philox(act_seed, PURPOSE_GOV, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)(b >> 2));
+    gov[j] = (int32_t)(((word_of(w, b & 3) >> 32) * 21ull) >> 32);
+}
+
 }  // namespace econ
 
 // ===========================================================================
@@ -1536,7 +1547,13 @@ int ej_env_random_actions(ej_env* h, uint64_t act_seed, int32_t* d_act, int32_t*
 {
     if (!h || (h->P.K > 0 && !d_gov)) return EJ_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    env_random_actions_kernel<<<h->E, 256, 0, st>>>(h->P, h->state(), act_seed, d_act, d_gov);
+    if (d_act) {
+        env_random_actions_kernel<<<h->E, 256, 0, st>>>(h->P, h->state(), act_seed, d_act, d_gov);
+    } else {
+        if (h->P.K == 0) return EJ_OK;
+        const int64_t n = (int64_t)h->E * h->P.K;
+        env_random_gov_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(h->P, h->state(), act_seed, d_gov);
+    }
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }

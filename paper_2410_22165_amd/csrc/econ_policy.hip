@@ -14,22 +14,63 @@
 // running total W accumulates S_c; the chunk becomes the candidate when
 // u1_c * W < S_c (weighted reservoir: chunk c ends chosen with probability
 // S_c / sum S).  Inside a candidate chunk the action is the first allowed
-// action whose cumulative weight exceeds u2_c * S_c (inverse CDF), walking
-// the chunk's actions in the fixed order c 128 + 16 t + j for j = 0..15
-// (outer) and t = 0..7 (inner) -- the order of the MFMA accumulator layout.
+// action, in action order, whose cumulative weight exceeds u2_c * S_c
+// (inverse CDF).
 #include "econ_mlp.h"
 
 namespace econ {
 
-// per-row sampling uniforms of the current chunk (LDS, RS_N floats per row)
-enum { RS_U1 = 0, RS_U2, RS_N };
+// LDS row stride (floats) of the fp32 logit chunk: 128 + 4 keeps the rows
+// read by one wave on distinct banks
+constexpr int ZS = 132;
 
-// LDS weight staging: only the logit layer (128 columns at a time) goes
-// through LDS; double-buffered for 128-row tiles
+// LDS bytes: activations (aliased by the logit chunk when there is only one
+// chunk), mask words, uniforms, biases
 template <int H, int RPW>
-constexpr int policy_wbuf() { return (MlpTile<H, RPW>::DB ? 2 : 1) * 128 * WSTRIDE; }
+size_t policy_lds_bytes(int W, int A1p)
+{
+    using T = MlpTile<H, RPW>;
+    const size_t hb = (size_t)T::TILE * T::HS * 2, zb = (size_t)T::TILE * ZS * 4;
+    const size_t region = A1p == 128 ? (hb > zb ? hb : zb) : hb + zb;
+    return region + (size_t)T::TILE * W * 4 + (size_t)T::TILE * 2 * 4 + (size_t)(2 * H + A1p) * 4;
+}
 
-// 64-row tiles with H <= 256 take 47 KB of LDS: three workgroups per CU
+// sums / maxima over the 4 lanes of a quad
+__device__ inline float quad_sum(float v)
+{
+    v += dpp_f<DPP_XOR1>(v);
+    v += dpp_f<DPP_XOR2>(v);
+    return v;
+}
+__device__ inline float quad_max(float v)
+{
+    v = fmaxf(v, dpp_f<DPP_XOR1>(v));
+    v = fmaxf(v, dpp_f<DPP_XOR2>(v));
+    return v;
+}
+__device__ inline int quad_min_i(int v)
+{
+    v = min(v, dpp_i<DPP_XOR1>(v));
+    v = min(v, dpp_i<DPP_XOR2>(v));
+    return v;
+}
+__device__ inline int quad_max_i(int v)
+{
+    v = max(v, dpp_i<DPP_XOR1>(v));
+    v = max(v, dpp_i<DPP_XOR2>(v));
+    return v;
+}
+// inclusive prefix sum over the 4 lanes of a quad (q = lane % 4)
+__device__ inline float quad_scan(float v, int q)
+{
+    const float t1 = dpp_f<DPP_ROW_SHR1>(v);
+    v += q >= 1 ? t1 : 0.f;
+    const float t2 = dpp_f<DPP_ROW_SHR2>(v);
+    v += q >= 2 ? t2 : 0.f;
+    return v;
+}
+
+// 64-row tiles with H <= 256 take 37 KB of LDS and 160 VGPRs: three workgroups per CU
 template <int H, int RPW_>
 __global__ void __launch_bounds__(256, (RPW_ == 16 && H <= 256) ? 3 : 1)
 policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
@@ -40,20 +81,18 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
 {
     const uint64_t ctr = ctr_arg + (ctr_base ? *ctr_base : 0ull);
     using T = MlpTile<H, RPW_>;
-    constexpr int RT = T::RT, RPW = T::RPW, TILE = T::TILE, HS = T::HS;
+    constexpr int RPW = T::RPW, TILE = T::TILE, HS = T::HS, TR = TILE / 16;
     extern __shared__ __align__(16) unsigned char smem[];
+    const size_t hb = (size_t)TILE * HS * 2, zb = (size_t)TILE * ZS * 4;
+    const size_t region = d.A1p == 128 ? (hb > zb ? hb : zb) : hb + zb;
     uint16_t* hbuf = (uint16_t*)smem;
-    uint16_t* wbuf = hbuf + TILE * HS;
-    uint32_t* smask = (uint32_t*)(wbuf + policy_wbuf<H, RPW_>());  // [TILE][W]
-    float* rstate = (float*)(smask + TILE * W);      // [TILE][RS_N] uniforms of the current chunk
-    float* sbias = rstate + TILE * RS_N;              // b1 [H], b2 [H], b3 [A1p] (zero padded)
+    float* zbuf = (float*)(smem + (d.A1p == 128 ? 0 : hb));  // logit chunk [TILE][ZS]
+    uint32_t* smask = (uint32_t*)(smem + region);            // [TILE][W]
+    float* urow = (float*)(smask + TILE * W);                 // [TILE][2] uniforms of the current chunk
+    float* sbias = urow + TILE * 2;                           // b1 [H], b2 [H], b3 [A1p] (zero padded)
     const int wave = threadIdx.x >> 6, l = lane_id();
     const int64_t row0 = (int64_t)blockIdx.x * TILE;
-    const int arow0 = wave * RPW;
 
-    // first chunk of the logit layer's weights in flight while the tile loads
-    ECON_Q8_DECL;
-    chunk_gload<128>(work + d.oW3f, ECON_Q8_ARGS);
     // observation tile -> activation buffer columns [0, K1p); mask rows -> LDS
     const int ppr = d.K1p / 8;
     for (int p = threadIdx.x; p < TILE * ppr; p += 256) {
@@ -70,10 +109,11 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     for (int p = threadIdx.x; p < 2 * H + d.A1p; p += 256)
         sbias[p] = p < H ? params[d.ob1 + p] : p < 2 * H ? params[d.ob2 + p - H] : (p - 2 * H < d.A1 ? params[d.ob3 + p - 2 * H] : 0.f);
 
-    // hidden layers split by columns: wave w computes every row of the tile
-    // for columns [w H / 4, (w + 1) H / 4)
+    // All three layers are split by columns: wave w computes every row of the
+    // tile for a quarter of the output columns, with weight fragments loaded
+    // from L2 straight into registers.
     {
-        constexpr int TR = TILE / 16, CTW = H / 64;
+        constexpr int CTW = H / 64;
         const int col0 = wave * (H / 4);
         f32x4 acc[TR][CTW];
         __syncthreads();  // observation tile in LDS
@@ -84,153 +124,147 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
         dense_cs<TR, CTW, H / 32>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
         __syncthreads();
         epilogue_relu_cs<TR, CTW>(acc, sbias + H, hbuf, HS, col0);
-        // the logit layer's first barrier publishes these rows
+        __syncthreads();
     }
 
-    // The logits are consumed in the MFMA accumulator layout: lane l owns rows
-    // 4 (l / 16) + i of each 16-row tile, so the 16 lanes of a DPP row share
-    // one matrix row.  Every lane of a DPP row keeps the running state of its
-    // rows in registers (the row reductions leave the result in all 16
-    // lanes); the row loop has no branches, so the reduction chains of the
-    // wave's rows interleave.
+    // Logits, 128 actions (one chunk) at a time: wave w computes columns
+    // [32 w, 32 w + 32) of the chunk for every row and leaves them in LDS
+    // (fp32).  Then four lanes share a row (q = lane % 4 takes the chunk's
+    // columns 32 q .. 32 q + 31 in order), so every row reduction is a
+    // two-step quad reduction.  Each lane keeps its rows' running state.
     const float NEG = -__builtin_huge_valf();
-    float sM[RT][4], sS[RT][4], sT[RT][4], sW[RT][4], sV[RT][4], sZ[RT][4];
-    int sA[RT][4];
+    constexpr int SR = RPW / 16;  // softmax rows per lane
+    const int q = l & 3;
+    float sM[SR], sS[SR], sT[SR], sW[SR], sV[SR], sZ[SR];
+    int sA[SR];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            sM[rt][i] = NEG;
-            sS[rt][i] = sT[rt][i] = sW[rt][i] = sV[rt][i] = sZ[rt][i] = 0.f;
-            sA[rt][i] = 0;
-        }
-    for (int c = 0; c < d.NC; ++c) {
-        f32x4 acc3[RT][8];
-        const uint16_t* next = c + 1 < d.NC ? work + d.oW3f + (int64_t)(c + 1) * 128 * 32 : nullptr;
-        dense_layer_pf<RT, 128, 128, T::DB>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32,
-                                            (int64_t)d.A1p * 32, wbuf, true, next, ECON_Q8_ARGS);
-        // uniforms of chunk c: lane j < RPW draws for the wave's row j
-        if (l < RPW) {
-            u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row0 + arow0 + l), ctr, (uint64_t)(c >> 1), 0);
-            rstate[(arow0 + l) * RS_N + RS_U1] = unif24(word_of(w, 2 * (c & 1)));
-            rstate[(arow0 + l) * RS_N + RS_U2] = unif24(word_of(w, 2 * (c & 1) + 1));
-        }
-        wave_lds_fence();
-        float bcol[8];
-#pragma unroll
-        for (int ct = 0; ct < 8; ++ct) {
-            const int col = c * 128 + ct * 16 + (l & 15);
-            bcol[ct] = sbias[2 * H + col];
-        }
-        if (logits) {
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int64_t row = row0 + arow0 + rt * 16 + 4 * (l >> 4) + i;
-                    if (row < M)
-#pragma unroll
-                        for (int ct = 0; ct < 8; ++ct) {
-                            const int col = c * 128 + ct * 16 + (l & 15);
-                            if (col < d.A) logits[row * d.A + col] = acc3[rt][ct][i] + bcol[ct];
-                        }
-                }
-        }
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int rloc = arow0 + rt * 16 + 4 * (l >> 4) + i;  // row within the tile
-                const float u1 = rstate[rloc * RS_N + RS_U1], u2 = rstate[rloc * RS_N + RS_U2];
-                float z[8];
-                bool ok[8];
-                float zval = 0.f, zmax = NEG;
-#pragma unroll
-                for (int ct = 0; ct < 8; ++ct) {
-                    const int col = c * 128 + ct * 16 + (l & 15);
-                    const int wi = c * 4 + (ct >> 1);
-                    const uint32_t mw = wi < W ? smask[rloc * W + wi] : 0u;
-                    z[ct] = acc3[rt][ct][i] + bcol[ct];
-                    ok[ct] = col < d.A && ((mw >> (col & 31)) & 1u);
-                    zval = col == d.A ? z[ct] : zval;
-                    zmax = ok[ct] ? fmaxf(zmax, z[ct]) : zmax;
-                }
-                const float zv = row16_sum(zval);  // the value head sits right after the logits
-                const float mc = row16_max(zmax);
-                const bool any = mc != NEG;
-                // Walk order inside the chunk: lane-major (lane j's eight actions
-                // j, 16 + j, ..., 112 + j, then lane j + 1's): a lane-local prefix
-                // plus one 16-lane scan of the lane totals.
-                float e[8], P[8], own = 0.f, tl = 0.f;
-#pragma unroll
-                for (int ct = 0; ct < 8; ++ct) {
-                    e[ct] = ok[ct] ? __expf(z[ct] - mc) : 0.f;
-                    tl += ok[ct] ? e[ct] * (z[ct] - mc) : 0.f;
-                    own += e[ct];
-                    P[ct] = own;
-                }
-                const float incl = row16_scan(own);
-                const float before = incl - own;
-                const float Sc = row16_sum(own);
-#pragma unroll
-                for (int ct = 0; ct < 8; ++ct) P[ct] += before;
-                const float Tc = row16_sum(tl);
-                const float m = sM[rt][i], S0 = sS[rt][i], T0 = sT[rt][i], W0 = sW[rt][i];
-                const float mn = any ? fmaxf(m, mc) : m;
-                const float fo = (m == NEG) ? 0.f : __expf(m - mn), fc = any ? __expf(mc - mn) : 0.f;
-                const float Tn = (m == NEG ? 0.f : fo * (T0 + (m - mn) * S0)) + (any ? fc * (Tc + (mc - mn) * Sc) : 0.f);
-                const float Sn = S0 * fo + Sc * fc;
-                const float Wn = W0 * fo + Sc * fc;
-                const bool take = any && u1 * Wn < Sc * fc;
-                // first allowed action whose cumulative weight exceeds u2 * Sc
-                const float target = u2 * Sc;
-                // position in the walk: (lane, ct) -> 8 lane + ct
-                int key = 1 << 20, last = -1;
-#pragma unroll
-                for (int ct = 7; ct >= 0; --ct) {
-                    key = (ok[ct] && P[ct] > target) ? 8 * (l & 15) + ct : key;
-                    last = (ok[ct] && last < 0) ? 8 * (l & 15) + ct : last;
-                }
-                key = row16_min_i(key);
-                const int top = row16_max_i(last);
-                key = key == (1 << 20) ? top : key;  // rounding put the target at the top
-                float zk = 0.f;
-#pragma unroll
-                for (int ct = 0; ct < 8; ++ct) zk = 8 * (l & 15) + ct == key ? z[ct] : zk;
-                zk = row16_sum(zk);
-                key = (key & 7) * 16 + (key >> 3);  // walk position -> column in the chunk
-                sM[rt][i] = mn;
-                sS[rt][i] = Sn;
-                sT[rt][i] = Tn;
-                sW[rt][i] = Wn;
-                sV[rt][i] += zv;
-                sA[rt][i] = take ? c * 128 + key : sA[rt][i];
-                sZ[rt][i] = take ? zk : sZ[rt][i];
-            }
+    for (int k = 0; k < SR; ++k) {
+        sM[k] = NEG;
+        sS[k] = sT[k] = sW[k] = sV[k] = sZ[k] = 0.f;
+        sA[k] = 0;
     }
-    // outputs: sampled action, its log-probability, entropy, value (lane 0 of each DPP row)
-    if ((l & 15) == 0) {
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int64_t row = row0 + arow0 + rt * 16 + 4 * (l >> 4) + i;
-                if (row >= M) continue;
-                const float S = sS[rt][i];
-                int a = sA[rt][i];
-                float lp = 0.f, h = 0.f;
-                if (S > 0.f) {
-                    const float lS = __logf(S);
-                    lp = sZ[rt][i] - sM[rt][i] - lS;
-                    h = lS - sT[rt][i] / S;
-                } else {
-                    a = 0;
-                }
-                act[row] = a;
-                logp[row] = lp;
-                ent[row] = h;
-                val[row] = sV[rt][i];
+    for (int c = 0; c < d.NC; ++c) {
+        {
+            f32x4 acc3[TR][2];
+            dense_cs<TR, 2, H / 32>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32,
+                                    32 * wave);
+            // uniforms of chunk c: lane j < RPW draws for the wave's row j
+            if (l < RPW) {
+                u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row0 + wave * RPW + l), ctr, (uint64_t)(c >> 1), 0);
+                urow[(wave * RPW + l) * 2 + 0] = unif24(word_of(w, 2 * (c & 1)));
+                urow[(wave * RPW + l) * 2 + 1] = unif24(word_of(w, 2 * (c & 1) + 1));
             }
+            if (d.A1p == 128) __syncthreads();  // the logit chunk overwrites the activations
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+                const int cc = 32 * wave + ct * 16 + (l & 15);
+                const float b = sbias[2 * H + c * 128 + cc];
+#pragma unroll
+                for (int rt = 0; rt < TR; ++rt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) zbuf[(rt * 16 + 4 * (l >> 4) + i) * ZS + cc] = acc3[rt][ct][i] + b;
+            }
+        }
+        __syncthreads();  // the chunk's logits and uniforms are in LDS
+        const int colq = c * 128 + 32 * q;  // first action of this lane's quarter
+#pragma unroll
+        for (int k = 0; k < SR; ++k) {
+            const int rloc = wave * RPW + k * 16 + (l >> 2);
+            float z[32];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float4 v = *(const float4*)(zbuf + rloc * ZS + 32 * q + 4 * j);
+                z[4 * j] = v.x;
+                z[4 * j + 1] = v.y;
+                z[4 * j + 2] = v.z;
+                z[4 * j + 3] = v.w;
+            }
+            if (logits && row0 + rloc < M) {
+#pragma unroll
+                for (int j = 0; j < 32; ++j)
+                    if (colq + j < d.A) logits[(row0 + rloc) * d.A + colq + j] = z[j];
+            }
+            const int wi = c * 4 + q;
+            const uint32_t mw = wi < W ? smask[rloc * W + wi] : 0u;
+            const float u1 = urow[rloc * 2], u2 = urow[rloc * 2 + 1];
+            float zmax = NEG, zval = 0.f;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                const bool ok = colq + j < d.A && ((mw >> j) & 1u);
+                zmax = ok ? fmaxf(zmax, z[j]) : zmax;
+                zval = colq + j == d.A ? z[j] : zval;  // the value head sits right after the logits
+            }
+            const float mc = quad_max(zmax);
+            const bool any = mc != NEG;
+            float e[32], own = 0.f, tl = 0.f;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                const bool ok = colq + j < d.A && ((mw >> j) & 1u);
+                e[j] = ok ? __expf(z[j] - mc) : 0.f;
+                tl += ok ? e[j] * (z[j] - mc) : 0.f;
+                own += e[j];
+            }
+            const float before = quad_scan(own, q) - own;
+            const float Sc = quad_sum(own);
+            const float Tc = quad_sum(tl);
+            const float zv = quad_sum(zval);
+            const float m = sM[k], S0 = sS[k], T0 = sT[k], W0 = sW[k];
+            const float mn = any ? fmaxf(m, mc) : m;
+            const float fo = (m == NEG) ? 0.f : __expf(m - mn), fc = any ? __expf(mc - mn) : 0.f;
+            const float Tn = (m == NEG ? 0.f : fo * (T0 + (m - mn) * S0)) + (any ? fc * (Tc + (mc - mn) * Sc) : 0.f);
+            const float Sn = S0 * fo + Sc * fc;
+            const float Wn = W0 * fo + Sc * fc;
+            const bool take = any && u1 * Wn < Sc * fc;
+            // inverse CDF inside the chunk (action order): the first allowed
+            // action whose cumulative weight exceeds u2 * Sc
+            const float target = u2 * Sc;
+            int key = 1 << 20, last = -1;
+            float cum = before;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                const bool ok = colq + j < d.A && ((mw >> j) & 1u);
+                cum += e[j];
+                key = (ok && cum > target && key == (1 << 20)) ? 32 * q + j : key;
+                last = ok ? 32 * q + j : last;
+            }
+            key = quad_min_i(key);
+            const int top = quad_max_i(last);
+            key = key == (1 << 20) ? top : key;  // rounding put the target at the top
+            float zk = 0.f;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) zk = 32 * q + j == key ? z[j] : zk;
+            zk = quad_sum(zk);
+            sM[k] = mn;
+            sS[k] = Sn;
+            sT[k] = Tn;
+            sW[k] = Wn;
+            sV[k] += zv;
+            sA[k] = take ? c * 128 + key : sA[k];
+            sZ[k] = take ? zk : sZ[k];
+        }
+        if (c + 1 < d.NC) __syncthreads();  // before the next chunk overwrites the logits and uniforms
+    }
+    // outputs: sampled action, its log-probability, entropy, value (lane 0 of each quad)
+    if (q == 0) {
+#pragma unroll
+        for (int k = 0; k < SR; ++k) {
+            const int64_t row = row0 + wave * RPW + k * 16 + (l >> 2);
+            if (row >= M) continue;
+            const float S = sS[k];
+            int a = sA[k];
+            float lp = 0.f, h = 0.f;
+            if (S > 0.f) {
+                const float lS = __logf(S);
+                lp = sZ[k] - sM[k] - lS;
+                h = lS - sT[k] / S;
+            } else {
+                a = 0;
+            }
+            act[row] = a;
+            logp[row] = lp;
+            ent[row] = h;
+            val[row] = sV[k];
+        }
     }
 }
 
@@ -267,13 +301,6 @@ __global__ void mlp_sync_kernel(const MlpDims d, const float* __restrict__ p, ui
     }
 }
 
-template <int H, int RPW>
-size_t policy_lds_bytes(int W, int A1p)
-{
-    using T = MlpTile<H, RPW>;
-    return (size_t)T::TILE * T::HS * 2 + (size_t)policy_wbuf<H, RPW>() * 2 + (size_t)T::TILE * W * 4 +
-           (size_t)T::TILE * RS_N * 4 + (size_t)(2 * H + A1p) * 4;
-}
 
 template <int H, int RPW>
 int launch_policy_forward(const MlpDims& d, const float* params, const uint16_t* work, const uint16_t* obs,
