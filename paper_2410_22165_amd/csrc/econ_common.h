@@ -170,6 +170,16 @@ __device__ inline int dpp_i(int v, int fill = 0)
     return __builtin_amdgcn_update_dpp(fill, v, CTRL, 0xF, 0xF, false);
 }
 
+// Workgroup barrier that orders LDS only: outstanding global loads and
+// stores stay in flight across it (a full __syncthreads waits for them).
+// For threads that communicate through LDS alone.
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // all-reduce over the 16 lanes of each row
 __device__ inline float row16_sum(float v)
 {
@@ -226,6 +236,41 @@ __device__ inline int row16_scan_i(int v)
     v += dpp_i<DPP_ROW_SHR2>(v);
     v += dpp_i<DPP_ROW_SHR4>(v);
     v += dpp_i<DPP_ROW_SHR8>(v);
+    return v;
+}
+
+// sums / maxima over the 4 lanes of a quad
+__device__ inline float quad_sum(float v)
+{
+    v += dpp_f<DPP_XOR1>(v);
+    v += dpp_f<DPP_XOR2>(v);
+    return v;
+}
+__device__ inline float quad_max(float v)
+{
+    v = fmaxf(v, dpp_f<DPP_XOR1>(v));
+    v = fmaxf(v, dpp_f<DPP_XOR2>(v));
+    return v;
+}
+__device__ inline int quad_min_i(int v)
+{
+    v = min(v, dpp_i<DPP_XOR1>(v));
+    v = min(v, dpp_i<DPP_XOR2>(v));
+    return v;
+}
+__device__ inline int quad_max_i(int v)
+{
+    v = max(v, dpp_i<DPP_XOR1>(v));
+    v = max(v, dpp_i<DPP_XOR2>(v));
+    return v;
+}
+// inclusive prefix sum over the 4 lanes of a quad (q = lane % 4)
+__device__ inline float quad_scan(float v, int q)
+{
+    const float t1 = dpp_f<DPP_ROW_SHR1>(v);
+    v += q >= 1 ? t1 : 0.f;
+    const float t2 = dpp_f<DPP_ROW_SHR2>(v);
+    v += q >= 2 ? t2 : 0.f;
     return v;
 }
 

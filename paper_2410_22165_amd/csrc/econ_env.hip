@@ -299,9 +299,9 @@ __device__ inline int64_t block_sum_i64(int64_t v, int64_t* red)
 {
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     v = wave_sum(v);
-    __syncthreads();
+    lds_barrier();
     if (lane_id() == 0) red[w] = v;
-    __syncthreads();
+    lds_barrier();
     int64_t tot = 0;
     for (int j = 0; j < nw; ++j) tot += red[j];
     return tot;
@@ -342,7 +342,7 @@ __device__ inline void bitonic_sort_i64(int64_t* a, int n2)
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
 }
@@ -681,6 +681,21 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     const int R = P.R, X = P.X, K = P.K, PX = P.P * P.X;
     const int S2 = next_pow2(NL);
 
+    // The agent's state and action loads go out first and stay in flight
+    // while the LDS tables are initialised (the workgroup's threads talk
+    // through LDS only, so its barriers do not wait for global memory).
+    Agent<RM, XM> ag[APT];
+    int a_in[APT];
+    const double cached_ug = S.ug[e];  // social welfare of the step-start state, NaN when unknown
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        a_in[k] = 0;
+        if (li < n) {
+            load_agent(P, S, off + li, ag[k]);
+            a_in[k] = act[row0 + li];
+        }
+    }
     for (int j = tid; j < P.P; j += NT) L.prices[j] = P.prices[j];
     for (int j = tid; j < K - 1; j += NT) L.cutoffs[j] = P.cutoffs[j];
     if (tid < K) {
@@ -698,9 +713,8 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     }
     for (int j = tid; j < 2 * R * P.P; j += NT) L.nbcnt[j] = 0;
     for (int j = tid; j < S2; j += NT) L.sortbuf[j] = INT64_MAX;
-    __syncthreads();
+    lds_barrier();
 
-    Agent<RM, XM> ag[APT];
     double u0[APT];
     int eff[APT];
     int my_rank[APT];
@@ -713,17 +727,15 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         eff[k] = 0;
         my_rank[k] = 0;
         if (li < n) {
-            load_agent(P, S, off + li, ag[k]);
             const int64_t C = (int64_t)ag[k].coin_inv + ag[k].coin_esc;
             u0[k] = utility(C, ag[k].labor, P.eta);
             L.sortbuf[li] = welfare_key(C, li, n);
-            const int a = act[row0 + li];
+            const int a = a_in[k];
             if (action_allowed(P, ag[k], n_active(ag[k], X), a, L.prices)) eff[k] = a;
             else ++invalid;
         }
     }
-    __syncthreads();
-    const double cached_ug = S.ug[e];
+    lds_barrier();
     const double ug0 = cached_ug == cached_ug ? cached_ug : social_welfare_block(P, L, n, S2);
 
     // apply every agent's action; new orders go to slot t mod X
@@ -774,9 +786,9 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             my_rank[k] = atomicAdd(&L.nbcnt[code], 1);  // arrival position, ranked below
         }
     }
-    __syncthreads();
+    lds_barrier();
     seg_exclusive_scan(L.nbcnt, L.nboff, 1, 2 * R * P.P);
-    __syncthreads();
+    lds_barrier();
     // this step's orders listed per (side, r, p) in arrival order; the
     // welfare sort buffer is free until the rewards
     int32_t* ntmp = (int32_t*)L.sortbuf;
@@ -785,7 +797,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         const int li = tid + k * NT;
         if (li < n && L.ncode[li] >= 0) ntmp[L.nboff[L.ncode[li]] + my_rank[k]] = li;
     }
-    __syncthreads();
+    lds_barrier();
 
     // placement rank of each new order within its (side, r, p) list: by tie
     // key, then agent id; the new-order table lists the orders by rank.  Then
@@ -824,9 +836,9 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     seg_exclusive_scan(L.hcnt, L.hexc, 2 * R, PX);
-    __syncthreads();
+    lds_barrier();
 
     // trades per resource: k_r = max_p min(#bids >= price p, #asks <= price p)
     {
@@ -848,7 +860,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             if (lane == 0) L.kr[r] = best;
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     // settlement: every agent settles its own filled orders
 #pragma unroll
@@ -955,9 +967,9 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     }
 
     // rewards (Eq. (2)) and the end-of-step coin for the welfare
-    __syncthreads();
+    lds_barrier();
     for (int j = tid; j < S2; j += NT) L.sortbuf[j] = INT64_MAX;
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
         const int li = tid + k * NT;
@@ -967,7 +979,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         rew[row0 + li] = (float)(u1 - u0[k]);
         L.sortbuf[li] = welfare_key(C, li, n);
     }
-    __syncthreads();
+    lds_barrier();
     const double ug1 = social_welfare_block(P, L, n, S2);
     const int64_t n_invalid = block_sum_i64(invalid, L.red);
     if (tid == 0) {
@@ -1016,7 +1028,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     } else {
         market_stats(P, L, L.kr, X - 1);
     }
-    __syncthreads();
+    lds_barrier();
     // Rows go through LDS (the bucket arrays are free now) so that the whole
     // economy's rows leave in coalesced stores; direct stores when they do
     // not fit.  Staged, an agent writes only the 32-bit words that hold its
@@ -1045,7 +1057,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         }
     }
     if (!staged) return;
-    __syncthreads();
+    lds_barrier();
     if (obs) {
         uint32_t* dst = (uint32_t*)(obs + row0 * (int64_t)P.Ds);
         const uint32_t mg = 0xFFFFFFFFu / (uint32_t)dw + 1u;  // j / dw = umulhi(j, mg) for j < 2^16
@@ -1091,9 +1103,9 @@ env_step_persistent_kernel(const EnvParams P, const EnvState S, const int32_t* _
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_slot;
     for (;;) {
-        __syncthreads();  // everyone has read the previous slot
+        lds_barrier();  // everyone has read the previous slot
         if (threadIdx.x == 0) s_slot = (int)atomicAdd(&S.queue[0], 1u);
-        __syncthreads();
+        lds_barrier();
         const int k = s_slot;
         if (k >= S.E) break;
         env_step_one<RM, XM, APT>(P, S, S.order[k], act, gov, rew, gov_rew, done_out, obs, mask, smem);
@@ -1134,7 +1146,7 @@ env_observe_kernel(const EnvParams P, const EnvState S, uint16_t* __restrict__ o
         L.hcnt[j] = 0;
         L.hexc[j] = 0;
     }
-    __syncthreads();
+    lds_barrier();
     Agent<RM, XM> ag[APT];
     const int tX = t % X;
 #pragma unroll
@@ -1152,9 +1164,9 @@ env_observe_kernel(const EnvParams P, const EnvState S, uint16_t* __restrict__ o
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     market_stats(P, L, nullptr, -1);
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
         const int li = tid + k * NT;
@@ -1165,9 +1177,9 @@ env_observe_kernel(const EnvParams P, const EnvState S, uint16_t* __restrict__ o
     if (gov_obs == nullptr) return;
     float* g = gov_obs + (int64_t)e * P.Dg;
     for (int feat = 0; feat < 3 + R; ++feat) {
-        __syncthreads();
+        lds_barrier();
         for (int j = tid; j < S2; j += NT) L.sortbuf[j] = INT64_MAX;
-        __syncthreads();
+        lds_barrier();
         int64_t s1 = 0, s2 = 0;
 #pragma unroll
         for (int k = 0; k < APT; ++k) {

@@ -201,12 +201,12 @@ __device__ inline void dense_layer(f32x4 (&acc)[RT][N / 16], const uint16_t* abu
 // A fragments come from LDS one k-step ahead.  Every A fragment feeds CTW
 // MFMAs and every B fragment TR, and no weight passes through LDS.  The
 // caller synchronises before (abuf complete) and after (before abuf is
-// overwritten).
-template <int TR, int CTW, int NK>
+// overwritten).  ZERO = false accumulates onto acc.
+template <int TR, int CTW, int NK, bool ZERO = true>
 __device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int as,
                                 const uint16_t* __restrict__ wglob, int64_t kstride, int col0)
 {
-    zero_acc(acc);
+    if constexpr (ZERO) zero_acc(acc);
     const int l = lane_id();
     const uint16_t* bp = wglob + (int64_t)(col0 + (l & 15)) * 32 + 8 * (l >> 4);
     const uint16_t* ap = abuf + (l & 15) * as + 8 * (l >> 4);

@@ -35,41 +35,6 @@ size_t policy_lds_bytes(int W, int A1p)
     return region + (size_t)T::TILE * W * 4 + (size_t)T::TILE * 2 * 4 + (size_t)(2 * H + A1p) * 4;
 }
 
-// sums / maxima over the 4 lanes of a quad
-__device__ inline float quad_sum(float v)
-{
-    v += dpp_f<DPP_XOR1>(v);
-    v += dpp_f<DPP_XOR2>(v);
-    return v;
-}
-__device__ inline float quad_max(float v)
-{
-    v = fmaxf(v, dpp_f<DPP_XOR1>(v));
-    v = fmaxf(v, dpp_f<DPP_XOR2>(v));
-    return v;
-}
-__device__ inline int quad_min_i(int v)
-{
-    v = min(v, dpp_i<DPP_XOR1>(v));
-    v = min(v, dpp_i<DPP_XOR2>(v));
-    return v;
-}
-__device__ inline int quad_max_i(int v)
-{
-    v = max(v, dpp_i<DPP_XOR1>(v));
-    v = max(v, dpp_i<DPP_XOR2>(v));
-    return v;
-}
-// inclusive prefix sum over the 4 lanes of a quad (q = lane % 4)
-__device__ inline float quad_scan(float v, int q)
-{
-    const float t1 = dpp_f<DPP_ROW_SHR1>(v);
-    v += q >= 1 ? t1 : 0.f;
-    const float t2 = dpp_f<DPP_ROW_SHR2>(v);
-    v += q >= 2 ? t2 : 0.f;
-    return v;
-}
-
 // 64-row tiles with H <= 256 take 37 KB of LDS and 160 VGPRs: three workgroups per CU
 template <int H, int RPW_>
 __global__ void __launch_bounds__(256, (RPW_ == 16 && H <= 256) ? 3 : 1)

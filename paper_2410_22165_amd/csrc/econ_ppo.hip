@@ -138,9 +138,6 @@ __global__ void __launch_bounds__(256) adv_stats_final(const double* __restrict_
 // ---------------------------------------------------------------------------
 // the fused row kernel
 // ---------------------------------------------------------------------------
-__device__ inline float group16_max(float v) { return row16_max(v); }
-__device__ inline float group16_sum(float v) { return row16_sum(v); }
-
 // 4 consecutive rows (acc element order) of one column -> 8-byte store in the m-block layout
 __device__ inline void store_mblock4(uint16_t* T, int ncol, int64_t jrow, int col, const float (&v)[4])
 {
@@ -154,88 +151,121 @@ __device__ inline void store_mblock4(uint16_t* T, int ncol, int64_t jrow, int co
 
 // bias + ReLU of a hidden layer: bf16 into the wave's own LDS rows, the
 // m-block copy for the weight gradient, and the ReLU mask bits
-template <int RT, int CT>
-__device__ inline void ppo_hidden_epilogue(const f32x4 (&acc)[RT][CT], const float* __restrict__ bias, uint16_t* hbuf,
-                                           int hs, int arow0, uint16_t* Tout, int64_t tile_row0,
-                                           uint32_t (&bits)[RT][(CT + 7) / 8])
+// bias + ReLU of a column-split hidden layer: bf16 activations -> hbuf (A
+// operand of the next layer), m-block copy for the weight gradients, and the
+// ReLU pattern of the wave's columns (bit 4 ct + i of bits[rt]) for the
+// backward
+template <int TR, int CTW>
+__device__ inline void ppo_hidden_epilogue_cs(const f32x4 (&acc)[TR][CTW], const float* __restrict__ bias,
+                                              uint16_t* hbuf, int hs, int col0, int ncol, uint16_t* Tout,
+                                              int64_t tile_row0, uint32_t (&bits)[TR])
 {
     const int l = lane_id();
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int rt = 0; rt < TR; ++rt) bits[rt] = 0u;
 #pragma unroll
-        for (int w = 0; w < (CT + 7) / 8; ++w) bits[rt][w] = 0u;
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-        const int col = ct * 16 + (l & 15);
+    for (int ct = 0; ct < CTW; ++ct) {
+        const int col = col0 + ct * 16 + (l & 15);
         const float b = bias[col];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int rloc = arow0 + rt * 16 + 4 * (l >> 4);
+        for (int rt = 0; rt < TR; ++rt) {
+            const int rloc = rt * 16 + 4 * (l >> 4);
             float v[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float x = acc[rt][ct][i] + b;
+                const float x = acc[rt][ct][i] + b;
                 v[i] = x > 0.f ? x : 0.f;
-                if (x > 0.f) bits[rt][ct >> 3] |= 1u << ((ct & 7) * 4 + i);
+                bits[rt] |= (x > 0.f ? 1u : 0u) << (ct * 4 + i);
                 hbuf[(rloc + i) * hs + col] = f32_to_bf16(v[i]);
             }
-            store_mblock4(Tout, CT * 16, tile_row0 + rloc, col, v);
+            store_mblock4(Tout, ncol, tile_row0 + rloc, col, v);
         }
     }
 }
 
+// masked input gradient of a column-split layer -> m-blocks (and bf16 rows
+// into hbuf when hbuf is not null)
+template <int TR, int CTW>
+__device__ inline void ppo_masked_grad_cs(const f32x4 (&dh)[TR][CTW], const uint32_t (&bits)[TR], uint16_t* hbuf,
+                                          int hs, int col0, int ncol, uint16_t* Tout, int64_t tile_row0)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int ct = 0; ct < CTW; ++ct) {
+        const int col = col0 + ct * 16 + (l & 15);
+#pragma unroll
+        for (int rt = 0; rt < TR; ++rt) {
+            const int rloc = rt * 16 + 4 * (l >> 4);
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[i] = ((bits[rt] >> (ct * 4 + i)) & 1u) ? dh[rt][ct][i] : 0.f;
+                if (hbuf) hbuf[(rloc + i) * hs + col] = f32_to_bf16(v[i]);
+            }
+            store_mblock4(Tout, ncol, tile_row0 + rloc, col, v);
+        }
+    }
+}
+
+// Row tile of the PPO kernel: 64 rows, four waves; every H-wide product is
+// split by columns (wave w: all rows x columns [w H / 4, (w + 1) H / 4)).
 template <int H>
 struct PpoTile {
-    using T = MlpTile<H>;
-    static constexpr int YS = 128 + 8;  // LDS row stride of the dY chunk
+    static constexpr int TILE = 64, TR = 4, HS = H + 8, CTW = H / 64;
+    static constexpr int ZS = 132;  // fp32 row stride of the logit chunk
+    static constexpr int YS = 136;  // bf16 row stride of the dY chunk (aliases the logit chunk)
 };
 
 template <int H>
-size_t ppo_rows_lds_bytes(int W)
+size_t ppo_rows_lds_bytes(int W, int A1p)
 {
-    using T = MlpTile<H>;
-    return (size_t)T::TILE * T::HS * 2 + (size_t)T::TILE * PpoTile<H>::YS * 2 + (size_t)T::WBUF * 2 +
-           (size_t)T::TILE * 6 * 4 + (size_t)T::TILE * W * 4 + 64 * 4 + (size_t)(2 * H + 1024) * 4;
+    using P = PpoTile<H>;
+    return (size_t)P::TILE * P::HS * 2 + (size_t)P::TILE * P::ZS * 4 + (size_t)P::TILE * 6 * 4 +
+           (size_t)P::TILE * W * 4 + 64 * 4 + (size_t)(2 * H + A1p) * 4;
 }
 
+// One fused pass over a tile of minibatch rows: recompute the forward (bf16
+// MFMA), the masked-softmax statistics and the loss terms, then dY = dL/d
+// [logits | value], dh2 = (dY W3^T) * [h2 > 0] and dh1 = (dh2 W2^T) *
+// [h1 > 0].  The weight-gradient GEMMs read the m-block copies written here.
+// The workgroup's threads talk through LDS only.
 template <int H>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, H <= 256 ? 2 : 1)  // H <= 256: 73 KB of LDS, two workgroups per CU
 ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
                 const PpoBatchDev B, const PpoHp hp, const float* __restrict__ stats, int W,
                 uint16_t* __restrict__ Tobs, uint16_t* __restrict__ Th1, uint16_t* __restrict__ Th2,
                 uint16_t* __restrict__ TdY, uint16_t* __restrict__ Tdh2, uint16_t* __restrict__ Tdh1,
                 float* __restrict__ loss_parts)
 {
-    using T = MlpTile<H>;
-    constexpr int RT = T::RT, RPW = T::RPW, TILE = T::TILE, HS = T::HS, YS = PpoTile<H>::YS;
-    constexpr int CT = H / 16;
+    using P = PpoTile<H>;
+    constexpr int TILE = P::TILE, TR = P::TR, HS = P::HS, CTW = P::CTW, ZS = P::ZS, YS = P::YS;
     extern __shared__ __align__(16) unsigned char smem[];
-    uint16_t* hbuf = (uint16_t*)smem;
-    uint16_t* ybuf = hbuf + TILE * HS;
-    uint16_t* wbuf = ybuf + TILE * YS;
-    float* rinfo = (float*)(wbuf + T::WBUF);  // [6][TILE]: act, logp_old, val_old, adv_hat, ret, valid
-    uint32_t* smask = (uint32_t*)(rinfo + 6 * TILE);
-    float* lred = (float*)(smask + TILE * W);  // [4 waves][4]
-    float* sbias = lred + 64;                  // b1 [H], b2 [H], b3 [A1p] (zero padded)
+    uint16_t* hbuf = (uint16_t*)smem;                 // [TILE][HS] obs -> h1 -> h2 -> dh2
+    float* zbuf = (float*)(hbuf + TILE * HS);         // [TILE][ZS] logit chunk
+    uint16_t* ybuf = (uint16_t*)zbuf;                 // [TILE][YS] dY chunk once the logits are consumed
+    float* rinfo = zbuf + TILE * ZS;                  // [6][TILE]: act, logp_old, val_old, adv_hat, ret, valid
+    uint32_t* smask = (uint32_t*)(rinfo + 6 * TILE);  // [TILE][W]
+    float* lred = (float*)(smask + TILE * W);         // [4 waves][4]
+    float* sbias = lred + 64;                         // b1 [H], b2 [H], b3 [A1p] (zero padded)
 
-    const int wave = threadIdx.x >> 6, l = lane_id();
+    const int wave = threadIdx.x >> 6, l = lane_id(), q = l & 3;
     const int64_t tile_row0 = (int64_t)blockIdx.x * TILE;
-    const int arow0 = wave * RPW;
     const float inv_n = 1.0f / (float)B.rows;
+    const int col0 = wave * (H / 4);
 
     // gather the tile's samples
     for (int r = threadIdx.x; r < TILE; r += 256) {
         const int64_t j = tile_row0 + r;
         float va = 0.f, lpo = 0.f, vo = 0.f, ah = 0.f, rt = 0.f, valid = 0.f;
         if (j < B.rows) {
-            const int64_t s = sample_of(B, j);
-            va = __int_as_float(B.act[s]);
-            lpo = B.logp_old[s];
-            vo = B.val_old[s];
-            ah = (B.adv[s] - stats[0]) * stats[1];
-            rt = B.ret[s];
+            const int64_t sidx = sample_of(B, j);
+            va = __int_as_float(B.act[sidx]);
+            lpo = B.logp_old[sidx];
+            vo = B.val_old[sidx];
+            ah = (B.adv[sidx] - stats[0]) * stats[1];
+            rt = B.ret[sidx];
             valid = 1.f;
-            for (int w = 0; w < W; ++w) smask[r * W + w] = B.mask[s * W + w];
+            for (int w = 0; w < W; ++w) smask[r * W + w] = B.mask[sidx * W + w];
         } else {
             for (int w = 0; w < W; ++w) smask[r * W + w] = 0u;
         }
@@ -256,128 +286,127 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         if (j < B.rows && cc * 8 < d.Ds) v = *(const uint4*)(B.obs + sample_of(B, j) * d.Ds + cc * 8);
         *(uint4*)(hbuf + r * HS + cc * 8) = v;
     }
-    __syncthreads();
+    lds_barrier();
     // observation m-blocks for dW1: piece = (block, column, quarter of 8 rows)
     for (int p = threadIdx.x; p < (TILE / 32) * d.K1p * 4; p += 256) {
-        const int q = p & 3, col = (p >> 2) % d.K1p, blk = (p >> 2) / d.K1p;
+        const int qq = p & 3, col = (p >> 2) % d.K1p, blk = (p >> 2) / d.K1p;
         uint32_t w4[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int r0 = blk * 32 + q * 8 + 2 * k;
+            const int r0 = blk * 32 + qq * 8 + 2 * k;
             w4[k] = (uint32_t)hbuf[r0 * HS + col] | ((uint32_t)hbuf[(r0 + 1) * HS + col] << 16);
         }
         const int64_t mb = (tile_row0 >> 5) + blk;
-        *(uint4*)(Tobs + (mb * d.K1p + col) * 32 + q * 8) = uint4{w4[0], w4[1], w4[2], w4[3]};
+        *(uint4*)(Tobs + (mb * d.K1p + col) * 32 + qq * 8) = uint4{w4[0], w4[1], w4[2], w4[3]};
     }
 
-    f32x4 acc[RT][CT];
-    uint32_t m1[RT][(CT + 7) / 8], m2[RT][(CT + 7) / 8];
-    ECON_Q8_DECL;
-    dense_layer_pf<RT, H, H, T::DB>(acc, hbuf, HS, arow0, d.K1p, work + d.oW1f, (int64_t)H * 32, wbuf, false, work + d.oW2f,
-                             ECON_Q8_ARGS);
-    ppo_hidden_epilogue<RT, CT>(acc, sbias, hbuf, HS, arow0, Th1, tile_row0, m1);
-    dense_layer_pf<RT, H, 128, T::DB>(acc, hbuf, HS, arow0, H, work + d.oW2f, (int64_t)H * 32, wbuf, true, work + d.oW3f,
-                               ECON_Q8_ARGS);
-    ppo_hidden_epilogue<RT, CT>(acc, sbias + H, hbuf, HS, arow0, Th2, tile_row0, m2);
+    // ---- forward of the hidden layers (column split)
+    f32x4 acc[TR][CTW];
+    uint32_t m1[TR], m2[TR];
+    dense_cs<TR, CTW, 2>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
+    lds_barrier();  // every wave is done reading the observations
+    ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias, hbuf, HS, col0, H, Th1, tile_row0, m1);
+    lds_barrier();
+    dense_cs<TR, CTW, H / 32>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
+    lds_barrier();
+    ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias + H, hbuf, HS, col0, H, Th2, tile_row0, m2);
+    lds_barrier();
 
-    // ---- pass 1: statistics of the masked softmax, logit of the taken action, value
+    // Logit chunks: wave w computes columns [32 w, 32 w + 32) of the chunk for
+    // every row into LDS (fp32); then a quad of lanes owns a row (q = lane % 4
+    // takes the chunk's columns 32 q .. 32 q + 31).
     const float NEG = -__builtin_huge_valf();
-    float sm[RT][4], sS[RT][4], sT[RT][4], za[RT][4], zv[RT][4];
+    const int srow = wave * 16 + (l >> 2);
+    const int a_taken = __float_as_int(rinfo[srow]);
+    auto logit_chunk = [&](int c) {
+        f32x4 acc3[TR][2];
+        dense_cs<TR, 2, H / 32>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32, 32 * wave);
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+        for (int ct = 0; ct < 2; ++ct) {
+            const int cc = 32 * wave + ct * 16 + (l & 15);
+            const float b = sbias[2 * H + c * 128 + cc];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            sm[rt][i] = NEG;
-            sS[rt][i] = 0.f;
-            sT[rt][i] = 0.f;
-            za[rt][i] = 0.f;
-            zv[rt][i] = 0.f;
+            for (int rt = 0; rt < TR; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) zbuf[(rt * 16 + 4 * (l >> 4) + i) * ZS + cc] = acc3[rt][ct][i] + b;
         }
-    f32x4 acc3[RT][8];
+    };
+    auto load_row = [&](float (&z)[32]) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float4 v = *(const float4*)(zbuf + srow * ZS + 32 * q + 4 * j);
+            z[4 * j] = v.x;
+            z[4 * j + 1] = v.y;
+            z[4 * j + 2] = v.z;
+            z[4 * j + 3] = v.w;
+        }
+    };
+
+    // ---- pass 1: masked-softmax statistics, logit of the taken action, value
+    float sm = NEG, sS = 0.f, sT = 0.f, za = 0.f, zv = 0.f;
     for (int c = 0; c < d.NC; ++c) {
-        const uint16_t* next = c + 1 < d.NC ? work + d.oW3f + (int64_t)(c + 1) * 128 * 32 : nullptr;
-        dense_layer_pf<RT, 128, 128, T::DB>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32,
-                                     (int64_t)d.A1p * 32, wbuf, c == 0, next, ECON_Q8_ARGS);
-        float bcol[8];
+        logit_chunk(c);
+        lds_barrier();
+        float z[32];
+        load_row(z);
+        const int colq = c * 128 + 32 * q;
+        const int wi = c * 4 + q;
+        const uint32_t mw = wi < W ? smask[srow * W + wi] : 0u;
+        float zmax = NEG, zsel = 0.f, zval = 0.f;
 #pragma unroll
-        for (int ct = 0; ct < 8; ++ct) bcol[ct] = sbias[2 * H + c * 128 + ct * 16 + (l & 15)];
+        for (int j = 0; j < 32; ++j) {
+            const bool ok = colq + j < d.A && ((mw >> j) & 1u);
+            zmax = ok ? fmaxf(zmax, z[j]) : zmax;
+            zsel = colq + j == a_taken ? z[j] : zsel;
+            zval = colq + j == d.A ? z[j] : zval;
+        }
+        zmax = quad_max(zmax);
+        za += quad_sum(zsel);
+        zv += quad_sum(zval);
+        const bool any = zmax != NEG;
+        float se = 0.f, te = 0.f;
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int rloc = arow0 + rt * 16 + 4 * (l >> 4) + i;
-                const int a_taken = __float_as_int(rinfo[rloc]);
-                float zmax = NEG, zsel = 0.f, zval = 0.f;
-#pragma unroll
-                for (int ct = 0; ct < 8; ++ct) {
-                    const int col = c * 128 + ct * 16 + (l & 15);
-                    const float z = acc3[rt][ct][i] + bcol[ct];
-                    const bool ok = col < d.A && ((smask[rloc * W + (col >> 5)] >> (col & 31)) & 1u);
-                    if (ok) zmax = fmaxf(zmax, z);
-                    if (col == a_taken) zsel = z;
-                    if (col == d.A) zval = z;
-                }
-                zmax = group16_max(zmax);
-                za[rt][i] += group16_sum(zsel);
-                zv[rt][i] += group16_sum(zval);
-                if (zmax == NEG) continue;
-                float s = 0.f, t = 0.f;
-#pragma unroll
-                for (int ct = 0; ct < 8; ++ct) {
-                    const int col = c * 128 + ct * 16 + (l & 15);
-                    const float z = acc3[rt][ct][i] + bcol[ct];
-                    const bool ok = col < d.A && ((smask[rloc * W + (col >> 5)] >> (col & 31)) & 1u);
-                    if (ok) {
-                        const float e = __expf(z - zmax);
-                        s += e;
-                        t += e * (z - zmax);
-                    }
-                }
-                s = group16_sum(s);
-                t = group16_sum(t);
-                const float m = sm[rt][i], mn = fmaxf(m, zmax);
-                const float fo = m == NEG ? 0.f : __expf(m - mn), fc = __expf(zmax - mn);
-                sT[rt][i] = (m == NEG ? 0.f : fo * (sT[rt][i] + (m - mn) * sS[rt][i])) + fc * (t + (zmax - mn) * s);
-                sS[rt][i] = sS[rt][i] * fo + s * fc;
-                sm[rt][i] = mn;
-            }
+        for (int j = 0; j < 32; ++j) {
+            const bool ok = colq + j < d.A && ((mw >> j) & 1u);
+            const float e = ok ? __expf(z[j] - zmax) : 0.f;
+            se += e;
+            te += ok ? e * (z[j] - zmax) : 0.f;
+        }
+        se = quad_sum(se);
+        te = quad_sum(te);
+        const float mn = any ? fmaxf(sm, zmax) : sm;
+        const float fo = sm == NEG ? 0.f : __expf(sm - mn), fc = any ? __expf(zmax - mn) : 0.f;
+        sT = (sm == NEG ? 0.f : fo * (sT + (sm - mn) * sS)) + (any ? fc * (te + (zmax - mn) * se) : 0.f);
+        sS = sS * fo + se * fc;
+        sm = mn;
+        if (c + 1 < d.NC) lds_barrier();  // before the next chunk overwrites the logits
     }
 
     // ---- per-row loss terms and gradient coefficients
-    float lse[RT][4], ent[RT][4], cpg[RT][4], dzv[RT][4];
-    float part_pg = 0.f, part_vf = 0.f, part_ent = 0.f, part_clip = 0.f;
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int rloc = arow0 + rt * 16 + 4 * (l >> 4) + i;
-            const bool valid = rinfo[5 * TILE + rloc] != 0.f && sS[rt][i] > 0.f;
-            const float lS = valid ? __logf(sS[rt][i]) : 0.f;
-            lse[rt][i] = sm[rt][i] + lS;
-            const float h = valid ? lS - sT[rt][i] / sS[rt][i] : 0.f;
-            ent[rt][i] = h;
-            const float lpn = za[rt][i] - lse[rt][i];
-            const float ratio = __expf(lpn - rinfo[1 * TILE + rloc]);
-            const float ah = rinfo[3 * TILE + rloc];
-            const float s1 = ratio * ah;
-            const float rc = fminf(fmaxf(ratio, 1.f - hp.clip), 1.f + hp.clip);
-            const float s2 = rc * ah;
-            const bool active = !(s1 > s2);
-            cpg[rt][i] = valid ? (active ? -ah * ratio : 0.f) * inv_n : 0.f;
-            const float V = zv[rt][i], vo = rinfo[2 * TILE + rloc], R = rinfo[4 * TILE + rloc];
-            const float dvv = V - vo;
-            const float vc = vo + fminf(fmaxf(dvv, -hp.vclip), hp.vclip);
-            const float l1 = (V - R) * (V - R), l2 = (vc - R) * (vc - R);
-            const float gv = l1 >= l2 ? (V - R) : ((dvv >= -hp.vclip && dvv <= hp.vclip) ? (vc - R) : 0.f);
-            dzv[rt][i] = valid ? hp.vf_coef * gv * inv_n : 0.f;
-            if (valid && (l & 15) == 0) {
-                part_pg += -fminf(s1, s2);
-                part_vf += 0.5f * fmaxf(l1, l2);
-                part_ent += h;
-                part_clip += fabsf(ratio - 1.f) > hp.clip ? 1.f : 0.f;
-            }
-        }
+    const bool valid = rinfo[5 * TILE + srow] != 0.f && sS > 0.f;
+    const float lS = valid ? __logf(sS) : 0.f;
+    const float lse = sm + lS;
+    const float ent = valid ? lS - sT / sS : 0.f;
+    const float lpn = za - lse;
+    const float ratio = __expf(lpn - rinfo[1 * TILE + srow]);
+    const float ah = rinfo[3 * TILE + srow];
+    const float s1 = ratio * ah;
+    const float rc = fminf(fmaxf(ratio, 1.f - hp.clip), 1.f + hp.clip);
+    const float s2 = rc * ah;
+    const bool active = !(s1 > s2);
+    const float cpg = valid ? (active ? -ah * ratio : 0.f) * inv_n : 0.f;
+    const float V = zv, vo = rinfo[2 * TILE + srow], R = rinfo[4 * TILE + srow];
+    const float dvv = V - vo;
+    const float vc = vo + fminf(fmaxf(dvv, -hp.vclip), hp.vclip);
+    const float l1 = (V - R) * (V - R), l2 = (vc - R) * (vc - R);
+    const float gv = l1 >= l2 ? (V - R) : ((dvv >= -hp.vclip && dvv <= hp.vclip) ? (vc - R) : 0.f);
+    const float dzv = valid ? hp.vf_coef * gv * inv_n : 0.f;
     {
+        const bool cnt = valid && q == 0;
+        float part_pg = cnt ? -fminf(s1, s2) : 0.f;
+        float part_vf = cnt ? 0.5f * fmaxf(l1, l2) : 0.f;
+        float part_ent = cnt ? ent : 0.f;
+        float part_clip = cnt && fabsf(ratio - 1.f) > hp.clip ? 1.f : 0.f;
         part_pg = wave_sum(part_pg);
         part_vf = wave_sum(part_vf);
         part_ent = wave_sum(part_ent);
@@ -392,80 +421,67 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
 
     // ---- pass 2: dY = dL/d[logits | value] per chunk, dh2 += dY W3^T
     const float cent = hp.ent_coef * inv_n;
-    f32x4 dh[RT][CT];
+    f32x4 dh[TR][CTW];
     for (int c = 0; c < d.NC; ++c) {
-        if (d.NC > 1)
-            dense_layer<RT, 128, T::DB>(acc3, hbuf, HS, arow0, H, work + d.oW3f + (int64_t)c * 128 * 32,
-                                        (int64_t)d.A1p * 32, wbuf);
-        float bcol[8];
-#pragma unroll
-        for (int ct = 0; ct < 8; ++ct) bcol[ct] = sbias[2 * H + c * 128 + ct * 16 + (l & 15)];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int rloc0 = arow0 + rt * 16 + 4 * (l >> 4);
-#pragma unroll
-            for (int ct = 0; ct < 8; ++ct) {
-                const int col = c * 128 + ct * 16 + (l & 15);
-                float g[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int rloc = rloc0 + i;
-                    const float z = acc3[rt][ct][i] + bcol[ct];
-                    const bool ok = col < d.A && ((smask[rloc * W + (col >> 5)] >> (col & 31)) & 1u);
-                    float gg = 0.f;
-                    if (ok) {
-                        const float lp = z - lse[rt][i];
-                        const float p = __expf(lp);
-                        const int a_taken = __float_as_int(rinfo[rloc]);
-                        gg = cpg[rt][i] * ((col == a_taken ? 1.f : 0.f) - p) + cent * p * (lp + ent[rt][i]);
-                    } else if (col == d.A) {
-                        gg = dzv[rt][i];
-                    }
-                    g[i] = gg;
-                    ybuf[rloc * YS + ct * 16 + (l & 15)] = f32_to_bf16(gg);
-                }
-                store_mblock4(TdY, d.A1p, tile_row0 + rloc0, col, g);
-            }
+        if (d.NC > 1) {  // with one chunk its logits are still in LDS
+            lds_barrier();  // everyone is done with the previous chunk's dY
+            logit_chunk(c);
+            lds_barrier();
         }
-        dense_layer<RT, H, T::DB>(dh, ybuf, YS, arow0, 128, work + d.oW3b + (int64_t)c * 4 * H * 32, (int64_t)H * 32,
-                                  wbuf, c == 0);
+        float z[32];
+        load_row(z);
+        const int colq = c * 128 + 32 * q;
+        const int wi = c * 4 + q;
+        const uint32_t mw = wi < W ? smask[srow * W + wi] : 0u;
+        uint32_t gp[16];
+#pragma unroll
+        for (int j = 0; j < 32; j += 2) {
+            float g2[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int col = colq + j + h;
+                const bool ok = col < d.A && ((mw >> (j + h)) & 1u);
+                const float lp = z[j + h] - lse;
+                const float p = __expf(lp);
+                const float gg = cpg * ((col == a_taken ? 1.f : 0.f) - p) + cent * p * (lp + ent);
+                g2[h] = ok ? gg : (col == d.A ? dzv : 0.f);
+            }
+            gp[j >> 1] = f32_to_bf16(g2[0]) | (f32_to_bf16(g2[1]) << 16);
+        }
+        lds_barrier();  // every lane has read its logits: the chunk's space takes dY
+        uint32_t* yrow = (uint32_t*)(ybuf + srow * YS + 32 * q);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) yrow[j] = gp[j];
+        lds_barrier();
+        // dY m-blocks for dW3: piece = (block, column, quarter of 8 rows)
+        for (int p = threadIdx.x; p < (TILE / 32) * 128 * 4; p += 256) {
+            const int qq = p & 3, col = (p >> 2) & 127, blk = p >> 9;
+            uint32_t w4[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int r0 = blk * 32 + qq * 8 + 2 * k;
+                w4[k] = (uint32_t)ybuf[r0 * YS + col] | ((uint32_t)ybuf[(r0 + 1) * YS + col] << 16);
+            }
+            const int64_t mb = (tile_row0 >> 5) + blk;
+            *(uint4*)(TdY + (mb * d.A1p + c * 128 + col) * 32 + qq * 8) = uint4{w4[0], w4[1], w4[2], w4[3]};
+        }
+        if (c == 0)
+            dense_cs<TR, CTW, 4, true>(dh, ybuf, YS, work + d.oW3b, (int64_t)H * 32, col0);
+        else
+            dense_cs<TR, CTW, 4, false>(dh, ybuf, YS, work + d.oW3b + (int64_t)c * 4 * H * 32, (int64_t)H * 32, col0);
     }
 
     // ---- dh2 = (dY W3^T) * [h2 > 0] -> LDS (A operand of the next product) and m-blocks
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-        const int col = ct * 16 + (l & 15);
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int rloc = arow0 + rt * 16 + 4 * (l >> 4);
-            float v[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                v[i] = ((m2[rt][ct >> 3] >> ((ct & 7) * 4 + i)) & 1u) ? dh[rt][ct][i] : 0.f;
-                hbuf[(rloc + i) * HS + col] = f32_to_bf16(v[i]);
-            }
-            store_mblock4(Tdh2, H, tile_row0 + rloc, col, v);
-        }
-    }
+    lds_barrier();  // the activations h2 are no longer read
+    ppo_masked_grad_cs<TR, CTW>(dh, m2, hbuf, HS, col0, H, Tdh2, tile_row0);
+    lds_barrier();
     // ---- dh1 = (dh2 W2^T) * [h1 > 0] -> m-blocks
-    dense_layer<RT, H, T::DB>(dh, hbuf, HS, arow0, H, work + d.oW2b, (int64_t)H * 32, wbuf);
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-        const int col = ct * 16 + (l & 15);
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int rloc = arow0 + rt * 16 + 4 * (l >> 4);
-            float v[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = ((m1[rt][ct >> 3] >> ((ct & 7) * 4 + i)) & 1u) ? dh[rt][ct][i] : 0.f;
-            store_mblock4(Tdh1, H, tile_row0 + rloc, col, v);
-        }
-    }
-    __syncthreads();
+    dense_cs<TR, CTW, H / 32>(dh, hbuf, HS, work + d.oW2b, (int64_t)H * 32, col0);
+    ppo_masked_grad_cs<TR, CTW>(dh, m1, nullptr, HS, col0, H, Tdh1, tile_row0);
     if (threadIdx.x < 4) {
-        float s = 0.f;
-        for (int w = 0; w < 4; ++w) s += lred[w * 4 + threadIdx.x];
-        loss_parts[(int64_t)blockIdx.x * 4 + threadIdx.x] = s;
+        float sum = 0.f;
+        for (int w = 0; w < 4; ++w) sum += lred[w * 4 + threadIdx.x];
+        loss_parts[(int64_t)blockIdx.x * 4 + threadIdx.x] = sum;
     }
 }
 
@@ -603,7 +619,7 @@ struct PpoWorkspace {
 
 static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static int ppo_tile_rows(int H) { return H <= 256 ? 128 : 64; }
+static int ppo_tile_rows(int) { return 64; }
 
 static int ppo_workspace(const MlpDims& d, int64_t rows, PpoWorkspace* w)
 {
@@ -661,7 +677,7 @@ static int launch_rows(const MlpDims& d, const float* params, const uint16_t* wo
                        const PpoHp& hp, const float* stats, int W, uint16_t* const* T, float* loss_parts, int64_t ntiles,
                        hipStream_t st)
 {
-    const size_t lds = ppo_rows_lds_bytes<H>(W);
+    const size_t lds = ppo_rows_lds_bytes<H>(W, d.A1p);
     ppo_rows_kernel<H><<<(unsigned)ntiles, 256, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[1], T[2], T[3],
                                                            T[4], T[5], loss_parts);
     EJ_LAUNCH_CHECK();
