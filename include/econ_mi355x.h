@@ -197,8 +197,8 @@ int ej_env_status(ej_env* env, int64_t* h_invalid_actions, int64_t* h_invalid_go
  * ------------------------------------------------------------------------ */
 typedef struct ej_mlp_desc {
     int32_t D, D_stride, H, A;
-    int32_t tile_rows; /* rows per workgroup of the policy forward: 0 (default: 128 for H <= 256,
-                          64 for H = 512), 64 or 128 (H <= 256); chosen by the autotuner */
+    int32_t tile_rows; /* rows per workgroup of the policy forward: 0 (default, 64), 64, or 128
+                          (H <= 256 only); chosen by the autotuner */
 } ej_mlp_desc;
 
 typedef struct ej_mlp_layout_t {

@@ -348,7 +348,7 @@ int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_
     if (M == 0) return EJ_OK;
     const int W = (m->A + 31) / 32;
     hipStream_t st = (hipStream_t)stream;
-    const bool small = m->tile_rows == 64 || m->H == 512;
+    const bool small = m->tile_rows != 128 || m->H == 512;  // 64-row tiles unless 128 is asked for
 #define EJ_POLICY(HH, RR) \
     launch_policy_forward<HH, RR>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_ctr_base, d_act, d_logp, d_val, \
                                   d_ent, d_logits, st)

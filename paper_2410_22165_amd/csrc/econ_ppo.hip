@@ -584,12 +584,26 @@ __global__ void dw_reduce_kernel(const float* __restrict__ part, const float* __
     }
 }
 
-// minibatch means of the four loss terms from the per-tile partial sums; one 256-thread workgroup
-__global__ void __launch_bounds__(256) loss_final_kernel(const float* __restrict__ parts, int nparts, int64_t rows,
-                                                         float* __restrict__ out)
+// minibatch means of the four loss terms from the per-tile partial sums: the
+// tiles are cut into fixed slices (one workgroup each, partial sums in
+// double), then one workgroup adds the slices in order
+__global__ void __launch_bounds__(256) loss_slices_kernel(const float* __restrict__ parts, int nparts, int nslices,
+                                                          double* __restrict__ slice_sums)
+{
+    const int64_t b0 = (int64_t)nparts * blockIdx.x / nslices, b1 = (int64_t)nparts * (blockIdx.x + 1) / nslices;
+    double t[4];
+    block_sum_records<4>(parts + 4 * b0, b1 - b0, t);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) slice_sums[4 * blockIdx.x + c] = t[c];
+    }
+}
+
+__global__ void __launch_bounds__(256) loss_final_kernel(const double* __restrict__ slice_sums, int nslices,
+                                                         int64_t rows, float* __restrict__ out)
 {
     double t[4];
-    block_sum_records<4>(parts, nparts, t);
+    block_sum_records<4>(slice_sums, nslices, t);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) out[c] = (float)(t[c] / (double)rows);
@@ -614,7 +628,8 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
 // ---------------------------------------------------------------------------
 struct PpoWorkspace {
     int64_t nmb, ntiles, G;
-    size_t o_obs, o_h1, o_h2, o_dy, o_dh2, o_dh1, o_p1, o_p2, o_p3, o_c1, o_c2, o_c3, o_adv, o_stats, o_loss, bytes;
+    size_t o_obs, o_h1, o_h2, o_dy, o_dh2, o_dh1, o_p1, o_p2, o_p3, o_c1, o_c2, o_c3, o_adv, o_stats, o_loss, o_lslices,
+        bytes;
 };
 
 static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -645,6 +660,7 @@ static int ppo_workspace(const MlpDims& d, int64_t rows, PpoWorkspace* w)
     w->o_adv = o; o = al256(o + 2 * 1024 * 8);
     w->o_stats = o; o = al256(o + 16);
     w->o_loss = o; o = al256(o + (size_t)w->ntiles * 16);
+    w->o_lslices = o; o = al256(o + 256 * 4 * 8);
     w->bytes = o;
     return EJ_OK;
 }
@@ -772,7 +788,11 @@ int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t*
     dw_reduce_kernel<<<red_blocks((int64_t)d.H * d.A1p + d.A1p), 256, 0, st>>>(p3, c3, d.H, d.A1p, G, d.H, d.A1,
                                                                               d_grads, d.oW3, d.A1, d.ob3);
     EJ_LAUNCH_CHECK();
-    loss_final_kernel<<<1, 256, 0, st>>>(lparts, (int)w.ntiles, b->rows, d_loss);
+    const int nslices = (int)(w.ntiles < 256 ? w.ntiles : 256);
+    double* lslices = (double*)(ws + w.o_lslices);
+    loss_slices_kernel<<<nslices, 256, 0, st>>>(lparts, (int)w.ntiles, nslices, lslices);
+    EJ_LAUNCH_CHECK();
+    loss_final_kernel<<<1, 256, 0, st>>>(lslices, nslices, b->rows, d_loss);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }
