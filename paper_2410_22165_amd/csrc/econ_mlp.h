@@ -197,12 +197,12 @@ __device__ inline void dense_layer(f32x4 (&acc)[RT][N / 16], const uint16_t* abu
 // `abuf` (row stride `as`) by its own CTW x 16 columns of the weights,
 // starting at column `col0`.  B fragments come straight from global memory
 // (L2-resident weights in the K-chunk layout: lane l reads the 16 bytes of
-// column l % 16, k = 8 (l / 16) .. + 7), two k-steps ahead of the MFMAs;
+// column l % 16, k = 8 (l / 16) .. + 7), PF k-steps ahead of the MFMAs;
 // A fragments come from LDS one k-step ahead.  Every A fragment feeds CTW
 // MFMAs and every B fragment TR, and no weight passes through LDS.  The
 // caller synchronises before (abuf complete) and after (before abuf is
 // overwritten).  ZERO = false accumulates onto acc.
-template <int TR, int CTW, int NK, bool ZERO = true>
+template <int TR, int CTW, int NK, bool ZERO = true, int PF = 2, bool PIN = false>
 __device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int as,
                                 const uint16_t* __restrict__ wglob, int64_t kstride, int col0)
 {
@@ -210,7 +210,6 @@ __device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int
     const int l = lane_id();
     const uint16_t* bp = wglob + (int64_t)(col0 + (l & 15)) * 32 + 8 * (l >> 4);
     const uint16_t* ap = abuf + (l & 15) * as + 8 * (l >> 4);
-    constexpr int PF = 2;
     bf16x8 bq[NK][CTW];
     bf16x8 aq[NK][TR];
 #pragma unroll
@@ -228,6 +227,9 @@ __device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int
         if (kt + 1 < NK)
 #pragma unroll
             for (int rt = 0; rt < TR; ++rt) aq[kt + 1][rt] = lds_frag(ap + rt * 16 * as + (kt + 1) * 32);
+        // PIN keeps the loads here (the scheduler otherwise sinks each one next
+        // to its first MFMA, trading latency hiding for registers)
+        if constexpr (PIN) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ct = 0; ct < CTW; ++ct)
 #pragma unroll
@@ -255,6 +257,12 @@ __device__ inline void epilogue_relu_cs(const f32x4 (&acc)[TR][CTW], const float
             }
     }
 }
+
+// fp32 logit chunk in LDS: a row's 128 columns as four 32-column quarters,
+// each padded to ZQ words, so that the four lanes reading one row's quarters
+// (and the rows a wave reads together) fall on distinct banks
+constexpr int ZQ = 36, ZS = 4 * ZQ;
+__device__ inline int zcol(int cc) { return (cc >> 5) * ZQ + (cc & 31); }
 
 // bias + ReLU, rounded to bf16, written to the wave's own rows of hbuf
 template <int RT, int CT>

@@ -20,10 +20,6 @@
 
 namespace econ {
 
-// LDS row stride (floats) of the fp32 logit chunk: 128 + 4 keeps the rows
-// read by one wave on distinct banks
-constexpr int ZS = 132;
-
 // LDS bytes: activations (aliased by the logit chunk when there is only one
 // chunk), mask words, uniforms, biases
 template <int H, int RPW>
@@ -127,7 +123,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
 #pragma unroll
                 for (int rt = 0; rt < TR; ++rt)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) zbuf[(rt * 16 + 4 * (l >> 4) + i) * ZS + cc] = acc3[rt][ct][i] + b;
+                    for (int i = 0; i < 4; ++i) zbuf[(rt * 16 + 4 * (l >> 4) + i) * ZS + zcol(cc)] = acc3[rt][ct][i] + b;
             }
         }
         __syncthreads();  // the chunk's logits and uniforms are in LDS
@@ -138,7 +134,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
             float z[32];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                const float4 v = *(const float4*)(zbuf + rloc * ZS + 32 * q + 4 * j);
+                const float4 v = *(const float4*)(zbuf + rloc * ZS + q * ZQ + 4 * j);
                 z[4 * j] = v.x;
                 z[4 * j + 1] = v.y;
                 z[4 * j + 2] = v.z;

@@ -138,27 +138,15 @@ __global__ void __launch_bounds__(256) adv_stats_final(const double* __restrict_
 // ---------------------------------------------------------------------------
 // the fused row kernel
 // ---------------------------------------------------------------------------
-// 4 consecutive rows (acc element order) of one column -> 8-byte store in the m-block layout
-__device__ inline void store_mblock4(uint16_t* T, int ncol, int64_t jrow, int col, const float (&v)[4])
-{
-    const int64_t mb = jrow >> 5;
-    const int r = (int)(jrow & 31);
-    uint2 p;
-    p.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
-    p.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
-    *(uint2*)(T + (mb * ncol + col) * 32 + r) = p;
-}
 
 // bias + ReLU of a hidden layer: bf16 into the wave's own LDS rows, the
 // m-block copy for the weight gradient, and the ReLU mask bits
 // bias + ReLU of a column-split hidden layer: bf16 activations -> hbuf (A
-// operand of the next layer), m-block copy for the weight gradients, and the
-// ReLU pattern of the wave's columns (bit 4 ct + i of bits[rt]) for the
-// backward
+// operand of the next layer and source of the m-block copy), and the ReLU
+// pattern of the wave's columns (bit 4 ct + i of bits[rt]) for the backward
 template <int TR, int CTW>
 __device__ inline void ppo_hidden_epilogue_cs(const f32x4 (&acc)[TR][CTW], const float* __restrict__ bias,
-                                              uint16_t* hbuf, int hs, int col0, int ncol, uint16_t* Tout,
-                                              int64_t tile_row0, uint32_t (&bits)[TR])
+                                              uint16_t* hbuf, int hs, int col0, uint32_t (&bits)[TR])
 {
     const int l = lane_id();
 #pragma unroll
@@ -168,42 +156,51 @@ __device__ inline void ppo_hidden_epilogue_cs(const f32x4 (&acc)[TR][CTW], const
         const int col = col0 + ct * 16 + (l & 15);
         const float b = bias[col];
 #pragma unroll
-        for (int rt = 0; rt < TR; ++rt) {
-            const int rloc = rt * 16 + 4 * (l >> 4);
-            float v[4];
+        for (int rt = 0; rt < TR; ++rt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float x = acc[rt][ct][i] + b;
-                v[i] = x > 0.f ? x : 0.f;
                 bits[rt] |= (x > 0.f ? 1u : 0u) << (ct * 4 + i);
-                hbuf[(rloc + i) * hs + col] = f32_to_bf16(v[i]);
+                hbuf[(rt * 16 + 4 * (l >> 4) + i) * hs + col] = f32_to_bf16(x > 0.f ? x : 0.f);
             }
-            store_mblock4(Tout, ncol, tile_row0 + rloc, col, v);
-        }
     }
 }
 
-// masked input gradient of a column-split layer -> m-blocks (and bf16 rows
-// into hbuf when hbuf is not null)
+// masked input gradient of a column-split layer -> bf16 rows in hbuf
 template <int TR, int CTW>
 __device__ inline void ppo_masked_grad_cs(const f32x4 (&dh)[TR][CTW], const uint32_t (&bits)[TR], uint16_t* hbuf,
-                                          int hs, int col0, int ncol, uint16_t* Tout, int64_t tile_row0)
+                                          int hs, int col0)
 {
     const int l = lane_id();
 #pragma unroll
     for (int ct = 0; ct < CTW; ++ct) {
         const int col = col0 + ct * 16 + (l & 15);
 #pragma unroll
-        for (int rt = 0; rt < TR; ++rt) {
-            const int rloc = rt * 16 + 4 * (l >> 4);
-            float v[4];
+        for (int rt = 0; rt < TR; ++rt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                v[i] = ((bits[rt] >> (ct * 4 + i)) & 1u) ? dh[rt][ct][i] : 0.f;
-                if (hbuf) hbuf[(rloc + i) * hs + col] = f32_to_bf16(v[i]);
-            }
-            store_mblock4(Tout, ncol, tile_row0 + rloc, col, v);
+            for (int i = 0; i < 4; ++i)
+                hbuf[(rt * 16 + 4 * (l >> 4) + i) * hs + col] =
+                    f32_to_bf16(((bits[rt] >> (ct * 4 + i)) & 1u) ? dh[rt][ct][i] : 0.f);
+    }
+}
+
+// m-block copy of an LDS tile: rows [0, rows) x columns [0, ncol) of a bf16
+// tile (row stride hs) -> T[(mb0 + row / 32) ncol_total + col_off + col][32];
+// one 16-byte store per (32-row block, column, quarter of 8 rows), so each
+// column's 64 bytes of a block leave in one coalesced piece.  All threads call it.
+__device__ inline void tile_to_mblocks(const uint16_t* tile, int hs, int rows, int ncol, uint16_t* T, int64_t mb0,
+                                       int ncol_total, int col_off)
+{
+    const int np = (rows / 32) * ncol * 4;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        const int qq = p & 3, col = (p >> 2) % ncol, blk = (p >> 2) / ncol;
+        uint32_t w4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r0 = blk * 32 + qq * 8 + 2 * k;
+            w4[k] = (uint32_t)tile[r0 * hs + col] | ((uint32_t)tile[(r0 + 1) * hs + col] << 16);
         }
+        *(uint4*)(T + ((mb0 + blk) * ncol_total + col_off + col) * 32 + qq * 8) = uint4{w4[0], w4[1], w4[2], w4[3]};
     }
 }
 
@@ -212,7 +209,6 @@ __device__ inline void ppo_masked_grad_cs(const f32x4 (&dh)[TR][CTW], const uint
 template <int H>
 struct PpoTile {
     static constexpr int TILE = 64, TR = 4, HS = H + 8, CTW = H / 64;
-    static constexpr int ZS = 132;  // fp32 row stride of the logit chunk
     static constexpr int YS = 136;  // bf16 row stride of the dY chunk (aliases the logit chunk)
 };
 
@@ -220,7 +216,7 @@ template <int H>
 size_t ppo_rows_lds_bytes(int W, int A1p)
 {
     using P = PpoTile<H>;
-    return (size_t)P::TILE * P::HS * 2 + (size_t)P::TILE * P::ZS * 4 + (size_t)P::TILE * 6 * 4 +
+    return (size_t)P::TILE * P::HS * 2 + (size_t)P::TILE * ZS * 4 + (size_t)P::TILE * 6 * 4 +
            (size_t)P::TILE * W * 4 + 64 * 4 + (size_t)(2 * H + A1p) * 4;
 }
 
@@ -238,7 +234,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
                 float* __restrict__ loss_parts)
 {
     using P = PpoTile<H>;
-    constexpr int TILE = P::TILE, TR = P::TR, HS = P::HS, CTW = P::CTW, ZS = P::ZS, YS = P::YS;
+    constexpr int TILE = P::TILE, TR = P::TR, HS = P::HS, CTW = P::CTW, YS = P::YS;
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* hbuf = (uint16_t*)smem;                 // [TILE][HS] obs -> h1 -> h2 -> dh2
     float* zbuf = (float*)(hbuf + TILE * HS);         // [TILE][ZS] logit chunk
@@ -287,30 +283,23 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         *(uint4*)(hbuf + r * HS + cc * 8) = v;
     }
     lds_barrier();
-    // observation m-blocks for dW1: piece = (block, column, quarter of 8 rows)
-    for (int p = threadIdx.x; p < (TILE / 32) * d.K1p * 4; p += 256) {
-        const int qq = p & 3, col = (p >> 2) % d.K1p, blk = (p >> 2) / d.K1p;
-        uint32_t w4[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int r0 = blk * 32 + qq * 8 + 2 * k;
-            w4[k] = (uint32_t)hbuf[r0 * HS + col] | ((uint32_t)hbuf[(r0 + 1) * HS + col] << 16);
-        }
-        const int64_t mb = (tile_row0 >> 5) + blk;
-        *(uint4*)(Tobs + (mb * d.K1p + col) * 32 + qq * 8) = uint4{w4[0], w4[1], w4[2], w4[3]};
-    }
+    const int64_t mb0 = tile_row0 >> 5;
+    tile_to_mblocks(hbuf, HS, TILE, d.K1p, Tobs, mb0, d.K1p, 0);  // observations for dW1
 
-    // ---- forward of the hidden layers (column split)
+    // ---- forward of the hidden layers (column split); every layer's bf16
+    // output also leaves as m-blocks for the weight gradients
     f32x4 acc[TR][CTW];
     uint32_t m1[TR], m2[TR];
     dense_cs<TR, CTW, 2>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
     lds_barrier();  // every wave is done reading the observations
-    ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias, hbuf, HS, col0, H, Th1, tile_row0, m1);
+    ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias, hbuf, HS, col0, m1);
     lds_barrier();
-    dense_cs<TR, CTW, H / 32>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
+    tile_to_mblocks(hbuf, HS, TILE, H, Th1, mb0, H, 0);
+    dense_cs<TR, CTW, H / 32, true, 3, true>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
     lds_barrier();
-    ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias + H, hbuf, HS, col0, H, Th2, tile_row0, m2);
+    ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias + H, hbuf, HS, col0, m2);
     lds_barrier();
+    tile_to_mblocks(hbuf, HS, TILE, H, Th2, mb0, H, 0);
 
     // Logit chunks: wave w computes columns [32 w, 32 w + 32) of the chunk for
     // every row into LDS (fp32); then a quad of lanes owns a row (q = lane % 4
@@ -328,13 +317,13 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
 #pragma unroll
             for (int rt = 0; rt < TR; ++rt)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) zbuf[(rt * 16 + 4 * (l >> 4) + i) * ZS + cc] = acc3[rt][ct][i] + b;
+                for (int i = 0; i < 4; ++i) zbuf[(rt * 16 + 4 * (l >> 4) + i) * ZS + zcol(cc)] = acc3[rt][ct][i] + b;
         }
     };
     auto load_row = [&](float (&z)[32]) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const float4 v = *(const float4*)(zbuf + srow * ZS + 32 * q + 4 * j);
+            const float4 v = *(const float4*)(zbuf + srow * ZS + q * ZQ + 4 * j);
             z[4 * j] = v.x;
             z[4 * j + 1] = v.y;
             z[4 * j + 2] = v.z;
@@ -449,22 +438,11 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
             gp[j >> 1] = f32_to_bf16(g2[0]) | (f32_to_bf16(g2[1]) << 16);
         }
         lds_barrier();  // every lane has read its logits: the chunk's space takes dY
-        uint32_t* yrow = (uint32_t*)(ybuf + srow * YS + 32 * q);
+        uint4* yrow = (uint4*)(ybuf + srow * YS + 32 * q);  // 16-byte stores: no bank conflicts
 #pragma unroll
-        for (int j = 0; j < 16; ++j) yrow[j] = gp[j];
+        for (int j = 0; j < 4; ++j) yrow[j] = uint4{gp[4 * j], gp[4 * j + 1], gp[4 * j + 2], gp[4 * j + 3]};
         lds_barrier();
-        // dY m-blocks for dW3: piece = (block, column, quarter of 8 rows)
-        for (int p = threadIdx.x; p < (TILE / 32) * 128 * 4; p += 256) {
-            const int qq = p & 3, col = (p >> 2) & 127, blk = p >> 9;
-            uint32_t w4[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int r0 = blk * 32 + qq * 8 + 2 * k;
-                w4[k] = (uint32_t)ybuf[r0 * YS + col] | ((uint32_t)ybuf[(r0 + 1) * YS + col] << 16);
-            }
-            const int64_t mb = (tile_row0 >> 5) + blk;
-            *(uint4*)(TdY + (mb * d.A1p + c * 128 + col) * 32 + qq * 8) = uint4{w4[0], w4[1], w4[2], w4[3]};
-        }
+        tile_to_mblocks(ybuf, YS, TILE, 128, TdY, mb0, d.A1p, c * 128);  // dY for dW3
         if (c == 0)
             dense_cs<TR, CTW, 4, true>(dh, ybuf, YS, work + d.oW3b, (int64_t)H * 32, col0);
         else
@@ -473,11 +451,15 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
 
     // ---- dh2 = (dY W3^T) * [h2 > 0] -> LDS (A operand of the next product) and m-blocks
     lds_barrier();  // the activations h2 are no longer read
-    ppo_masked_grad_cs<TR, CTW>(dh, m2, hbuf, HS, col0, H, Tdh2, tile_row0);
+    ppo_masked_grad_cs<TR, CTW>(dh, m2, hbuf, HS, col0);
     lds_barrier();
+    tile_to_mblocks(hbuf, HS, TILE, H, Tdh2, mb0, H, 0);
     // ---- dh1 = (dh2 W2^T) * [h1 > 0] -> m-blocks
-    dense_cs<TR, CTW, H / 32>(dh, hbuf, HS, work + d.oW2b, (int64_t)H * 32, col0);
-    ppo_masked_grad_cs<TR, CTW>(dh, m1, nullptr, HS, col0, H, Tdh1, tile_row0);
+    dense_cs<TR, CTW, H / 32, true, 3, true>(dh, hbuf, HS, work + d.oW2b, (int64_t)H * 32, col0);
+    lds_barrier();  // everyone is done reading dh2
+    ppo_masked_grad_cs<TR, CTW>(dh, m1, hbuf, HS, col0);
+    lds_barrier();
+    tile_to_mblocks(hbuf, HS, TILE, H, Tdh1, mb0, H, 0);
     if (threadIdx.x < 4) {
         float sum = 0.f;
         for (int w = 0; w < 4; ++w) sum += lred[w * 4 + threadIdx.x];
