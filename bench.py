@@ -123,6 +123,13 @@ def ppo_benchmark(updates: int = 1):
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    # the same rollout from per-step host launches, for the graph's speed-up
+    ev[0].record(s)
+    tr.collect(graph=False)
+    ev[1].record(s)
+    torch.cuda.synchronize()
+    t_plain = ev[0].elapsed_time(ev[1])
+    tr.next_rollout()
     t_roll = t_upd = 0.0
     for _ in range(updates):
         ev[0].record(s)
@@ -139,9 +146,74 @@ def ppo_benchmark(updates: int = 1):
     return {"value": round(samples / ((t_roll + t_upd) / 1e3), 1), "unit": "samples/s",
             "update_only": round(samples / (t_upd / 1e3), 1), "rollout_ms": round(t_roll / updates, 3),
             "update_ms": round(t_upd / updates, 3), "samples_per_update": tr.M_total,
+            "rollout_plain_ms": round(t_plain, 3), "rollout_x_vs_plain": round(t_plain / (t_roll / updates), 4),
             "workload": f"{POLICY_WORKLOAD}: E={cfg['E']} N={cfg['N']} T={wl['rollout']} "
                         f"{wl['epochs']}x{wl['minibatches']} minibatches, hidden {wl['hidden']}",
             "last_loss_terms": [round(x, 5) for x in terms]}
+
+
+def rollout_benchmark(name: str, H: int, steps: int = 40, graph_steps: int = 20, n_per_env=None):
+    """Rollout steps (policy forward + government draw + economy step) on one
+    workload: plain per-step launches with one workgroup per economy against
+    the autotuned launch shapes replayed from a captured graph."""
+    import torch
+
+    from paper_2410_22165_amd import autotune, binding
+
+    wl = W.workload(name)
+    cfg = wl["env"]
+    env = binding.Env(cfg, W.obs_scales(cfg), n_per_env)
+    b = env.buffers()
+    M, A, D, Ds = env.M, env.A, env.D, env.Ds
+    mlp = binding.Mlp(D, Ds, H, A, W.policy_weights(D, H, A, seed=0))
+    dev = torch.device("cuda")
+    act = torch.zeros(M, dtype=torch.int32, device=dev)
+    logp, val, ent = (torch.zeros(M, device=dev) for _ in range(3))
+    ctr_base = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    env.observe(b["obs"], b["mask"])
+
+    def step(i):
+        mlp.forward(b["obs"], b["mask"], M, 1, i, act, logp, val, ent, ctr_base=ctr_base)
+        env.random_actions(2, None, b["gov"])
+        env.step(act, b["gov"], b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    env.set_launch(0, 0)
+    for i in range(5):
+        step(i)
+    ms_plain = timed(lambda: step(0), steps) / steps
+    tuned_env = autotune.tune_env(env, dict(b, act=act), use_cache=False)
+    tuned_pol = autotune.tune_policy(mlp, b["obs"], b["mask"], M, (act, logp, val, ent), use_cache=False)
+    for i in range(3):
+        step(i)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for i in range(graph_steps):
+            step(i)
+        binding.counter_add(ctr_base, graph_steps)
+    graph.replay()
+    reps = max(1, steps // graph_steps)
+    ms_graph = timed(graph.replay, reps) / (reps * graph_steps)
+    env.close()
+    del graph
+    return {"workload": name, "economies": cfg["E"], "agents": int(M), "hidden": H,
+            "value": round(M / (ms_graph / 1e3), 1), "unit": "agent-steps/s",
+            "plain_ms_per_step": round(ms_plain, 5), "graph_ms_per_step": round(ms_graph, 5),
+            "x_vs_plain": round(ms_plain / ms_graph, 4),
+            "env_launch": {"mode": tuned_env["mode"], "workgroups": tuned_env["workgroups"]},
+            "policy_tile_rows": tuned_pol["tile_rows"]}
 
 
 def main():
@@ -151,6 +223,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ppo", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the uneven-population and 1000-agent rollouts")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--graph-steps", type=int, default=50)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -302,6 +375,11 @@ def main():
     del graph
     if not args.no_ppo:
         out["ppo"] = ppo_benchmark()
+    if not args.no_extra:
+        wl4 = W.workload("econ_e512_uneven")
+        ns = W.uneven_populations(wl4["env"]["E"], wl4["n_min"], wl4["n_max"], seed=0)
+        out["uneven"] = rollout_benchmark("econ_e512_uneven", 256, n_per_env=ns)
+        out["large"] = rollout_benchmark("econ_e256_n1000_ppo", W.workload("econ_e256_n1000_ppo")["hidden"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, weights, args.cpu_budget)
         out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)
