@@ -157,13 +157,13 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
             }
             const float mc = quad_max(zmax);
             const bool any = mc != NEG;
-            float e[32], own = 0.f, tl = 0.f;
+            float own = 0.f, tl = 0.f;
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
                 const bool ok = colq + j < d.A && ((mw >> j) & 1u);
-                e[j] = ok ? __expf(z[j] - mc) : 0.f;
-                tl += ok ? e[j] * (z[j] - mc) : 0.f;
-                own += e[j];
+                const float e = ok ? __expf(z[j] - mc) : 0.f;
+                tl += ok ? e * (z[j] - mc) : 0.f;
+                own += e;
             }
             const float before = quad_scan(own, q) - own;
             const float Sc = quad_sum(own);
@@ -184,7 +184,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
                 const bool ok = colq + j < d.A && ((mw >> j) & 1u);
-                cum += e[j];
+                cum += ok ? __expf(z[j] - mc) : 0.f;  // the same weights, recomputed (registers)
                 key = (ok && cum > target && key == (1 << 20)) ? 32 * q + j : key;
                 last = ok ? 32 * q + j : last;
             }
