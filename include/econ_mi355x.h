@@ -142,6 +142,7 @@ int ej_env_reset(ej_env* env, int32_t episode, void* stream);
  *             and are counted (ej_env_status).
  *   d_gov     [E * K] int32 government levels 0..20, read at the first step of a
  *             tax period (t mod P_tax == 0); out-of-range levels keep the old rate.
+ *             NULL when ej_env_set_gov_draw enabled the step's own draw.
  *   d_rew     [M] float  u(t+1) - u(t) (Eq. (1), Eq. (2)), difference in fp64
  *   d_gov_rew [E] float  change of Eq * Prod (Eqs. (3)-(5))
  *   d_done    [M] uint8  1 when the step ended the episode (the economy then
@@ -158,6 +159,14 @@ int ej_env_step(ej_env* env, const int32_t* d_act, const int32_t* d_gov, float* 
  * the queue resets itself at the end of every launch, so the call can be
  * captured in a graph and replayed.  Results are identical in both modes. */
 int ej_env_set_launch(ej_env* env, int32_t mode, int32_t workgroups);
+
+/* Government levels drawn by the step itself (ej_env_step with d_gov = NULL):
+ * uniform over 0..20, exactly the levels ej_env_random_actions(env, seed, ...)
+ * would write for the same step, drawn only where a tax period starts (the
+ * only steps that read them; Sec. 3 "Setting tax rates").  For workloads whose
+ * government acts at random; saves a launch per step.  enabled = 0 turns it
+ * off (then d_gov is required again). */
+int ej_env_set_gov_draw(ej_env* env, int32_t enabled, uint64_t seed);
 
 /* Observation of the current state.  d_obs / d_mask as in ej_env_step (both
  * required); d_gov_obs [E * D_gov] float, nullable: per-feature mean, std and

@@ -94,6 +94,7 @@ def lib():
     L.ej_env_set_state.argtypes = [vp, C.POINTER(EjStateView), vp]
     L.ej_env_status.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), vp]
     L.ej_env_set_launch.argtypes = [vp, i32, i32]
+    L.ej_env_set_gov_draw.argtypes = [vp, i32, C.c_uint64]
     _declare_learner(L)
     _lib = L
     return L
@@ -222,6 +223,10 @@ class Env:
     def set_launch(self, mode: int, workgroups: int = 0):
         """mode 0: one workgroup per economy; 1: persistent work queue."""
         check(lib().ej_env_set_launch(self._h, mode, workgroups), "ej_env_set_launch")
+
+    def set_gov_draw(self, enabled: bool, seed: int = 0):
+        """Let step() draw uniform government levels itself (gov=None)."""
+        check(lib().ej_env_set_gov_draw(self._h, int(enabled), seed), "ej_env_set_gov_draw")
 
     def status(self, stream=None):
         a, g = C.c_int64(), C.c_int64()

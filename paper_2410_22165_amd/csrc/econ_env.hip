@@ -40,6 +40,8 @@ struct EnvParams {
     int32_t A, W, D, Ds, Dg, HB;
     double eta, omega;
     uint64_t seed;
+    uint64_t gov_seed;  // government levels drawn in the step when gov_draw != 0 and no levels are passed
+    int32_t gov_draw;
     int64_t Ntot;  // stride between two state fields
     int32_t prices[EJ_MAX_P];
     int32_t cutoffs[EJ_MAX_K];
@@ -659,6 +661,13 @@ __device__ inline void write_mask_row(const EnvParams& P, const Lds& L, const Ag
     }
 }
 
+// uniform government level 0..20 of bracket b at step t (economy e, episode ep)
+__device__ inline int32_t gov_level_draw(uint64_t seed, int e, int ep, int t, int b)
+{
+    u64x4 w = philox(seed, PURPOSE_GOV, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)(b >> 2));
+    return (int32_t)(((word_of(w, b & 3) >> 32) * (uint64_t)EJ_GOV_LEVELS) >> 32);
+}
+
 // ---------------------------------------------------------------------------
 // the step kernel: one workgroup per economy
 // ---------------------------------------------------------------------------
@@ -696,17 +705,19 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             a_in[k] = act[row0 + li];
         }
     }
+    // this bracket's rate: the government sets the period's rates at its
+    // first step (kept in a register until after the first barrier, so that
+    // the barrier does not wait for the loads)
+    int rate = 0;
+    if (tid < K) {
+        rate = S.env_rates[e * K + tid];
+        if (t % P.P_tax == 0) {
+            const int g = gov ? gov[e * K + tid] : gov_level_draw(P.gov_seed, e, ep, t, tid);
+            if (g >= 0 && g < EJ_GOV_LEVELS) rate = g;
+        }
+    }
     for (int j = tid; j < P.P; j += NT) L.prices[j] = P.prices[j];
     for (int j = tid; j < K - 1; j += NT) L.cutoffs[j] = P.cutoffs[j];
-    if (tid < K) {
-        int old = S.env_rates[e * K + tid];
-        int lv = old;
-        if (t % P.P_tax == 0) {  // government sets the period's rates at its first step
-            int g = gov[e * K + tid];
-            if (g >= 0 && g < EJ_GOV_LEVELS) lv = g;
-        }
-        L.rates[tid] = lv;
-    }
     for (int j = tid; j < P.HB; j += NT) {
         L.hcnt[j] = 0;
         L.hmin[j] = INT_MAX;
@@ -720,6 +731,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     int my_rank[APT];
     int invalid = 0;
 
+    if (tid < K) L.rates[tid] = rate;
     // load, utilities of the step-start state, action validation (step-start mask)
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
@@ -985,7 +997,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     if (tid == 0) {
         gov_rew[e] = (float)(ug1 - ug0);
         int bad_gov = 0;
-        if (t % P.P_tax == 0)
+        if (gov && t % P.P_tax == 0)
             for (int b = 0; b < K; ++b) {
                 int g = gov[e * K + b];
                 bad_gov += (g < 0 || g >= EJ_GOV_LEVELS);
@@ -1250,9 +1262,7 @@ __global__ void env_random_actions_kernel(const EnvParams P, const EnvState S, u
         }
     }
     if ((int)threadIdx.x < P.K) {
-        const int b = threadIdx.x;
-        u64x4 w = philox(act_seed, PURPOSE_GOV, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)(b >> 2));
-        gov[e * P.K + b] = (int32_t)(((word_of(w, b & 3) >> 32) * 21ull) >> 32);
+        gov[e * P.K + threadIdx.x] = gov_level_draw(act_seed, e, ep, t, threadIdx.x);
     }
 }
 
@@ -1262,9 +1272,7 @@ __global__ void env_random_gov_kernel(const EnvParams P, const EnvState S, uint6
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= S.E * P.K) return;
     const int e = j / P.K, b = j - e * P.K;
-    const int t = S.env_t[e], ep = S.env_ep[e];
-    u64x4 w = philox(act_seed, PURPOSE_GOV, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)(b >> 2));
-    gov[j] = (int32_t)(((word_of(w, b & 3) >> 32) * 21ull) >> 32);
+    gov[j] = gov_level_draw(act_seed, e, S.env_ep[e], S.env_t[e], b);
 }
 
 }  // namespace econ
@@ -1500,7 +1508,7 @@ int ej_env_step(ej_env* h, const int32_t* d_act, const int32_t* d_gov, float* d_
                 uint8_t* d_done, uint16_t* d_obs, uint32_t* d_mask, void* stream)
 {
     if (!h || !d_act || !d_rew || !d_gov_rew || !d_done) return EJ_EINVAL;
-    if (h->P.K > 0 && !d_gov) return EJ_EINVAL;
+    if (h->P.K > 0 && !d_gov && !h->P.gov_draw) return EJ_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     EnvState S = h->state();
 #define EJ_STEP_LAUNCH(KERNEL, G)                                                                           \
@@ -1527,6 +1535,14 @@ int ej_env_step(ej_env* h, const int32_t* d_act, const int32_t* d_gov, float* d_
     }
 #undef EJ_STEP_LAUNCH
     EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+int ej_env_set_gov_draw(ej_env* h, int32_t enabled, uint64_t seed)
+{
+    if (!h) return EJ_EINVAL;
+    h->P.gov_draw = enabled != 0;
+    h->P.gov_seed = seed;
     return EJ_OK;
 }
 

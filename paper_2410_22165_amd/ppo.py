@@ -1,9 +1,9 @@
 """PPO driver for the batched economy (argument marshalling around the C ABI).
 
 Rollout: every step the shared policy samples all agents' actions
-(ej_policy_forward), the government draws its tax levels, and the economy
-step (ej_env_step) writes rewards, done flags and the next observation and
-mask straight into the rollout storage.  Update: GAE (ej_gae), then epochs x
+(ej_policy_forward) and the economy step (ej_env_step, which also draws the
+government's uniform tax levels) writes rewards, done flags and the next
+observation and mask straight into the rollout storage.  Update: GAE (ej_gae), then epochs x
 minibatches of the hand-written backward (ej_ppo_backward) and Adam
 (ej_adam), with the bf16 work copy refreshed after every step
 (ej_mlp_sync_weights).  Table 2 of the paper lists the PPO settings; the
@@ -101,6 +101,7 @@ class PPOTrainer:
         self.updates = 0
         self.adam_step = 0
         self.graph = None
+        self.env.set_gov_draw(True, seed + 1)
         self.env.observe(self.store.obs[0], self.store.mask[0])
 
     # ---- rollout ----
@@ -108,8 +109,8 @@ class PPOTrainer:
         s = self.store
         self.mlp.forward(s.obs[t], s.mask[t], self.M, self.seed, t, s.act[t], s.logp[t], s.val[t], s.ent[t],
                          ctr_base=self.ctr_base)
-        self.env.random_actions(self.seed + 1, None, self.gov)
-        self.env.step(s.act[t], self.gov, s.rew[t], self.gov_rew, s.done[t], s.obs[t + 1], s.mask[t + 1])
+        # the government's uniform levels are drawn inside the step (seed + 1)
+        self.env.step(s.act[t], None, s.rew[t], self.gov_rew, s.done[t], s.obs[t + 1], s.mask[t + 1])
 
     def _collect_launches(self):
         for t in range(self.T):

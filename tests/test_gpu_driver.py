@@ -124,3 +124,31 @@ def test_persistent_launch_equals_plain_launch():
         assert np.array_equal(s0[k], s1[k]), k
     for e in envs:
         e.close()
+
+
+def test_step_drawn_government_levels_equal_explicit_draw():
+    """ej_env_step with the government draw switched on (no level buffer)
+    gives the same economy as drawing the levels with ej_env_random_actions
+    and passing them, over several tax periods."""
+    import torch
+    from paper_2410_22165_amd import binding
+    cfg = W.env_config(E=6, N=30, R=3, P=8, X=5, P_tax=7, K=5, T=50, seed=5)
+    envs = [binding.Env(cfg, W.obs_scales(cfg)) for _ in range(2)]
+    envs[0].set_gov_draw(True, 9)
+    bufs = [e.buffers() for e in envs]
+    for step in range(60):
+        envs[0].random_actions(4, bufs[0]["act"], bufs[0]["gov"])
+        envs[1].random_actions(4, bufs[1]["act"], bufs[1]["gov"])
+        envs[1].random_actions(9, None, bufs[1]["gov"])
+        b0, b1 = bufs
+        envs[0].step(b0["act"], None, b0["rew"], b0["gov_rew"], b0["done"], b0["obs"], b0["mask"])
+        envs[1].step(b1["act"], b1["gov"], b1["rew"], b1["gov_rew"], b1["done"], b1["obs"], b1["mask"])
+        torch.cuda.synchronize()
+        for k in ("rew", "gov_rew", "done", "obs", "mask"):
+            assert torch.equal(b0[k], b1[k]), (step, k)
+    s0, s1 = envs[0].get_state(), envs[1].get_state()
+    for k in s0:
+        assert np.array_equal(s0[k], s1[k]), k
+    assert envs[0].status() == envs[1].status()
+    for e in envs:
+        e.close()
