@@ -716,8 +716,11 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             if (g >= 0 && g < EJ_GOV_LEVELS) rate = g;
         }
     }
-    for (int j = tid; j < P.P; j += NT) L.prices[j] = P.prices[j];
-    for (int j = tid; j < K - 1; j += NT) L.cutoffs[j] = P.cutoffs[j];
+    // price grid and bracket cutoffs: read now, stored after the barrier
+    // (NT >= 64 and P <= 128: at most two prices per thread)
+    const int32_t pr0 = tid < P.P ? P.prices[tid] : 0;
+    const int32_t pr1 = tid + NT < P.P ? P.prices[tid + NT] : 0;
+    const int32_t cut = tid < K - 1 ? P.cutoffs[tid] : 0;
     for (int j = tid; j < P.HB; j += NT) {
         L.hcnt[j] = 0;
         L.hmin[j] = INT_MAX;
@@ -732,7 +735,10 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     int invalid = 0;
 
     if (tid < K) L.rates[tid] = rate;
-    // load, utilities of the step-start state, action validation (step-start mask)
+    if (tid < P.P) L.prices[tid] = pr0;
+    if (tid + NT < P.P) L.prices[tid + NT] = pr1;
+    if (tid < K - 1) L.cutoffs[tid] = cut;
+    // utilities of the step-start state
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
         const int li = tid + k * NT;
@@ -742,13 +748,19 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             const int64_t C = (int64_t)ag[k].coin_inv + ag[k].coin_esc;
             u0[k] = utility(C, ag[k].labor, P.eta);
             L.sortbuf[li] = welfare_key(C, li, n);
-            const int a = a_in[k];
-            if (action_allowed(P, ag[k], n_active(ag[k], X), a, L.prices)) eff[k] = a;
-            else ++invalid;
         }
     }
     lds_barrier();
     const double ug0 = cached_ug == cached_ug ? cached_ug : social_welfare_block(P, L, n, S2);
+    // action validation against the step-start mask
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int li = tid + k * NT;
+        if (li >= n) continue;
+        const int a = a_in[k];
+        if (action_allowed(P, ag[k], n_active(ag[k], X), a, L.prices)) eff[k] = a;
+        else ++invalid;
+    }
 
     // apply every agent's action; new orders go to slot t mod X
     const int slot_new = t % X;
