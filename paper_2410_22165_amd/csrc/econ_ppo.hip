@@ -185,22 +185,34 @@ __device__ inline void ppo_masked_grad_cs(const f32x4 (&dh)[TR][CTW], const uint
 }
 
 // m-block copy of an LDS tile: rows [0, rows) x columns [0, ncol) of a bf16
-// tile (row stride hs) -> T[(mb0 + row / 32) ncol_total + col_off + col][32];
-// one 16-byte store per (32-row block, column, quarter of 8 rows), so each
-// column's 64 bytes of a block leave in one coalesced piece.  All threads call it.
+// tile (row stride hs, a multiple of 4) -> T[(mb0 + row / 32) ncol_total +
+// col_off + col][32].  A work item is (32-row block, group of four columns,
+// quarter of 8 rows): eight 8-byte LDS reads give the quarter of all four
+// columns, which leave as four 16-byte stores (each column's 64 bytes of a
+// block come from four consecutive lanes).  ncol is a multiple of 4.  All
+// threads call it.
 __device__ inline void tile_to_mblocks(const uint16_t* tile, int hs, int rows, int ncol, uint16_t* T, int64_t mb0,
                                        int ncol_total, int col_off)
 {
-    const int np = (rows / 32) * ncol * 4;
+    const int ng = ncol >> 2;
+    const int np = (rows / 32) * ng * 4;
     for (int p = threadIdx.x; p < np; p += blockDim.x) {
-        const int qq = p & 3, col = (p >> 2) % ncol, blk = (p >> 2) / ncol;
-        uint32_t w4[4];
+        const int qq = p & 3, g = (p >> 2) % ng, blk = (p >> 2) / ng;
+        uint2 v[8];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int r0 = blk * 32 + qq * 8 + 2 * k;
-            w4[k] = (uint32_t)tile[r0 * hs + col] | ((uint32_t)tile[(r0 + 1) * hs + col] << 16);
+        for (int k = 0; k < 8; ++k) v[k] = *(const uint2*)(tile + (blk * 32 + qq * 8 + k) * hs + 4 * g);
+        uint16_t* dst = T + ((mb0 + blk) * ncol_total + col_off + 4 * g) * 32 + qq * 8;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint32_t w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t lo = (j < 2 ? v[2 * k].x : v[2 * k].y) >> (16 * (j & 1));
+                const uint32_t hi = (j < 2 ? v[2 * k + 1].x : v[2 * k + 1].y) >> (16 * (j & 1));
+                w[k] = (lo & 0xFFFFu) | (hi << 16);
+            }
+            *(uint4*)(dst + j * 32) = uint4{w[0], w[1], w[2], w[3]};
         }
-        *(uint4*)(T + ((mb0 + blk) * ncol_total + col_off + col) * 32 + qq * 8) = uint4{w4[0], w4[1], w4[2], w4[3]};
     }
 }
 
