@@ -886,6 +886,41 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     }
     lds_barrier();
 
+    // Fill rank -> bucket tables: side s of resource r holds its k_r filled
+    // ranks at tab_off[r] + s k_r, tab_off[r] = 2 (k_0 + ... + k_{r-1}).
+    // 16-bit entries in the sort buffer (idle until the rewards); when they do
+    // not fit, settlement falls back to a binary search over the prefix sums.
+    // Every entry is found by its own thread (one binary search each, all in
+    // parallel), so settlement reads one entry per filled order.
+    uint16_t* ftab = (uint16_t*)L.sortbuf;
+    int tab_off[RM], krr[RM];
+    int ftot = 0;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        krr[r] = r < R ? L.kr[r] : 0;
+        tab_off[r] = ftot;
+        ftot += 2 * krr[r];
+    }
+    const bool use_tab = ftot <= 4 * S2;
+    if (use_tab) {
+        for (int j = tid; j < ftot; j += NT) {
+            int r = 0;
+#pragma unroll
+            for (int q = 1; q < RM; ++q) r = (q < R && tab_off[q] <= j) ? q : r;
+            const int kr = rget(krr, r), rel = j - rget(tab_off, r);
+            const int side = rel >= kr ? 1 : 0, g = rel - side * kr;
+            const int ob = (r * 2 + side) * PX;
+            int lo = 0, hi = PX - 1;
+            while (lo < hi) {  // largest pos with hexc <= g
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.hexc[ob + mid] <= g) lo = mid;
+                else hi = mid - 1;
+            }
+            ftab[j] = (uint16_t)lo;
+        }
+        lds_barrier();
+    }
+
     // settlement: every agent settles its own filled orders
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
@@ -903,13 +938,18 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             if (g >= L.kr[r]) continue;
             // the counterpart holds rank g on the other side
             const int ob = (r * 2 + (1 - side)) * PX;
-            int lo = 0, hi = PX - 1;
-            while (lo < hi) {  // largest pos with hexc <= g
-                int mid = (lo + hi + 1) >> 1;
-                if (L.hexc[ob + mid] <= g) lo = mid;
-                else hi = mid - 1;
+            int opos;
+            if (use_tab) {
+                opos = ftab[rget(tab_off, r) + (1 - side) * rget(krr, r) + g];
+            } else {
+                int lo = 0, hi = PX - 1;
+                while (lo < hi) {  // largest pos with hexc <= g
+                    int mid = (lo + hi + 1) >> 1;
+                    if (L.hexc[ob + mid] <= g) lo = mid;
+                    else hi = mid - 1;
+                }
+                opos = lo;
             }
-            const int opos = lo;
             const int oage = X - 1 - (opos % X);
             const int opl = opos / X;
             const int op = side == 0 ? opl : P.P - 1 - opl;
