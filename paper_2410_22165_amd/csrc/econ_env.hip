@@ -311,19 +311,32 @@ __device__ inline int64_t block_sum_i64(int64_t v, int64_t* red)
 
 // exclusive scans of `nseg` segments of `len` ints (src -> dst); waves take
 // segments round-robin; the caller synchronises before and after.
+// A wave takes U of its segments at once so that their load and scan
+// chains overlap (absent segments scan zeros).
+template <int U>
 __device__ inline void seg_exclusive_scan(const int32_t* src, int32_t* dst, int nseg, int len)
 {
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = lane_id();
-    for (int s = w; s < nseg; s += nw) {
-        int32_t carry = 0;
-        int32_t v = lane < len ? src[s * len + lane] : 0;
+    for (int s0 = w; s0 < nseg; s0 += U * nw) {
+        int32_t carry[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) carry[u] = 0;
         for (int c = 0; c < len; c += 64) {
             const int j = c + lane;
-            const int32_t vn = j + 64 < len ? src[s * len + j + 64] : 0;  // next chunk in flight
-            const int32_t inc = wave_scan_i(v);
-            if (j < len) dst[s * len + j] = carry + inc - v;
-            carry += __builtin_amdgcn_readlane(inc, 63);
-            v = vn;
+            int32_t v[U], inc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int sg = s0 + u * nw;
+                v[u] = (sg < nseg && j < len) ? src[sg * len + j] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) inc[u] = wave_scan_i(v[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int sg = s0 + u * nw;
+                if (sg < nseg && j < len) dst[sg * len + j] = carry[u] + inc[u] - v[u];
+                carry[u] += __builtin_amdgcn_readlane(inc[u], 63);
+            }
         }
     }
 }
@@ -480,37 +493,55 @@ __device__ inline double social_welfare_block(const EnvParams& P, const Lds& L, 
 // `kr` null -> no fills; `skip_age` >= 0 -> that age has expired.
 __device__ inline void market_stats(const EnvParams& P, const Lds& L, const int32_t* kr, int skip_age)
 {
+    // a wave takes up to four (r, side) segments at once (independent chains)
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = lane_id();
-    const int PX = P.P * P.X;
-    for (int seg = w; seg < 2 * P.R; seg += nw) {
-        const int r = seg >> 1, side = seg & 1;
-        const int k = kr ? kr[r] : 0;
-        int best = INT_MAX, count = 0;
+    const int PX = P.P * P.X, nseg = 2 * P.R;
+    for (int s0 = w; s0 < nseg; s0 += 4 * nw) {
+        int best[4], count[4], k[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int sg = s0 + u * nw;
+            best[u] = INT_MAX;
+            count[u] = 0;
+            k[u] = (sg < nseg && kr) ? kr[sg >> 1] : 0;
+        }
         for (int c = 0; c < PX; c += 64) {
-            int pos = c + lane;
-            if (pos < PX) {
-                int b = seg * PX + pos;
-                int cnt = L.hcnt[b];
-                int fill = k - L.hexc[b];
-                fill = fill < 0 ? 0 : (fill > cnt ? cnt : fill);
-                int alive = cnt - fill;
-                int age = P.X - 1 - (pos % P.X);
-                if (age == skip_age) alive = 0;
-                if (alive > 0 && pos < best) best = pos;
-                count += alive;
+            const int pos = c + lane;
+            const int age = P.X - 1 - (pos % P.X);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int sg = s0 + u * nw;
+                if (sg < nseg && pos < PX) {
+                    const int b = sg * PX + pos;
+                    const int cnt = L.hcnt[b];
+                    int fill = k[u] - L.hexc[b];
+                    fill = fill < 0 ? 0 : (fill > cnt ? cnt : fill);
+                    const int alive = age == skip_age ? 0 : cnt - fill;
+                    if (alive > 0 && pos < best[u]) best[u] = pos;
+                    count[u] += alive;
+                }
             }
         }
-        best = wave_min_i(best);
-        count = wave_sum_i(count);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            best[u] = wave_min_i(best[u]);
+            count[u] = wave_sum_i(count[u]);
+        }
         if (lane == 0) {
-            int price = 0;
-            if (best != INT_MAX) {
-                int pl = best / P.X;
-                int p = side == 0 ? P.P - 1 - pl : pl;
-                price = L.prices[p];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int sg = s0 + u * nw;
+                if (sg >= nseg) continue;
+                const int r = sg >> 1, side = sg & 1;
+                int price = 0;
+                if (best[u] != INT_MAX) {
+                    const int pl = best[u] / P.X;
+                    const int p = side == 0 ? P.P - 1 - pl : pl;
+                    price = L.prices[p];
+                }
+                L.mstat[4 * r + side] = price;
+                L.mstat[4 * r + 2 + side] = count[u];
             }
-            L.mstat[4 * r + side] = price;
-            L.mstat[4 * r + 2 + side] = count;
         }
     }
 }
@@ -811,7 +842,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         }
     }
     lds_barrier();
-    seg_exclusive_scan(L.nbcnt, L.nboff, 1, 2 * R * P.P);
+    seg_exclusive_scan<1>(L.nbcnt, L.nboff, 1, 2 * R * P.P);
     lds_barrier();
     // this step's orders listed per (side, r, p) in arrival order; the
     // welfare sort buffer is free until the rewards
@@ -861,7 +892,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         }
     }
     lds_barrier();
-    seg_exclusive_scan(L.hcnt, L.hexc, 2 * R, PX);
+    seg_exclusive_scan<4>(L.hcnt, L.hexc, 2 * R, PX);
     lds_barrier();
 
     // trades per resource: k_r = max_p min(#bids >= price p, #asks <= price p)
