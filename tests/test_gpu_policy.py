@@ -20,6 +20,7 @@ CASES = [  # (D, Ds, H, A, M)
     (49, 56, 512, 507, 333),       # 1000-agent economy: 5 resources, 50 prices
     (64, 64, 128, 300, 129),
     (35, 40, 256, 125, 1),
+    (64, 64, 256, 1000, 200),      # widest input (64 features) and 8 action chunks
 ]
 
 
@@ -149,3 +150,17 @@ def test_row_tile_variants_are_bit_identical():
         outs.append([t.cpu() for t in o])
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+def test_empty_batch_is_a_no_op():
+    """M = 0 rows: the call succeeds and writes nothing."""
+    import torch
+    from paper_2410_22165_amd import binding
+    D, Ds, H, A = 35, 40, 256, 125
+    mlp = binding.Mlp(D, Ds, H, A, W.policy_weights(D, H, A, seed=1))
+    o = [torch.full((4,), 7, dtype=torch.int32, device="cuda")] + [torch.full((4,), 7.0, device="cuda") for _ in range(3)]
+    obs = torch.zeros((4, Ds), dtype=torch.int16, device="cuda")
+    mask = torch.zeros((4, 4), dtype=torch.int32, device="cuda")
+    mlp.forward(obs, mask, 0, 1, 0, *o)
+    torch.cuda.synchronize()
+    assert all((t.cpu() == 7).all() for t in o)
