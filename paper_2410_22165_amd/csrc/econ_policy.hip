@@ -28,9 +28,10 @@ size_t policy_lds_bytes(int W, int A1p)
     using T = MlpTile<H, RPW>;
     const size_t hb = (size_t)T::TILE * T::HS * 2, zb = (size_t)T::TILE * ZS * 4;
     const size_t region = A1p == 128 ? (hb > zb ? hb : zb) : hb + zb;
-    return region + (size_t)T::TILE * W * 4 + (size_t)T::TILE * 2 * 4 + (size_t)(2 * H + A1p) * 4;
+    return region + (size_t)T::TILE * W * 4 + (size_t)T::TILE * 4 * 4 + (size_t)(2 * H + A1p) * 4;
 }
 
+// The workgroup's threads talk through LDS only (its barriers order LDS).
 // 64-row tiles with H <= 256 take 37 KB of LDS and 160 VGPRs: three workgroups per CU
 template <int H, int RPW_>
 __global__ void __launch_bounds__(256, (RPW_ == 16 && H <= 256) ? 3 : 1)
@@ -49,11 +50,23 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     uint16_t* hbuf = (uint16_t*)smem;
     float* zbuf = (float*)(smem + (d.A1p == 128 ? 0 : hb));  // logit chunk [TILE][ZS]
     uint32_t* smask = (uint32_t*)(smem + region);            // [TILE][W]
-    float* urow = (float*)(smask + TILE * W);                 // [TILE][2] uniforms of the current chunk
-    float* sbias = urow + TILE * 2;                           // b1 [H], b2 [H], b3 [A1p] (zero padded)
+    float* urow = (float*)(smask + TILE * W);                 // [TILE][4] uniforms of the current chunk pair
+    float* sbias = urow + TILE * 4;                           // b1 [H], b2 [H], b3 [A1p] (zero padded)
     const int wave = threadIdx.x >> 6, l = lane_id();
     const int64_t row0 = (int64_t)blockIdx.x * TILE;
 
+    // One Philox call gives the uniforms (u1, u2) of two chunks: lane j < RPW
+    // draws for the wave's row j.  The first pair is drawn here, under the
+    // latency of the tile loads.
+    auto draw_uniforms = [&](int c) {
+        if (l < RPW) {
+            const int rl = wave * RPW + l;
+            u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row0 + rl), ctr, (uint64_t)(c >> 1), 0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) urow[rl * 4 + k] = unif24(word_of(w, k));
+        }
+    };
+    draw_uniforms(0);
     // observation tile -> activation buffer columns [0, K1p); mask rows -> LDS
     const int ppr = d.K1p / 8;
     for (int p = threadIdx.x; p < TILE * ppr; p += 256) {
@@ -77,15 +90,15 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
         constexpr int CTW = H / 64;
         const int col0 = wave * (H / 4);
         f32x4 acc[TR][CTW];
-        __syncthreads();  // observation tile in LDS
+        lds_barrier();  // observation tile in LDS
         dense_cs<TR, CTW, 2>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
-        __syncthreads();  // every wave is done reading the observations
+        lds_barrier();  // every wave is done reading the observations
         epilogue_relu_cs<TR, CTW>(acc, sbias, hbuf, HS, col0);
-        __syncthreads();
+        lds_barrier();
         dense_cs<TR, CTW, H / 32>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
-        __syncthreads();
+        lds_barrier();
         epilogue_relu_cs<TR, CTW>(acc, sbias + H, hbuf, HS, col0);
-        __syncthreads();
+        lds_barrier();
     }
 
     // Logits, 128 actions (one chunk) at a time: wave w computes columns
@@ -109,13 +122,8 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
             f32x4 acc3[TR][2];
             dense_cs<TR, 2, H / 32>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32,
                                     32 * wave);
-            // uniforms of chunk c: lane j < RPW draws for the wave's row j
-            if (l < RPW) {
-                u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row0 + wave * RPW + l), ctr, (uint64_t)(c >> 1), 0);
-                urow[(wave * RPW + l) * 2 + 0] = unif24(word_of(w, 2 * (c & 1)));
-                urow[(wave * RPW + l) * 2 + 1] = unif24(word_of(w, 2 * (c & 1) + 1));
-            }
-            if (d.A1p == 128) __syncthreads();  // the logit chunk overwrites the activations
+            if (c > 0 && (c & 1) == 0) draw_uniforms(c);  // the next pair of chunks
+            if (d.A1p == 128) lds_barrier();  // the logit chunk overwrites the activations
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
                 const int cc = 32 * wave + ct * 16 + (l & 15);
@@ -126,7 +134,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
                     for (int i = 0; i < 4; ++i) zbuf[(rt * 16 + 4 * (l >> 4) + i) * ZS + zcol(cc)] = acc3[rt][ct][i] + b;
             }
         }
-        __syncthreads();  // the chunk's logits and uniforms are in LDS
+        lds_barrier();  // the chunk's logits and uniforms are in LDS
         const int colq = c * 128 + 32 * q;  // first action of this lane's quarter
 #pragma unroll
         for (int k = 0; k < SR; ++k) {
@@ -147,7 +155,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
             }
             const int wi = c * 4 + q;
             const uint32_t mw = wi < W ? smask[rloc * W + wi] : 0u;
-            const float u1 = urow[rloc * 2], u2 = urow[rloc * 2 + 1];
+            const float u1 = urow[rloc * 4 + 2 * (c & 1)], u2 = urow[rloc * 4 + 2 * (c & 1) + 1];
             float zmax = NEG, zval = 0.f;
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
@@ -203,7 +211,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
             sA[k] = take ? c * 128 + key : sA[k];
             sZ[k] = take ? zk : sZ[k];
         }
-        if (c + 1 < d.NC) __syncthreads();  // before the next chunk overwrites the logits and uniforms
+        if (c + 1 < d.NC) lds_barrier();  // before the next chunk overwrites the logits and uniforms
     }
     // outputs: sampled action, its log-probability, entropy, value (lane 0 of each quad)
     if (q == 0) {
