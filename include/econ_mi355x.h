@@ -153,6 +153,15 @@ int ej_env_reset(ej_env* env, int32_t episode, void* stream);
 int ej_env_step(ej_env* env, const int32_t* d_act, const int32_t* d_gov, float* d_rew, float* d_gov_rew,
                 uint8_t* d_done, uint16_t* d_obs, uint32_t* d_mask, void* stream);
 
+/* ej_env_step restricted to economies [e_begin, e_end): the arrays keep the
+ * layout of the whole batch (rows of economy e start at row offset e) and
+ * only the range's rows and economies are read and written, so that disjoint
+ * ranges may run concurrently on different streams (one workgroup per
+ * economy; the persistent launch applies to whole-batch calls only). */
+int ej_env_step_range(ej_env* env, int32_t e_begin, int32_t e_end, const int32_t* d_act, const int32_t* d_gov,
+                      float* d_rew, float* d_gov_rew, uint8_t* d_done, uint16_t* d_obs, uint32_t* d_mask,
+                      void* stream);
+
 /* Launch shape of ej_env_step.  mode 0: one workgroup per economy (one
  * launch per step).  mode 1: `workgroups` persistent workgroups (0: two per
  * compute unit) take economies from a work queue, largest populations first;
@@ -229,16 +238,18 @@ int ej_mlp_sync_weights(const ej_mlp_desc* m, const float* d_params, uint16_t* d
  * Sampling is exact for the masked softmax: the logits are taken in chunks
  * of 128 actions, a chunk is chosen by weighted reservoir with one uniform
  * and the action inside it by inverse CDF with a second one (the chunk's
- * actions walked in the order c 128 + 16 t + j, j = 0..15 outer, t = 0..7
- * inner); the uniforms of
- * row r, chunk c come from the counter-based generator keyed (seed, r, ctr',
- * c / 2) with ctr' = ctr + *d_ctr_base (d_ctr_base: nullable device
- * uint64_t, read when the kernel runs, so that a captured graph replayed
- * many times draws fresh uniforms after each ej_counter_add).  Logits are
+ * actions walked in action order); the uniforms of row r, chunk c come from
+ * the counter-based generator keyed (seed, row_base + r, ctr', c / 2) with
+ * ctr' = ctr + *d_ctr_base (d_ctr_base: nullable device uint64_t, read when
+ * the kernel runs, so that a captured graph replayed many times draws fresh
+ * uniforms after each ej_counter_add).  row_base >= 0 numbers the rows when
+ * the pointers address a slice of a larger batch: slices drawn separately
+ * give exactly the results of one call over the whole batch.  Logits are
  * never written to memory unless d_logits is given. */
 int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const uint16_t* d_obs,
-                      const uint32_t* d_mask, int64_t M, uint64_t seed, uint64_t ctr, const uint64_t* d_ctr_base,
-                      int32_t* d_act, float* d_logp, float* d_val, float* d_ent, float* d_logits, void* stream);
+                      const uint32_t* d_mask, int64_t M, int64_t row_base, uint64_t seed, uint64_t ctr,
+                      const uint64_t* d_ctr_base, int32_t* d_act, float* d_logp, float* d_val, float* d_ent,
+                      float* d_logits, void* stream);
 
 /* *d_counter += inc on the stream (one tiny kernel; usable inside a graph). */
 int ej_counter_add(uint64_t* d_counter, uint64_t inc, void* stream);

@@ -88,6 +88,7 @@ def lib():
     L.ej_env_row_offsets.restype = C.POINTER(i32)
     L.ej_env_reset.argtypes = [vp, i32, vp]
     L.ej_env_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.ej_env_step_range.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.ej_env_observe.argtypes = [vp, vp, vp, vp, vp]
     L.ej_env_random_actions.argtypes = [vp, u64, vp, vp, vp]
     L.ej_env_get_state.argtypes = [vp, C.POINTER(EjStateView), vp]
@@ -106,7 +107,7 @@ def _declare_learner(L):
     table = {
         "ej_mlp_layout": [C.POINTER(EjMlpDesc), C.POINTER(EjMlpLayout)],
         "ej_mlp_sync_weights": [C.POINTER(EjMlpDesc), vp, vp, vp],
-        "ej_policy_forward": [C.POINTER(EjMlpDesc), vp, vp, vp, vp, i64, u64, u64, vp, vp, vp, vp, vp, vp, vp],
+        "ej_policy_forward": [C.POINTER(EjMlpDesc), vp, vp, vp, vp, i64, i64, u64, u64, vp, vp, vp, vp, vp, vp, vp],
         "ej_counter_add": [vp, u64, vp],
         "ej_gae": [vp, vp, vp, vp, i32, i64, f32, f32, vp, vp, vp],
         "ej_ppo_workspace_size": [C.POINTER(EjMlpDesc), i64, C.POINTER(i64)],
@@ -209,9 +210,16 @@ class Env:
     def reset(self, episode: int = 0, stream=None):
         check(lib().ej_env_reset(self._h, episode, stream_ptr(stream)), "ej_env_reset")
 
-    def step(self, act, gov, rew, gov_rew, done, obs=None, mask=None, stream=None):
-        check(lib().ej_env_step(self._h, ptr(act), ptr(gov), ptr(rew), ptr(gov_rew), ptr(done), ptr(obs), ptr(mask),
-                                stream_ptr(stream)), "ej_env_step")
+    def step(self, act, gov, rew, gov_rew, done, obs=None, mask=None, stream=None, economies=None):
+        """One step of every economy, or of economies [begin, end) when
+        `economies` is given (arrays keep the whole batch's layout)."""
+        if economies is None:
+            check(lib().ej_env_step(self._h, ptr(act), ptr(gov), ptr(rew), ptr(gov_rew), ptr(done), ptr(obs),
+                                    ptr(mask), stream_ptr(stream)), "ej_env_step")
+        else:
+            check(lib().ej_env_step_range(self._h, economies[0], economies[1], ptr(act), ptr(gov), ptr(rew),
+                                          ptr(gov_rew), ptr(done), ptr(obs), ptr(mask), stream_ptr(stream)),
+                  "ej_env_step_range")
 
     def observe(self, obs, mask, gov_obs=None, stream=None):
         check(lib().ej_env_observe(self._h, ptr(obs), ptr(mask), ptr(gov_obs), stream_ptr(stream)), "ej_env_observe")
@@ -315,10 +323,10 @@ class Mlp:
               "ej_mlp_sync_weights")
 
     def forward(self, obs, mask, M: int, seed: int, ctr: int, act, logp, val, ent, logits=None, stream=None,
-                ctr_base=None):
+                ctr_base=None, row_base: int = 0):
         check(lib().ej_policy_forward(C.byref(self.desc), ptr(self.params), ptr(self.work), ptr(obs), ptr(mask), M,
-                                      seed, ctr, ptr(ctr_base), ptr(act), ptr(logp), ptr(val), ptr(ent), ptr(logits),
-                                      stream_ptr(stream)), "ej_policy_forward")
+                                      row_base, seed, ctr, ptr(ctr_base), ptr(act), ptr(logp), ptr(val), ptr(ent),
+                                      ptr(logits), stream_ptr(stream)), "ej_policy_forward")
 
 
 def gae(rew, val, done, last_val, T: int, M: int, gamma: float, lam: float, adv, ret, stream=None):

@@ -1178,10 +1178,10 @@ template <int RM, int XM, int APT, int MAXT>
 __global__ void __launch_bounds__(MAXT)
 env_step_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__ act,
                 const int32_t* __restrict__ gov, float* __restrict__ rew, float* __restrict__ gov_rew,
-                uint8_t* __restrict__ done_out, uint16_t* __restrict__ obs, uint32_t* __restrict__ mask)
+                uint8_t* __restrict__ done_out, uint16_t* __restrict__ obs, uint32_t* __restrict__ mask, int e_begin)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    env_step_one<RM, XM, APT>(P, S, blockIdx.x, act, gov, rew, gov_rew, done_out, obs, mask, smem);
+    env_step_one<RM, XM, APT>(P, S, e_begin + (int)blockIdx.x, act, gov, rew, gov_rew, done_out, obs, mask, smem);
 }
 
 // Persistent launch: a fixed set of workgroups takes economies from a work
@@ -1193,7 +1193,7 @@ __global__ void __launch_bounds__(MAXT)
 env_step_persistent_kernel(const EnvParams P, const EnvState S, const int32_t* __restrict__ act,
                            const int32_t* __restrict__ gov, float* __restrict__ rew, float* __restrict__ gov_rew,
                            uint8_t* __restrict__ done_out, uint16_t* __restrict__ obs,
-                           uint32_t* __restrict__ mask)
+                           uint32_t* __restrict__ mask, int)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_slot;
@@ -1590,7 +1590,18 @@ int ej_env_reset(ej_env* h, int32_t episode, void* stream)
 int ej_env_step(ej_env* h, const int32_t* d_act, const int32_t* d_gov, float* d_rew, float* d_gov_rew,
                 uint8_t* d_done, uint16_t* d_obs, uint32_t* d_mask, void* stream)
 {
+    if (!h) return EJ_EINVAL;
+    return ej_env_step_range(h, 0, h->E, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs, d_mask, stream);
+}
+
+int ej_env_step_range(ej_env* h, int32_t e_begin, int32_t e_end, const int32_t* d_act, const int32_t* d_gov,
+                      float* d_rew, float* d_gov_rew, uint8_t* d_done, uint16_t* d_obs, uint32_t* d_mask,
+                      void* stream)
+{
     if (!h || !d_act || !d_rew || !d_gov_rew || !d_done) return EJ_EINVAL;
+    if (e_begin < 0 || e_end > h->E || e_begin > e_end) return EJ_EINVAL;
+    if (e_begin == e_end) return EJ_OK;
+    const bool whole = e_begin == 0 && e_end == h->E;
     if (h->P.K > 0 && !d_gov && !h->P.gov_draw) return EJ_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     EnvState S = h->state();
@@ -1599,22 +1610,22 @@ int ej_env_step(ej_env* h, const int32_t* d_act, const int32_t* d_gov, float* d_
         const bool small = h->NT <= 256;                                                                    \
         if (h->variant == 0 && small)                                                                       \
             KERNEL<4, 16, 1, 256><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done,  \
-                                                            d_obs, d_mask);                                 \
+                                                            d_obs, d_mask, e_begin);                        \
         else if (h->variant == 0)                                                                           \
             KERNEL<4, 16, 1, 1024><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, \
-                                                             d_obs, d_mask);                                \
+                                                             d_obs, d_mask, e_begin);                       \
         else if (small)                                                                                     \
             KERNEL<8, 32, 1, 256><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done,  \
-                                                            d_obs, d_mask);                                 \
+                                                            d_obs, d_mask, e_begin);                        \
         else                                                                                                \
             KERNEL<8, 32, 1, 1024><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, \
-                                                             d_obs, d_mask);                                \
+                                                             d_obs, d_mask, e_begin);                       \
     } while (0)
-    if (h->mode == 1) {
+    if (h->mode == 1 && whole) {
         const unsigned G = (unsigned)h->persistent_wg;
         EJ_STEP_LAUNCH(env_step_persistent_kernel, G);
     } else {
-        EJ_STEP_LAUNCH(env_step_kernel, (unsigned)h->E);
+        EJ_STEP_LAUNCH(env_step_kernel, (unsigned)(e_end - e_begin));
     }
 #undef EJ_STEP_LAUNCH
     EJ_LAUNCH_CHECK();

@@ -36,8 +36,8 @@ size_t policy_lds_bytes(int W, int A1p)
 template <int H, int RPW_>
 __global__ void __launch_bounds__(256, (RPW_ == 16 && H <= 256) ? 3 : 1)
 policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
-                      const uint16_t* __restrict__ obs, const uint32_t* __restrict__ mask, int64_t M, int W,
-                      uint64_t seed, uint64_t ctr_arg, const uint64_t* __restrict__ ctr_base,
+                      const uint16_t* __restrict__ obs, const uint32_t* __restrict__ mask, int64_t M, int64_t row_base,
+                      int W, uint64_t seed, uint64_t ctr_arg, const uint64_t* __restrict__ ctr_base,
                       int32_t* __restrict__ act, float* __restrict__ logp, float* __restrict__ val,
                       float* __restrict__ ent, float* __restrict__ logits)
 {
@@ -61,7 +61,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     auto draw_uniforms = [&](int c) {
         if (l < RPW) {
             const int rl = wave * RPW + l;
-            u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row0 + rl), ctr, (uint64_t)(c >> 1), 0);
+            u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row_base + row0 + rl), ctr, (uint64_t)(c >> 1), 0);
 #pragma unroll
             for (int k = 0; k < 4; ++k) urow[rl * 4 + k] = unif24(word_of(w, k));
         }
@@ -273,14 +273,15 @@ __global__ void mlp_sync_kernel(const MlpDims d, const float* __restrict__ p, ui
 
 template <int H, int RPW>
 int launch_policy_forward(const MlpDims& d, const float* params, const uint16_t* work, const uint16_t* obs,
-                          const uint32_t* mask, int64_t M, int W, uint64_t seed, uint64_t ctr, const uint64_t* ctr_base,
-                          int32_t* act, float* logp, float* val, float* ent, float* logits, hipStream_t st)
+                          const uint32_t* mask, int64_t M, int64_t row_base, int W, uint64_t seed, uint64_t ctr,
+                          const uint64_t* ctr_base, int32_t* act, float* logp, float* val, float* ent, float* logits,
+                          hipStream_t st)
 {
     using T = MlpTile<H, RPW>;
     const int64_t blocks = (M + T::TILE - 1) / T::TILE;
     const size_t lds = policy_lds_bytes<H, RPW>(W, d.A1p);
-    policy_forward_kernel<H, RPW><<<(unsigned)blocks, 256, lds, st>>>(d, params, work, obs, mask, M, W, seed, ctr, ctr_base,
-                                                                  act, logp, val, ent, logits);
+    policy_forward_kernel<H, RPW><<<(unsigned)blocks, 256, lds, st>>>(d, params, work, obs, mask, M, row_base, W, seed,
+                                                                      ctr, ctr_base, act, logp, val, ent, logits);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }
@@ -342,20 +343,22 @@ int ej_counter_add(uint64_t* d_counter, uint64_t inc, void* stream)
 }
 
 int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const uint16_t* d_obs,
-                      const uint32_t* d_mask, int64_t M, uint64_t seed, uint64_t ctr, const uint64_t* d_ctr_base,
-                      int32_t* d_act, float* d_logp, float* d_val, float* d_ent, float* d_logits, void* stream)
+                      const uint32_t* d_mask, int64_t M, int64_t row_base, uint64_t seed, uint64_t ctr,
+                      const uint64_t* d_ctr_base, int32_t* d_act, float* d_logp, float* d_val, float* d_ent,
+                      float* d_logits, void* stream)
 {
     MlpDims d;
     int rc = desc_dims(m, &d);
     if (rc != EJ_OK) return rc;
-    if (M < 0 || !d_params || !d_work || !d_obs || !d_mask || !d_act || !d_logp || !d_val || !d_ent) return EJ_EINVAL;
+    if (M < 0 || row_base < 0 || !d_params || !d_work || !d_obs || !d_mask || !d_act || !d_logp || !d_val || !d_ent)
+        return EJ_EINVAL;
     if (M == 0) return EJ_OK;
     const int W = (m->A + 31) / 32;
     hipStream_t st = (hipStream_t)stream;
     const bool small = m->tile_rows != 128 || m->H == 512;  // 64-row tiles unless 128 is asked for
 #define EJ_POLICY(HH, RR) \
-    launch_policy_forward<HH, RR>(d, d_params, d_work, d_obs, d_mask, M, W, seed, ctr, d_ctr_base, d_act, d_logp, d_val, \
-                                  d_ent, d_logits, st)
+    launch_policy_forward<HH, RR>(d, d_params, d_work, d_obs, d_mask, M, row_base, W, seed, ctr, d_ctr_base, d_act, d_logp, \
+                                  d_val, d_ent, d_logits, st)
     switch (m->H) {
     case 64: return small ? EJ_POLICY(64, 16) : EJ_POLICY(64, 32);
     case 128: return small ? EJ_POLICY(128, 16) : EJ_POLICY(128, 32);

@@ -23,6 +23,42 @@ import torch
 from . import binding
 
 
+def economy_groups(env, groups: int):
+    """Split the economies into `groups` contiguous ranges:
+    [(e_begin, e_end, row_begin, row_end)] (rows from the env's row offsets)."""
+    E = env.E
+    groups = max(1, min(int(groups), E))
+    out = []
+    for g in range(groups):
+        e0, e1 = E * g // groups, E * (g + 1) // groups
+        out.append((e0, e1, int(env.row_offsets[e0]), int(env.row_offsets[e1])))
+    return out
+
+
+class GroupStreams:
+    """One stream per economy group (default priority).  Economies never
+    interact, so each group's policy -> step chain runs on its own stream and
+    one group's policy overlaps another's economy step.  fork() / join()
+    order the streams after / before the current stream's work (also inside
+    graph capture)."""
+
+    def __init__(self, n: int):
+        self.streams = [torch.cuda.Stream() for _ in range(n)] if n > 1 else []
+
+    def fork(self):
+        cur = torch.cuda.current_stream()
+        for st in self.streams:
+            st.wait_stream(cur)
+
+    def join(self):
+        cur = torch.cuda.current_stream()
+        for st in self.streams:
+            cur.wait_stream(st)
+
+    def stream(self, g: int):
+        return torch.cuda.stream(self.streams[g]) if self.streams else torch.cuda.stream(torch.cuda.current_stream())
+
+
 class PPOLoss(torch.autograd.Function):
     """loss = surrogate + c_v * value - c_e * entropy of one minibatch, as a
     function of the flat parameter vector `params` (= mlp.params)."""
@@ -70,7 +106,8 @@ class RolloutStorage:
 class PPOTrainer:
     def __init__(self, env_cfg: dict, scales: dict, hidden: int, rollout: int, epochs: int, minibatches: int,
                  gamma: float, lam: float, clip: float, vf_coef: float, vclip: float, ent_coef: float, lr: float,
-                 seed: int = 0, weights: dict | None = None, n_per_env=None, total_updates: int = 1):
+                 seed: int = 0, weights: dict | None = None, n_per_env=None, total_updates: int = 1,
+                 groups: int = 1):
         import workloads as W
         self.env = binding.Env(env_cfg, scales, n_per_env)
         e = self.env
@@ -101,20 +138,31 @@ class PPOTrainer:
         self.updates = 0
         self.adam_step = 0
         self.graph = None
+        self.groups = economy_groups(self.env, groups)  # rollout pipelined over economy groups
+        self.group_streams = GroupStreams(len(self.groups))
         self.env.set_gov_draw(True, seed + 1)
         self.env.observe(self.store.obs[0], self.store.mask[0])
 
     # ---- rollout ----
     def rollout_step(self, t: int):
+        """Policy and economy step for every group (the government's uniform
+        levels are drawn inside the step, seed + 1).  A group's rows are a
+        slice of the batch; row_base keeps the sampler's row numbering, so
+        any grouping gives the same rollout."""
         s = self.store
-        self.mlp.forward(s.obs[t], s.mask[t], self.M, self.seed, t, s.act[t], s.logp[t], s.val[t], s.ent[t],
-                         ctr_base=self.ctr_base)
-        # the government's uniform levels are drawn inside the step (seed + 1)
-        self.env.step(s.act[t], None, s.rew[t], self.gov_rew, s.done[t], s.obs[t + 1], s.mask[t + 1])
+        for g, (e0, e1, r0, r1) in enumerate(self.groups):
+            with self.group_streams.stream(g):
+                self.mlp.forward(s.obs[t][r0:r1], s.mask[t][r0:r1], r1 - r0, self.seed, t, s.act[t][r0:r1],
+                                 s.logp[t][r0:r1], s.val[t][r0:r1], s.ent[t][r0:r1], ctr_base=self.ctr_base,
+                                 row_base=r0)
+                self.env.step(s.act[t], None, s.rew[t], self.gov_rew, s.done[t], s.obs[t + 1], s.mask[t + 1],
+                              economies=(e0, e1))
 
     def _collect_launches(self):
+        self.group_streams.fork()
         for t in range(self.T):
             self.rollout_step(t)
+        self.group_streams.join()
         s = self.store
         self.mlp.forward(s.obs[self.T], s.mask[self.T], self.M, self.seed, self.T, s.scratch_act, s.scratch[0],
                          s.last_val, s.scratch[1], ctr_base=self.ctr_base)

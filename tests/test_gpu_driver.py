@@ -152,3 +152,37 @@ def test_step_drawn_government_levels_equal_explicit_draw():
     assert envs[0].status() == envs[1].status()
     for e in envs:
         e.close()
+
+
+def test_grouped_rollout_equals_single_stream():
+    """Economy groups on their own streams (sliced policy calls numbered by
+    row_base, ranged economy steps) give exactly the single-stream rollout,
+    from plain launches and from a replayed graph."""
+    import torch
+    a = small_trainer()
+    b = small_trainer(groups=3)
+    for k in range(2):
+        a.collect(graph=k > 0)
+        b.collect(graph=k > 0)
+        torch.cuda.synchronize()
+        for name in ("obs", "mask", "act", "logp", "val", "rew", "done", "adv", "ret"):
+            assert torch.equal(getattr(a.store, name), getattr(b.store, name)), (k, name)
+        a.next_rollout()
+        b.next_rollout()
+    a.close()
+    b.close()
+
+
+def test_env_step_range_rejects_bad_ranges():
+    import torch
+    from paper_2410_22165_amd import binding
+    cfg = W.env_config(E=4, N=10, R=2, P=5, X=4, P_tax=5, K=3, T=20, seed=1)
+    env = binding.Env(cfg, W.obs_scales(cfg))
+    env.set_gov_draw(True, 1)
+    bu = env.buffers()
+    for rng in ((-1, 2), (0, 5), (3, 2)):
+        with pytest.raises(binding.EconError):
+            env.step(bu["act"], None, bu["rew"], bu["gov_rew"], bu["done"], bu["obs"], bu["mask"], economies=rng)
+    env.step(bu["act"], None, bu["rew"], bu["gov_rew"], bu["done"], bu["obs"], bu["mask"], economies=(2, 2))
+    torch.cuda.synchronize()
+    env.close()

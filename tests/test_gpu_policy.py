@@ -164,3 +164,22 @@ def test_empty_batch_is_a_no_op():
     mlp.forward(obs, mask, 0, 1, 0, *o)
     torch.cuda.synchronize()
     assert all((t.cpu() == 7).all() for t in o)
+
+
+def test_row_slices_with_row_base_equal_one_call():
+    """Three slices drawn separately (row_base = first row) give bit for bit
+    the results of one call over the whole batch."""
+    import torch
+    from paper_2410_22165_amd import binding
+    D, Ds, H, A, M = 35, 40, 256, 125, 700
+    mlp = binding.Mlp(D, Ds, H, A, W.policy_weights(D, H, A, seed=2))
+    obs = torch.from_numpy(W.synthetic_obs(M, D, Ds, 2).view(np.int16)).cuda()
+    mask = torch.from_numpy(W.synthetic_masks(M, A, 2).view(np.int32)).cuda()
+    full = [torch.zeros(M, dtype=torch.int32, device="cuda")] + [torch.zeros(M, device="cuda") for _ in range(3)]
+    part = [torch.zeros_like(t) for t in full]
+    mlp.forward(obs, mask, M, 11, 3, *full)
+    for r0, r1 in ((0, 129), (129, 500), (500, 700)):
+        mlp.forward(obs[r0:r1], mask[r0:r1], r1 - r0, 11, 3, *[t[r0:r1] for t in part], row_base=r0)
+    torch.cuda.synchronize()
+    for a, b in zip(full, part):
+        assert torch.equal(a, b)
