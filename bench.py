@@ -228,7 +228,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the uneven-population and 1000-agent rollouts")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--graph-steps", type=int, default=50)
-    ap.add_argument("--groups", type=int, nargs="+", default=[1, 2, 4],
+    ap.add_argument("--groups", type=int, nargs="+", default=[1, 2, 3, 4],
                     help="economy-group counts tried for the graph-replayed step")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
