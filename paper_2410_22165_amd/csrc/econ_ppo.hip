@@ -33,15 +33,24 @@ struct PpoBatchDev {
     const float* adv;
     const float* ret;
     int64_t Mtot, a, c, begin, rows;
+    uint64_t mu;  // floor((2^64 - 1) / Mtot): Barrett reciprocal of the permutation modulus
 };
 
 struct PpoHp {
     float clip, vclip, vf_coef, ent_coef;
 };
 
+// sample behind minibatch row j: (a (begin + j) + c) mod Mtot.  With a, c,
+// begin + j < Mtot <= 2^31 - 1 the argument is below 2^63, and the Barrett
+// quotient umulhi(x, mu) undershoots floor(x / Mtot) by at most 2.
 __device__ inline int64_t sample_of(const PpoBatchDev& B, int64_t j)
 {
-    return (int64_t)(((uint64_t)B.a * (uint64_t)(B.begin + j) + (uint64_t)B.c) % (uint64_t)B.Mtot);
+    const uint64_t M = (uint64_t)B.Mtot;
+    const uint64_t x = (uint64_t)B.a * (uint64_t)(B.begin + j) + (uint64_t)B.c;
+    uint64_t r = x - __umul64hi(x, B.mu) * M;
+    r = r >= M ? r - M : r;
+    r = r >= M ? r - M : r;
+    return (int64_t)r;
 }
 
 // ---------------------------------------------------------------------------
@@ -745,7 +754,7 @@ int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t*
     const int64_t a = b->M_total == 1 ? 1 : b->perm_a % b->M_total;
     if (a == 0) return EJ_EINVAL;
     PpoBatchDev B{b->obs, b->mask, b->act, b->logp_old, b->val_old, b->adv, b->ret, b->M_total, a,
-                  b->perm_c % b->M_total, b->row_begin, b->rows};
+                  b->perm_c % b->M_total, b->row_begin, b->rows, UINT64_MAX / (uint64_t)b->M_total};
     PpoHp h{hp->clip, hp->vclip, hp->vf_coef, hp->ent_coef};
     const int W = (m->A + 31) / 32;
     double* advp = (double*)(ws + w.o_adv);
