@@ -399,7 +399,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32 economy + bf16 MFMA / fp32 policy",
+        "dtype": "int32+bf16",
         "data": "synthetic (seed-generated economies; random-init policy weights)",
         "config": {"workload": WORKLOAD, "E": cfg["E"], "N": cfg["N"], "R": cfg["R"], "P": cfg["P"],
                    "X": cfg["X"], "P_tax": cfg["P_tax"], "K": cfg["K"], "T": cfg["T"],
