@@ -311,7 +311,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     // output also leaves as m-blocks for the weight gradients
     f32x4 acc[TR][CTW];
     uint32_t m1[TR], m2[TR];
-    dense_cs<TR, CTW, 2>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
+    dense_cs<TR, CTW, 2, true, 2, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
     lds_barrier();  // every wave is done reading the observations
     ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias, hbuf, HS, col0, m1);
     lds_barrier();
@@ -330,7 +330,8 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     const int a_taken = __float_as_int(rinfo[srow]);
     auto logit_chunk = [&](int c) {
         f32x4 acc3[TR][2];
-        dense_cs<TR, 2, H / 32>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32, 32 * wave);
+        dense_cs<TR, 2, H / 32, true, 3, true>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32,
+                                                32 * wave);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
             const int cc = 32 * wave + ct * 16 + (l & 15);
@@ -465,9 +466,10 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         lds_barrier();
         tile_to_mblocks(ybuf, YS, TILE, 128, TdY, mb0, d.A1p, c * 128);  // dY for dW3
         if (c == 0)
-            dense_cs<TR, CTW, 4, true>(dh, ybuf, YS, work + d.oW3b, (int64_t)H * 32, col0);
+            dense_cs<TR, CTW, 4, true, 3, true>(dh, ybuf, YS, work + d.oW3b, (int64_t)H * 32, col0);
         else
-            dense_cs<TR, CTW, 4, false>(dh, ybuf, YS, work + d.oW3b + (int64_t)c * 4 * H * 32, (int64_t)H * 32, col0);
+            dense_cs<TR, CTW, 4, false, 3, true>(dh, ybuf, YS, work + d.oW3b + (int64_t)c * 4 * H * 32, (int64_t)H * 32,
+                                                 col0);
     }
 
     // ---- dh2 = (dY W3^T) * [h2 > 0] -> LDS (A operand of the next product) and m-blocks
