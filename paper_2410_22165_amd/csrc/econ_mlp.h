@@ -25,6 +25,8 @@ struct MlpDims {
 
 __host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+constexpr int K1P = 64;  // first-layer input padded to 64 (one layout for every D <= 64)
+
 __host__ inline int mlp_dims(int D, int Ds, int H, int A, MlpDims* d)
 {
     if (D <= 0 || D > 64 || Ds < D || (Ds & 7) != 0 || Ds > 64) return EJ_EUNSUPPORTED;
@@ -35,7 +37,7 @@ __host__ inline int mlp_dims(int D, int Ds, int H, int A, MlpDims* d)
     d->H = H;
     d->A = A;
     d->A1 = A + 1;
-    d->K1p = 64;  // first-layer input padded to 64 (one layout for every D <= 64)
+    d->K1p = K1P;
     d->A1p = round_up(A + 1, 128);
     d->NC = d->A1p / 128;
     int64_t o = 0;

@@ -68,13 +68,19 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     };
     draw_uniforms(0);
     // observation tile -> activation buffer columns [0, K1p); mask rows -> LDS
-    const int ppr = d.K1p / 8;
-    for (int p = threadIdx.x; p < TILE * ppr; p += 256) {
-        const int r = p / ppr, cc = p - r * ppr;
+    // (TILE x K1P / 8 pieces of 16 bytes: every load is issued before the first store)
+    constexpr int NPC = TILE * (K1P / 8) / 256;
+    uint4 pv[NPC];
+#pragma unroll
+    for (int i = 0; i < NPC; ++i) {
+        const int p = threadIdx.x + 256 * i, r = p >> 3, cc = p & 7;
         const int64_t row = row0 + r;
-        uint4 v = {0u, 0u, 0u, 0u};
-        if (row < M && cc * 8 < d.Ds) v = *(const uint4*)(obs + row * d.Ds + cc * 8);
-        *(uint4*)(hbuf + r * HS + cc * 8) = v;
+        pv[i] = (row < M && cc * 8 < d.Ds) ? *(const uint4*)(obs + row * d.Ds + cc * 8) : uint4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int i = 0; i < NPC; ++i) {
+        const int p = threadIdx.x + 256 * i;
+        *(uint4*)(hbuf + (p >> 3) * HS + (p & 7) * 8) = pv[i];
     }
     for (int p = threadIdx.x; p < TILE * W; p += 256) {
         const int64_t row = row0 + p / W;

@@ -282,9 +282,6 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
             ah = (B.adv[sidx] - stats[0]) * stats[1];
             rt = B.ret[sidx];
             valid = 1.f;
-            for (int w = 0; w < W; ++w) smask[r * W + w] = B.mask[sidx * W + w];
-        } else {
-            for (int w = 0; w < W; ++w) smask[r * W + w] = 0u;
         }
         rinfo[0 * TILE + r] = va;
         rinfo[1 * TILE + r] = lpo;
@@ -293,15 +290,27 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         rinfo[4 * TILE + r] = rt;
         rinfo[5 * TILE + r] = valid;
     }
+    for (int p = threadIdx.x; p < TILE * W; p += 256) {  // mask words, spread over the workgroup
+        const int r = p / W;
+        const int64_t j = tile_row0 + r;
+        smask[p] = j < B.rows ? B.mask[sample_of(B, j) * W + (p - r * W)] : 0u;
+    }
     for (int p = threadIdx.x; p < 2 * H + d.A1p; p += 256)
         sbias[p] = p < H ? params[d.ob1 + p] : p < 2 * H ? params[d.ob2 + p - H] : (p - 2 * H < d.A1 ? params[d.ob3 + p - 2 * H] : 0.f);
-    const int ppr = d.K1p / 8;
-    for (int p = threadIdx.x; p < TILE * ppr; p += 256) {
-        const int r = p / ppr, cc = p - r * ppr;
+    // (TILE x K1P / 8 pieces of 16 bytes: every load is issued before the first store)
+    constexpr int NPC = TILE * (K1P / 8) / 256;
+    uint4 pv[NPC];
+#pragma unroll
+    for (int i = 0; i < NPC; ++i) {
+        const int p = threadIdx.x + 256 * i, r = p >> 3, cc = p & 7;
         const int64_t j = tile_row0 + r;
-        uint4 v = {0u, 0u, 0u, 0u};
-        if (j < B.rows && cc * 8 < d.Ds) v = *(const uint4*)(B.obs + sample_of(B, j) * d.Ds + cc * 8);
-        *(uint4*)(hbuf + r * HS + cc * 8) = v;
+        pv[i] = (j < B.rows && cc * 8 < d.Ds) ? *(const uint4*)(B.obs + sample_of(B, j) * d.Ds + cc * 8)
+                                               : uint4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int i = 0; i < NPC; ++i) {
+        const int p = threadIdx.x + 256 * i;
+        *(uint4*)(hbuf + (p >> 3) * HS + (p & 7) * 8) = pv[i];
     }
     lds_barrier();
     const int64_t mb0 = tile_row0 >> 5;
