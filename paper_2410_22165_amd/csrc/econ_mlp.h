@@ -266,6 +266,28 @@ __device__ inline void epilogue_relu_cs(const f32x4 (&acc)[TR][CTW], const float
 constexpr int ZQ = 36, ZS = 4 * ZQ;
 __device__ inline int zcol(int cc) { return (cc >> 5) * ZQ + (cc & 31); }
 
+// b1 [H], b2 [H], b3 [A1p] (zero beyond A1) -> sbias, by a 256-thread
+// workgroup; all loads are issued before the first store (A1p <= 1024)
+template <int H>
+__device__ inline void load_biases(const MlpDims& d, const float* __restrict__ params, float* sbias)
+{
+    constexpr int NI = (2 * H + 1024 + 255) / 256;
+    const int n = 2 * H + d.A1p;
+    float v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int p = threadIdx.x + 256 * i;
+        v[i] = p >= n ? 0.f
+                      : p < H ? params[d.ob1 + p]
+                              : p < 2 * H ? params[d.ob2 + p - H] : (p - 2 * H < d.A1 ? params[d.ob3 + p - 2 * H] : 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int p = threadIdx.x + 256 * i;
+        if (p < n) sbias[p] = v[i];
+    }
+}
+
 // bias + ReLU, rounded to bf16, written to the wave's own rows of hbuf
 template <int RT, int CT>
 __device__ inline void epilogue_relu(const f32x4 (&acc)[RT][CT], const float* __restrict__ bias, uint16_t* hbuf,

@@ -86,8 +86,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
         const int64_t row = row0 + p / W;
         smask[p] = row < M ? mask[row0 * W + p] : 0u;
     }
-    for (int p = threadIdx.x; p < 2 * H + d.A1p; p += 256)
-        sbias[p] = p < H ? params[d.ob1 + p] : p < 2 * H ? params[d.ob2 + p - H] : (p - 2 * H < d.A1 ? params[d.ob3 + p - 2 * H] : 0.f);
+    load_biases<H>(d, params, sbias);
 
     // All three layers are split by columns: wave w computes every row of the
     // tile for a quarter of the output columns, with weight fragments loaded

@@ -295,8 +295,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         const int64_t j = tile_row0 + r;
         smask[p] = j < B.rows ? B.mask[sample_of(B, j) * W + (p - r * W)] : 0u;
     }
-    for (int p = threadIdx.x; p < 2 * H + d.A1p; p += 256)
-        sbias[p] = p < H ? params[d.ob1 + p] : p < 2 * H ? params[d.ob2 + p - H] : (p - 2 * H < d.A1 ? params[d.ob3 + p - 2 * H] : 0.f);
+    load_biases<H>(d, params, sbias);
     // (TILE x K1P / 8 pieces of 16 bytes: every load is issued before the first store)
     constexpr int NPC = TILE * (K1P / 8) / 256;
     uint4 pv[NPC];
