@@ -98,6 +98,9 @@ __host__ __device__ inline float bf16_to_f32(uint16_t b)
 // ---------------------------------------------------------------------------
 // wave64 primitives
 // ---------------------------------------------------------------------------
+// device arrays read with 16-byte vector loads must be 16-byte aligned
+__host__ inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 __device__ inline int lane_id() { return (int)(threadIdx.x & 63u); }
 
 template <typename T>

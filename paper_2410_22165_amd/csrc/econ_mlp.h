@@ -203,8 +203,11 @@ __device__ inline void dense_layer(f32x4 (&acc)[RT][N / 16], const uint16_t* abu
 // A fragments come from LDS one k-step ahead.  Every A fragment feeds CTW
 // MFMAs and every B fragment TR, and no weight passes through LDS.  The
 // caller synchronises before (abuf complete) and after (before abuf is
-// overwritten).  ZERO = false accumulates onto acc.
-template <int TR, int CTW, int NK, bool ZERO = true, int PF = 2, bool PIN = false>
+// overwritten).  ZERO = false accumulates onto acc.  TRANS swaps the MFMA
+// operands, which transposes each accumulator tile: lane l then holds row
+// l % 16 and the four adjacent columns 4 (l / 16) .. + 3 (instead of column
+// l % 16 of rows 4 (l / 16) .. + 3), so an epilogue stores 4 columns at once.
+template <int TR, int CTW, int NK, bool ZERO = true, int PF = 2, bool PIN = false, bool TRANS = false>
 __device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int as,
                                 const uint16_t* __restrict__ wglob, int64_t kstride, int col0)
 {
@@ -235,7 +238,9 @@ __device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int
 #pragma unroll
         for (int ct = 0; ct < CTW; ++ct)
 #pragma unroll
-            for (int rt = 0; rt < TR; ++rt) acc[rt][ct] = mfma16(aq[kt][rt], bq[kt][ct], acc[rt][ct]);
+            for (int rt = 0; rt < TR; ++rt)
+                acc[rt][ct] = TRANS ? mfma16(bq[kt][ct], aq[kt][rt], acc[rt][ct])
+                                    : mfma16(aq[kt][rt], bq[kt][ct], acc[rt][ct]);
     }
 }
 
@@ -257,6 +262,28 @@ __device__ inline void epilogue_relu_cs(const f32x4 (&acc)[TR][CTW], const float
                 v = v > 0.f ? v : 0.f;
                 hbuf[(rt * 16 + 4 * (l >> 4) + i) * hs + col] = f32_to_bf16(v);
             }
+    }
+}
+
+// The same for transposed accumulators (dense_cs with TRANS): one 8-byte
+// store of 4 adjacent bf16 columns per tile
+template <int TR, int CTW>
+__device__ inline void epilogue_relu_cs_t(const f32x4 (&acc)[TR][CTW], const float* __restrict__ bias,
+                                          uint16_t* hbuf, int hs, int col0)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int ct = 0; ct < CTW; ++ct) {
+        const int col = col0 + ct * 16 + 4 * (l >> 4);
+        const float4 b = *(const float4*)(bias + col);
+#pragma unroll
+        for (int rt = 0; rt < TR; ++rt) {
+            const float v0 = fmaxf(acc[rt][ct][0] + b.x, 0.f), v1 = fmaxf(acc[rt][ct][1] + b.y, 0.f);
+            const float v2 = fmaxf(acc[rt][ct][2] + b.z, 0.f), v3 = fmaxf(acc[rt][ct][3] + b.w, 0.f);
+            const uint2 pk = {(uint32_t)f32_to_bf16(v0) | ((uint32_t)f32_to_bf16(v1) << 16),
+                              (uint32_t)f32_to_bf16(v2) | ((uint32_t)f32_to_bf16(v3) << 16)};
+            *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) = pk;
+        }
     }
 }
 

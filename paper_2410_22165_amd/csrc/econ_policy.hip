@@ -28,13 +28,13 @@ size_t policy_lds_bytes(int W, int A1p)
     using T = MlpTile<H, RPW>;
     const size_t hb = (size_t)T::TILE * T::HS * 2, zb = (size_t)T::TILE * ZS * 4;
     const size_t region = A1p == 128 ? (hb > zb ? hb : zb) : hb + zb;
-    return region + (size_t)T::TILE * W * 4 + (size_t)T::TILE * 4 * 4 + (size_t)(2 * H + A1p) * 4;
+    return region + (size_t)T::TILE * W * 4 + (size_t)T::TILE * 4 * 4 + (size_t)A1p * 4;
 }
 
 // The workgroup's threads talk through LDS only (its barriers order LDS).
-// 64-row tiles with H <= 256 take 37 KB of LDS and 160 VGPRs: three workgroups per CU
+// 64-row tiles with H <= 256 take 38.5 KB of LDS and 128 VGPRs: four workgroups per CU
 template <int H, int RPW_>
-__global__ void __launch_bounds__(256, (RPW_ == 16 && H <= 256) ? 3 : 1)
+__global__ void __launch_bounds__(256, (RPW_ == 16 && H <= 256) ? 4 : 1)
 policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
                       const uint16_t* __restrict__ obs, const uint32_t* __restrict__ mask, int64_t M, int64_t row_base,
                       int W, uint64_t seed, uint64_t ctr_arg, const uint64_t* __restrict__ ctr_base,
@@ -51,7 +51,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     float* zbuf = (float*)(smem + (d.A1p == 128 ? 0 : hb));  // logit chunk [TILE][ZS]
     uint32_t* smask = (uint32_t*)(smem + region);            // [TILE][W]
     float* urow = (float*)(smask + TILE * W);                 // [TILE][4] uniforms of the current chunk pair
-    float* sbias = urow + TILE * 4;                           // b1 [H], b2 [H], b3 [A1p] (zero padded)
+    float* sb3 = urow + TILE * 4;                             // b3 [A1p] (zero padded)
     const int wave = threadIdx.x >> 6, l = lane_id();
     const int64_t row0 = (int64_t)blockIdx.x * TILE;
 
@@ -86,23 +86,24 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
         const int64_t row = row0 + p / W;
         smask[p] = row < M ? mask[row0 * W + p] : 0u;
     }
-    load_biases<H>(d, params, sbias);
+    for (int p = threadIdx.x; p < d.A1p; p += 256) sb3[p] = p < d.A1 ? params[d.ob3 + p] : 0.f;
 
     // All three layers are split by columns: wave w computes every row of the
     // tile for a quarter of the output columns, with weight fragments loaded
-    // from L2 straight into registers.
+    // from L2 straight into registers.  The accumulators are transposed
+    // (TRANS): a lane holds 4 adjacent columns of one row, stored at once.
     {
         constexpr int CTW = H / 64;
         const int col0 = wave * (H / 4);
         f32x4 acc[TR][CTW];
         lds_barrier();  // observation tile in LDS
-        dense_cs<TR, CTW, 2>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
+        dense_cs<TR, CTW, 2, true, 2, false, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
         lds_barrier();  // every wave is done reading the observations
-        epilogue_relu_cs<TR, CTW>(acc, sbias, hbuf, HS, col0);
+        epilogue_relu_cs_t<TR, CTW>(acc, params + d.ob1, hbuf, HS, col0);
         lds_barrier();
-        dense_cs<TR, CTW, H / 32>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
+        dense_cs<TR, CTW, H / 32, true, 2, false, true>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
         lds_barrier();
-        epilogue_relu_cs<TR, CTW>(acc, sbias + H, hbuf, HS, col0);
+        epilogue_relu_cs_t<TR, CTW>(acc, params + d.ob2, hbuf, HS, col0);
         lds_barrier();
     }
 
@@ -125,18 +126,19 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     for (int c = 0; c < d.NC; ++c) {
         {
             f32x4 acc3[TR][2];
-            dense_cs<TR, 2, H / 32>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32,
-                                    32 * wave);
+            dense_cs<TR, 2, H / 32, true, 2, false, true>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32,
+                                                          (int64_t)d.A1p * 32, 32 * wave);
             if (c > 0 && (c & 1) == 0) draw_uniforms(c);  // the next pair of chunks
             if (d.A1p == 128) lds_barrier();  // the logit chunk overwrites the activations
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
-                const int cc = 32 * wave + ct * 16 + (l & 15);
-                const float b = sbias[2 * H + c * 128 + cc];
+                const int cc = 32 * wave + ct * 16 + 4 * (l >> 4);  // 4 adjacent columns of row l % 16
+                const float4 b = *(const float4*)(sb3 + c * 128 + cc);
 #pragma unroll
                 for (int rt = 0; rt < TR; ++rt)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) zbuf[(rt * 16 + 4 * (l >> 4) + i) * ZS + zcol(cc)] = acc3[rt][ct][i] + b;
+                    *(float4*)(zbuf + (rt * 16 + (l & 15)) * ZS + zcol(cc)) =
+                        float4{acc3[rt][ct][0] + b.x, acc3[rt][ct][1] + b.y, acc3[rt][ct][2] + b.z,
+                               acc3[rt][ct][3] + b.w};
             }
         }
         lds_barrier();  // the chunk's logits and uniforms are in LDS
@@ -144,10 +146,11 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
 #pragma unroll
         for (int k = 0; k < SR; ++k) {
             const int rloc = wave * RPW + k * 16 + (l >> 2);
+            const float* zrow = zbuf + rloc * ZS;
             float z[32];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                const float4 v = *(const float4*)(zbuf + rloc * ZS + q * ZQ + 4 * j);
+                const float4 v = *(const float4*)(zrow + q * ZQ + 4 * j);
                 z[4 * j] = v.x;
                 z[4 * j + 1] = v.y;
                 z[4 * j + 2] = v.z;
@@ -158,30 +161,34 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
                 for (int j = 0; j < 32; ++j)
                     if (colq + j < d.A) logits[(row0 + rloc) * d.A + colq + j] = z[j];
             }
-            const int wi = c * 4 + q;
-            const uint32_t mw = wi < W ? smask[rloc * W + wi] : 0u;
+            // allowed actions of this lane's quarter (bits past the last action cleared)
+            const int wi = c * 4 + q, nact = d.A - colq;
+            uint32_t mw = wi < W ? smask[rloc * W + wi] : 0u;
+            mw = nact >= 32 ? mw : (nact <= 0 ? 0u : mw & ((1u << nact) - 1u));
             const float u1 = urow[rloc * 4 + 2 * (c & 1)], u2 = urow[rloc * 4 + 2 * (c & 1) + 1];
-            float zmax = NEG, zval = 0.f;
+            // masked logits: -inf where not allowed
+            float zmax = NEG;
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
-                const bool ok = colq + j < d.A && ((mw >> j) & 1u);
-                zmax = ok ? fmaxf(zmax, z[j]) : zmax;
-                zval = colq + j == d.A ? z[j] : zval;  // the value head sits right after the logits
+                z[j] = ((mw >> j) & 1u) ? z[j] : NEG;
+                zmax = fmaxf(zmax, z[j]);
             }
             const float mc = quad_max(zmax);
             const bool any = mc != NEG;
+            const float ms = any ? mc : 0.f;  // finite shift: exp(-inf - ms) = 0 for masked actions
+            // weights exp(z - mc), kept in z; their sum and sum of w (z - mc)
             float own = 0.f, tl = 0.f;
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
-                const bool ok = colq + j < d.A && ((mw >> j) & 1u);
-                const float e = ok ? __expf(z[j] - mc) : 0.f;
-                tl += ok ? e * (z[j] - mc) : 0.f;
+                const float dz = z[j] - ms;
+                const float e = __expf(dz);
+                tl += e > 0.f ? e * dz : 0.f;
                 own += e;
+                z[j] = e;
             }
             const float before = quad_scan(own, q) - own;
             const float Sc = quad_sum(own);
             const float Tc = quad_sum(tl);
-            const float zv = quad_sum(zval);
             const float m = sM[k], S0 = sS[k], T0 = sT[k], W0 = sW[k];
             const float mn = any ? fmaxf(m, mc) : m;
             const float fo = (m == NEG) ? 0.f : __expf(m - mn), fc = any ? __expf(mc - mn) : 0.f;
@@ -190,29 +197,30 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
             const float Wn = W0 * fo + Sc * fc;
             const bool take = any && u1 * Wn < Sc * fc;
             // inverse CDF inside the chunk (action order): the first allowed
-            // action whose cumulative weight exceeds u2 * Sc
+            // action whose cumulative weight exceeds u2 * Sc.  The running sum
+            // never decreases, so the actions where it exceeds the target form
+            // a suffix of the quarter; its first element is allowed (its weight
+            // is positive) unless the suffix is the whole quarter, where the
+            // first allowed action is taken.
             const float target = u2 * Sc;
-            int key = 1 << 20, last = -1;
             float cum = before;
+            int below = 0;  // actions of the quarter where the running sum is still <= target
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
-                const bool ok = colq + j < d.A && ((mw >> j) & 1u);
-                cum += ok ? __expf(z[j] - mc) : 0.f;  // the same weights, recomputed (registers)
-                key = (ok && cum > target && key == (1 << 20)) ? 32 * q + j : key;
-                last = ok ? 32 * q + j : last;
+                cum += z[j];
+                below += cum <= target ? 1 : 0;
             }
+            constexpr int NONE = 1 << 20;
+            int key = below == 32 ? NONE : below > 0 ? 32 * q + below : mw ? 32 * q + __builtin_ctz(mw) : NONE;
             key = quad_min_i(key);
-            const int top = quad_max_i(last);
-            key = key == (1 << 20) ? top : key;  // rounding put the target at the top
-            float zk = 0.f;
-#pragma unroll
-            for (int j = 0; j < 32; ++j) zk = 32 * q + j == key ? z[j] : zk;
-            zk = quad_sum(zk);
+            const int top = quad_max_i(mw ? 32 * q + 31 - __builtin_clz(mw) : -1);
+            key = key == NONE ? top : key;  // rounding put the target at the top
+            const float zk = zrow[zcol(key < 0 ? 0 : key)];  // the chosen action's logit
             sM[k] = mn;
             sS[k] = Sn;
             sT[k] = Tn;
             sW[k] = Wn;
-            sV[k] += zv;
+            if (c == d.NC - 1) sV[k] = zrow[zcol(d.A - c * 128)];  // the value head sits right after the logits
             sA[k] = take ? c * 128 + key : sA[k];
             sZ[k] = take ? zk : sZ[k];
         }
@@ -357,6 +365,7 @@ int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_
     if (rc != EJ_OK) return rc;
     if (M < 0 || row_base < 0 || !d_params || !d_work || !d_obs || !d_mask || !d_act || !d_logp || !d_val || !d_ent)
         return EJ_EINVAL;
+    if (!aligned16(d_params) || !aligned16(d_work) || !aligned16(d_obs)) return EJ_EINVAL;
     if (M == 0) return EJ_OK;
     const int W = (m->A + 31) / 32;
     hipStream_t st = (hipStream_t)stream;

@@ -750,6 +750,9 @@ int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t*
 {
     if (!m || !d_params || !d_work || !b || !hp || !d_workspace || !d_grads || !d_loss) return EJ_EINVAL;
     if (!b->obs || !b->mask || !b->act || !b->logp_old || !b->val_old || !b->adv || !b->ret) return EJ_EINVAL;
+    if (!aligned16(d_params) || !aligned16(d_work) || !aligned16(b->obs) || !aligned16(d_workspace) ||
+        !aligned16(d_grads))
+        return EJ_EINVAL;
     if (b->M_total <= 0 || b->M_total > INT32_MAX || b->rows <= 0 || b->perm_a <= 0 || b->perm_c < 0 ||
         b->row_begin < 0 || b->row_begin + b->rows > INT32_MAX)
         return EJ_EINVAL;

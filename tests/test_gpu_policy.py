@@ -183,3 +183,28 @@ def test_row_slices_with_row_base_equal_one_call():
     torch.cuda.synchronize()
     for a, b in zip(full, part):
         assert torch.equal(a, b)
+
+
+def test_misaligned_parameters_are_rejected():
+    """A parameter or observation pointer that is not 16-byte aligned returns
+    EJ_EINVAL before anything is launched; the outputs stay untouched."""
+    import ctypes as C
+    import torch
+    from paper_2410_22165_amd import binding
+    D, Ds, H, A = 35, 40, 256, 125
+    mlp = binding.Mlp(D, Ds, H, A, W.policy_weights(D, H, A, seed=1))
+    M = 64
+    obs = torch.zeros((M + 1, Ds), dtype=torch.int16, device="cuda")
+    mask = torch.full((M, 4), -1, dtype=torch.int32, device="cuda")
+    o = [torch.full((M,), 7, dtype=torch.int32, device="cuda")] + [torch.full((M,), 7.0, device="cuda") for _ in range(3)]
+    L = binding.lib()
+    P = lambda t, off=0: C.c_void_p(t.data_ptr() + off)
+    outs = [P(t) for t in o]
+    rc = L.ej_policy_forward(C.byref(mlp.desc), P(mlp.params, 4), P(mlp.work), P(obs), P(mask), M, 0, 1, 0, None,
+                             *outs, None, None)
+    assert rc == -1
+    rc = L.ej_policy_forward(C.byref(mlp.desc), P(mlp.params), P(mlp.work), P(obs, 8), P(mask), M, 0, 1, 0, None,
+                             *outs, None, None)
+    assert rc == -1
+    torch.cuda.synchronize()
+    assert all((t.cpu() == 7).all() for t in o)
