@@ -265,21 +265,35 @@ __device__ inline void epilogue_relu_cs(const f32x4 (&acc)[TR][CTW], const float
     }
 }
 
-// The same for transposed accumulators (dense_cs with TRANS): one 8-byte
-// store of 4 adjacent bf16 columns per tile
+// Transposed accumulators (dense_cs with TRANS) started at the bias: lane
+// l's four columns col0 + 16 ct + 4 (l / 16) .. + 3 of every row tile.  The
+// loads go out with the layer's first weight fragments (fp32 bias, 16-byte
+// aligned), so the epilogue has no bias to wait for.
 template <int TR, int CTW>
-__device__ inline void epilogue_relu_cs_t(const f32x4 (&acc)[TR][CTW], const float* __restrict__ bias,
-                                          uint16_t* hbuf, int hs, int col0)
+__device__ inline void bias_init_t(f32x4 (&acc)[TR][CTW], const float* __restrict__ bias, int col0)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int ct = 0; ct < CTW; ++ct) {
+        const float4 b = *(const float4*)(bias + col0 + ct * 16 + 4 * (l >> 4));
+#pragma unroll
+        for (int rt = 0; rt < TR; ++rt) acc[rt][ct] = f32x4{b.x, b.y, b.z, b.w};
+    }
+}
+
+// ReLU of transposed accumulators (bias included), rounded to bf16: one
+// 8-byte store of 4 adjacent columns per tile
+template <int TR, int CTW>
+__device__ inline void relu_store_t(const f32x4 (&acc)[TR][CTW], uint16_t* hbuf, int hs, int col0)
 {
     const int l = lane_id();
 #pragma unroll
     for (int ct = 0; ct < CTW; ++ct) {
         const int col = col0 + ct * 16 + 4 * (l >> 4);
-        const float4 b = *(const float4*)(bias + col);
 #pragma unroll
         for (int rt = 0; rt < TR; ++rt) {
-            const float v0 = fmaxf(acc[rt][ct][0] + b.x, 0.f), v1 = fmaxf(acc[rt][ct][1] + b.y, 0.f);
-            const float v2 = fmaxf(acc[rt][ct][2] + b.z, 0.f), v3 = fmaxf(acc[rt][ct][3] + b.w, 0.f);
+            const float v0 = fmaxf(acc[rt][ct][0], 0.f), v1 = fmaxf(acc[rt][ct][1], 0.f);
+            const float v2 = fmaxf(acc[rt][ct][2], 0.f), v3 = fmaxf(acc[rt][ct][3], 0.f);
             const uint2 pk = {(uint32_t)f32_to_bf16(v0) | ((uint32_t)f32_to_bf16(v1) << 16),
                               (uint32_t)f32_to_bf16(v2) | ((uint32_t)f32_to_bf16(v3) << 16)};
             *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) = pk;

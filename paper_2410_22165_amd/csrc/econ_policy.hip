@@ -91,19 +91,22 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     // All three layers are split by columns: wave w computes every row of the
     // tile for a quarter of the output columns, with weight fragments loaded
     // from L2 straight into registers.  The accumulators are transposed
-    // (TRANS): a lane holds 4 adjacent columns of one row, stored at once.
+    // (TRANS): a lane holds 4 adjacent columns of one row, stored at once,
+    // and start at the bias.
     {
         constexpr int CTW = H / 64;
         const int col0 = wave * (H / 4);
         f32x4 acc[TR][CTW];
+        bias_init_t<TR, CTW>(acc, params + d.ob1, col0);
         lds_barrier();  // observation tile in LDS
-        dense_cs<TR, CTW, 2, true, 2, false, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
+        dense_cs<TR, CTW, 2, false, 2, false, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
         lds_barrier();  // every wave is done reading the observations
-        epilogue_relu_cs_t<TR, CTW>(acc, params + d.ob1, hbuf, HS, col0);
+        relu_store_t<TR, CTW>(acc, hbuf, HS, col0);
+        bias_init_t<TR, CTW>(acc, params + d.ob2, col0);
         lds_barrier();
-        dense_cs<TR, CTW, H / 32, true, 2, false, true>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
+        dense_cs<TR, CTW, H / 32, false, 2, false, true>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
         lds_barrier();
-        epilogue_relu_cs_t<TR, CTW>(acc, params + d.ob2, hbuf, HS, col0);
+        relu_store_t<TR, CTW>(acc, hbuf, HS, col0);
         lds_barrier();
     }
 
