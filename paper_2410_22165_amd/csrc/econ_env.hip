@@ -61,6 +61,7 @@ struct EnvState {
     const int32_t* env_row;  // [E+1] first row of the economy
     int64_t* invalid;        // [E][2] rejected population actions / government levels
     double* ug;              // [E]   social welfare of the current state (NaN: not known)
+    double* u;               // [slots] utility of each agent's current state (NaN: not known)
     unsigned int* queue;     // [2]   persistent launch: next queue slot, finished workgroups
     const int32_t* order;    // [E]   persistent launch: economies by decreasing population
     int32_t E;
@@ -457,17 +458,18 @@ __device__ inline double social_welfare_block(const EnvParams& P, const Lds& L, 
         // smaller keys.  Entries n.. hold INT64_MAX, so the count runs over
         // whole groups of 8 (S2 >= that).
         const int n8 = (n + 7) & ~7;
+        const longlong2* sb2 = (const longlong2*)L.sortbuf;  // two keys per 16-byte read
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             const int64_t key = L.sortbuf[i];
             const int64_t x = key >> 8;
             int rank = 0;
-#pragma unroll 2
-            for (int j = 0; j < n8; j += 8) {
-                int64_t y[8];
+#pragma unroll 4
+            for (int j = 0; j < n8 / 2; j += 4) {
+                longlong2 y[4];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) y[q] = L.sortbuf[j + q];
+                for (int q = 0; q < 4; ++q) y[q] = sb2[j + q];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) rank += y[q] < key;
+                for (int q = 0; q < 4; ++q) rank += (y[q].x < key) + (y[q].y < key);
             }
             num += (int64_t)(2 * rank - n + 1) * x;
             sum += x;
@@ -726,14 +728,17 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     // through LDS only, so its barriers do not wait for global memory).
     Agent<RM, XM> ag[APT];
     int a_in[APT];
+    double u0[APT];  // utility of the step-start state: cached by the previous step, NaN when unknown
     const double cached_ug = S.ug[e];  // social welfare of the step-start state, NaN when unknown
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
         const int li = tid + k * NT;
         a_in[k] = 0;
+        u0[k] = 0.0;
         if (li < n) {
             load_agent(P, S, off + li, ag[k]);
             a_in[k] = act[row0 + li];
+            u0[k] = S.u[off + li];
         }
     }
     // this bracket's rate: the government sets the period's rates at its
@@ -760,7 +765,6 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     for (int j = tid; j < S2; j += NT) L.sortbuf[j] = INT64_MAX;
     lds_barrier();
 
-    double u0[APT];
     int eff[APT];
     int my_rank[APT];
     int invalid = 0;
@@ -777,7 +781,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         my_rank[k] = 0;
         if (li < n) {
             const int64_t C = (int64_t)ag[k].coin_inv + ag[k].coin_esc;
-            u0[k] = utility(C, ag[k].labor, P.eta);
+            if (u0[k] != u0[k]) u0[k] = utility(C, ag[k].labor, P.eta);
             L.sortbuf[li] = welfare_key(C, li, n);
         }
     }
@@ -1072,6 +1076,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         const int64_t C = (int64_t)ag[k].coin_inv + ag[k].coin_esc;
         const double u1 = utility(C, ag[k].labor, P.eta);
         rew[row0 + li] = (float)(u1 - u0[k]);
+        S.u[off + li] = t + 1 >= P.T ? __builtin_nan("") : u1;  // the next step starts from this state
         L.sortbuf[li] = welfare_key(C, li, n);
     }
     lds_barrier();
@@ -1322,6 +1327,7 @@ __global__ void __launch_bounds__(1024 / APT) env_reset_kernel(const EnvParams P
         Agent<RM, XM> ag;
         reset_agent(P, e, ep, li, ag);
         store_agent(P, S, off + li, ag);
+        S.u[off + li] = __builtin_nan("");
     }
     if (threadIdx.x == 0) {
         S.env_t[e] = 0;
@@ -1379,13 +1385,14 @@ struct ej_env {
     int32_t* d_row = nullptr;
     int64_t* d_invalid = nullptr;
     double* d_ug = nullptr;
+    double* d_u = nullptr;
     unsigned int* d_queue = nullptr;
     int32_t* d_order = nullptr;
     int mode = 0, persistent_wg = 0;  // mode 0: one workgroup per economy; 1: persistent work queue
     size_t lds = 0;
     EnvState state() const
     {
-        return EnvState{d_field, d_t, d_ep, d_rates, d_n, d_off, d_row, d_invalid, d_ug, d_queue, d_order, E};
+        return EnvState{d_field, d_t, d_ep, d_rates, d_n, d_off, d_row, d_invalid, d_ug, d_u, d_queue, d_order, E};
     }
 };
 
@@ -1508,7 +1515,7 @@ int ej_env_create(const ej_env_config* cfg, const int32_t* h_n_per_env, ej_env**
               hipMalloc(&h->d_n, 4 * (size_t)h->E) == hipSuccess && hipMalloc(&h->d_off, 4 * (size_t)h->E) == hipSuccess &&
               hipMalloc(&h->d_row, 4 * (size_t)(h->E + 1)) == hipSuccess &&
               hipMalloc(&h->d_invalid, 16 * (size_t)h->E) == hipSuccess &&
-              hipMalloc(&h->d_ug, 8 * (size_t)h->E) == hipSuccess &&
+              hipMalloc(&h->d_ug, 8 * (size_t)h->E) == hipSuccess && hipMalloc(&h->d_u, 8 * (size_t)slots) == hipSuccess &&
               hipMalloc(&h->d_queue, 8) == hipSuccess && hipMalloc(&h->d_order, 4 * (size_t)h->E) == hipSuccess;
     if (!ok) {
         ej_env_destroy(h);
@@ -1518,6 +1525,7 @@ int ej_env_create(const ej_env_config* cfg, const int32_t* h_n_per_env, ej_env**
         hipMemcpy(h->d_off, h->off.data(), 4 * (size_t)h->E, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->d_row, h->row.data(), 4 * (size_t)(h->E + 1), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h->d_invalid, 0, 16 * (size_t)h->E) != hipSuccess || hipMemset(h->d_queue, 0, 8) != hipSuccess ||
+        hipMemset(h->d_u, 0xFF, 8 * (size_t)slots) != hipSuccess ||  // all-ones: NaN, utility not known
         hipMemset(h->d_field, 0, nf * (size_t)slots * 4) != hipSuccess) {
         set_last_hip_error(hipGetLastError());
         ej_env_destroy(h);
@@ -1556,6 +1564,7 @@ int ej_env_destroy(ej_env* h)
     (void)hipFree(h->d_row);
     (void)hipFree(h->d_invalid);
     (void)hipFree(h->d_ug);
+    (void)hipFree(h->d_u);
     (void)hipFree(h->d_queue);
     (void)hipFree(h->d_order);
     delete h;
@@ -1782,6 +1791,7 @@ int ej_env_set_state(ej_env* h, const ej_state_view* v, void* stream)
     EJ_HIP(hipMemcpy(h->d_rates, rates.data(), rates.size() * 4, hipMemcpyHostToDevice));
     std::vector<double> unknown((size_t)E, __builtin_nan(""));
     EJ_HIP(hipMemcpy(h->d_ug, unknown.data(), 8 * (size_t)E, hipMemcpyHostToDevice));
+    EJ_HIP(hipMemset(h->d_u, 0xFF, 8 * (size_t)h->P.Ntot));  // all-ones: NaN, utility not known
     return EJ_OK;
 }
 
