@@ -148,11 +148,12 @@ __global__ void __launch_bounds__(256) adv_stats_final(const double* __restrict_
 // the fused row kernel
 // ---------------------------------------------------------------------------
 
-// bias + ReLU of a hidden layer: bf16 into the wave's own LDS rows, the
-// m-block copy for the weight gradient, and the ReLU mask bits
-// bias + ReLU of a column-split hidden layer: bf16 activations -> hbuf (A
-// operand of the next layer and source of the m-block copy), and the ReLU
-// pattern of the wave's columns (bit 4 ct + i of bits[rt]) for the backward
+// bias + ReLU of a column-split hidden layer with transposed accumulators
+// (dense_cs with TRANS: lane l holds row 16 rt + l % 16, columns col0 +
+// 16 ct + 4 (l / 16) .. + 3): bf16 activations -> hbuf (A operand of the next
+// layer and source of the m-block copy), one 8-byte store per tile, and the
+// ReLU pattern of the lane's columns (bit 4 ct + i of bits[rt]) for the
+// backward, whose products use the same layout
 template <int TR, int CTW>
 __device__ inline void ppo_hidden_epilogue_cs(const f32x4 (&acc)[TR][CTW], const float* __restrict__ bias,
                                               uint16_t* hbuf, int hs, int col0, uint32_t (&bits)[TR])
@@ -162,20 +163,25 @@ __device__ inline void ppo_hidden_epilogue_cs(const f32x4 (&acc)[TR][CTW], const
     for (int rt = 0; rt < TR; ++rt) bits[rt] = 0u;
 #pragma unroll
     for (int ct = 0; ct < CTW; ++ct) {
-        const int col = col0 + ct * 16 + (l & 15);
-        const float b = bias[col];
+        const int col = col0 + ct * 16 + 4 * (l >> 4);
+        const float4 b = *(const float4*)(bias + col);
 #pragma unroll
-        for (int rt = 0; rt < TR; ++rt)
+        for (int rt = 0; rt < TR; ++rt) {
+            const float bb[4] = {b.x, b.y, b.z, b.w};
+            uint32_t h[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float x = acc[rt][ct][i] + b;
+                const float x = acc[rt][ct][i] + bb[i];
                 bits[rt] |= (x > 0.f ? 1u : 0u) << (ct * 4 + i);
-                hbuf[(rt * 16 + 4 * (l >> 4) + i) * hs + col] = f32_to_bf16(x > 0.f ? x : 0.f);
+                h[i] = f32_to_bf16(x > 0.f ? x : 0.f);
             }
+            *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) = uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+        }
     }
 }
 
-// masked input gradient of a column-split layer -> bf16 rows in hbuf
+// masked input gradient of a column-split layer (transposed accumulators, as
+// above) -> bf16 rows in hbuf
 template <int TR, int CTW>
 __device__ inline void ppo_masked_grad_cs(const f32x4 (&dh)[TR][CTW], const uint32_t (&bits)[TR], uint16_t* hbuf,
                                           int hs, int col0)
@@ -183,13 +189,16 @@ __device__ inline void ppo_masked_grad_cs(const f32x4 (&dh)[TR][CTW], const uint
     const int l = lane_id();
 #pragma unroll
     for (int ct = 0; ct < CTW; ++ct) {
-        const int col = col0 + ct * 16 + (l & 15);
+        const int col = col0 + ct * 16 + 4 * (l >> 4);
 #pragma unroll
-        for (int rt = 0; rt < TR; ++rt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                hbuf[(rt * 16 + 4 * (l >> 4) + i) * hs + col] =
-                    f32_to_bf16(((bits[rt] >> (ct * 4 + i)) & 1u) ? dh[rt][ct][i] : 0.f);
+        for (int rt = 0; rt < TR; ++rt) {
+            const uint32_t m = bits[rt] >> (ct * 4);
+            const float v0 = (m & 1u) ? dh[rt][ct][0] : 0.f, v1 = (m & 2u) ? dh[rt][ct][1] : 0.f;
+            const float v2 = (m & 4u) ? dh[rt][ct][2] : 0.f, v3 = (m & 8u) ? dh[rt][ct][3] : 0.f;
+            const uint2 pk = {(uint32_t)f32_to_bf16(v0) | ((uint32_t)f32_to_bf16(v1) << 16),
+                              (uint32_t)f32_to_bf16(v2) | ((uint32_t)f32_to_bf16(v3) << 16)};
+            *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) = pk;
+        }
     }
 }
 
@@ -319,12 +328,12 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     // output also leaves as m-blocks for the weight gradients
     f32x4 acc[TR][CTW];
     uint32_t m1[TR], m2[TR];
-    dense_cs<TR, CTW, 2, true, 2, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
+    dense_cs<TR, CTW, 2, true, 2, true, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
     lds_barrier();  // every wave is done reading the observations
     ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias, hbuf, HS, col0, m1);
     lds_barrier();
     tile_to_mblocks(hbuf, HS, TILE, H, Th1, mb0, H, 0);
-    dense_cs<TR, CTW, H / 32, true, 3, true>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
+    dense_cs<TR, CTW, H / 32, true, 3, true, true>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
     lds_barrier();
     ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias + H, hbuf, HS, col0, m2);
     lds_barrier();
@@ -338,16 +347,16 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     const int a_taken = __float_as_int(rinfo[srow]);
     auto logit_chunk = [&](int c) {
         f32x4 acc3[TR][2];
-        dense_cs<TR, 2, H / 32, true, 3, true>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32, (int64_t)d.A1p * 32,
-                                                32 * wave);
+        dense_cs<TR, 2, H / 32, true, 3, true, true>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32,
+                                                      (int64_t)d.A1p * 32, 32 * wave);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-            const int cc = 32 * wave + ct * 16 + (l & 15);
-            const float b = sbias[2 * H + c * 128 + cc];
+            const int cc = 32 * wave + ct * 16 + 4 * (l >> 4);  // 4 adjacent columns of row l % 16
+            const float4 b = *(const float4*)(sbias + 2 * H + c * 128 + cc);
 #pragma unroll
             for (int rt = 0; rt < TR; ++rt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) zbuf[(rt * 16 + 4 * (l >> 4) + i) * ZS + zcol(cc)] = acc3[rt][ct][i] + b;
+                *(float4*)(zbuf + (rt * 16 + (l & 15)) * ZS + zcol(cc)) =
+                    float4{acc3[rt][ct][0] + b.x, acc3[rt][ct][1] + b.y, acc3[rt][ct][2] + b.z, acc3[rt][ct][3] + b.w};
         }
     };
     auto load_row = [&](float (&z)[32]) {
@@ -474,10 +483,10 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         lds_barrier();
         tile_to_mblocks(ybuf, YS, TILE, 128, TdY, mb0, d.A1p, c * 128);  // dY for dW3
         if (c == 0)
-            dense_cs<TR, CTW, 4, true, 3, true>(dh, ybuf, YS, work + d.oW3b, (int64_t)H * 32, col0);
+            dense_cs<TR, CTW, 4, true, 3, true, true>(dh, ybuf, YS, work + d.oW3b, (int64_t)H * 32, col0);
         else
-            dense_cs<TR, CTW, 4, false, 3, true>(dh, ybuf, YS, work + d.oW3b + (int64_t)c * 4 * H * 32, (int64_t)H * 32,
-                                                 col0);
+            dense_cs<TR, CTW, 4, false, 3, true, true>(dh, ybuf, YS, work + d.oW3b + (int64_t)c * 4 * H * 32,
+                                                       (int64_t)H * 32, col0);
     }
 
     // ---- dh2 = (dY W3^T) * [h2 > 0] -> LDS (A operand of the next product) and m-blocks
@@ -486,7 +495,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     lds_barrier();
     tile_to_mblocks(hbuf, HS, TILE, H, Tdh2, mb0, H, 0);
     // ---- dh1 = (dh2 W2^T) * [h1 > 0] -> m-blocks
-    dense_cs<TR, CTW, H / 32, true, 3, true>(dh, hbuf, HS, work + d.oW2b, (int64_t)H * 32, col0);
+    dense_cs<TR, CTW, H / 32, true, 3, true, true>(dh, hbuf, HS, work + d.oW2b, (int64_t)H * 32, col0);
     lds_barrier();  // everyone is done reading dh2
     ppo_masked_grad_cs<TR, CTW>(dh, m1, hbuf, HS, col0);
     lds_barrier();
