@@ -162,3 +162,35 @@ def test_ppo_backward_deterministic():
     _, g1, l1 = gpu_backward(w, st, D, Ds, H, A, M, a, c, 0, 1500)
     _, g2, l2 = gpu_backward(w, st, D, Ds, H, A, M, a, c, 0, 1500)
     assert np.array_equal(g1, g2) and np.array_equal(l1, l2)
+
+
+def test_ppo_backward_rejects_misaligned_arrays():
+    """A gradient, workspace or observation array that is not 16-byte aligned
+    returns EJ_EINVAL before anything is launched."""
+    import ctypes as C
+    import torch
+    from paper_2410_22165_amd import binding
+    D, Ds, H, A, M = 35, 40, 256, 125, 256
+    w, st = make_storage(D, Ds, H, A, M, seed=3)
+    a, c = W.affine_permutation(M, 0, seed=3)
+    mlp = binding.Mlp(D, Ds, H, A, w)
+    dev = {k: _t(v.view(np.int16) if k == "obs" else (v.view(np.int32) if k == "mask" else v)) for k, v in st.items()}
+    nbytes = binding.ppo_workspace_bytes(mlp, M)
+    ws = torch.zeros(nbytes + 16, dtype=torch.uint8, device="cuda")
+    grads = torch.full((mlp.layout["n_params"] + 4,), 7.0, device="cuda")
+    loss = torch.zeros(4, device="cuda")
+    h = binding.EjPpoHparams(HP["clip"], HP["vclip"], HP["vf_coef"], HP["ent_coef"])
+    L = binding.lib()
+    P = lambda t, off=0: C.c_void_p(t.data_ptr() + off)
+
+    def call(obs_off=0, ws_off=0, g_off=0):
+        b = binding.EjPpoBatch(P(dev["obs"], obs_off), *(P(dev[k]) for k in ("mask", "act", "logp_old", "val_old",
+                                                                              "adv", "ret")), M, a, c, 0, M)
+        return L.ej_ppo_backward(C.byref(mlp.desc), P(mlp.params), P(mlp.work), C.byref(b), C.byref(h),
+                                 P(ws, ws_off), nbytes, P(grads, g_off), P(loss), None)
+
+    assert call(g_off=4) == -1
+    assert call(ws_off=8) == -1
+    assert call(obs_off=8) == -1
+    torch.cuda.synchronize()
+    assert (grads.cpu() == 7.0).all()
