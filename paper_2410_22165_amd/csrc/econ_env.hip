@@ -434,6 +434,14 @@ __host__ __device__ __forceinline__ size_t lds_layout(const EnvParams& P, int NL
     return total;
 }
 
+// age of the order in slot s (0 <= s < X) when t mod X = tX: (tX - s) mod X,
+// from tX - s + X in [1, 2X) without a division
+__device__ inline int slot_age(int tX, int s, int X)
+{
+    const int a = tX - s + X;
+    return a >= X ? a - X : a;
+}
+
 // bucket position in matching-priority order within the (r, side) segment
 __device__ inline int bucket_pos(const EnvParams& P, int side, int p, int age)
 {
@@ -507,9 +515,10 @@ __device__ inline void market_stats(const EnvParams& P, const Lds& L, const int3
             count[u] = 0;
             k[u] = (sg < nseg && kr) ? kr[sg >> 1] : 0;
         }
+        const uint64_t mgX = 0xFFFFFFFFull / (uint64_t)P.X + 1ull;  // j / X = (j mgX) >> 32 for j < 2^27
         for (int c = 0; c < PX; c += 64) {
             const int pos = c + lane;
-            const int age = P.X - 1 - (pos % P.X);
+            const int age = P.X - 1 - (pos - (int)(((uint64_t)(uint32_t)pos * mgX) >> 32) * P.X);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int sg = s0 + u * nw;
@@ -888,7 +897,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             uint32_t sl = ag[k].slot[s];
             if (s < X && slot_valid(sl)) {
                 int side = slot_side(sl), r = slot_r(sl), p = slot_p(sl);
-                int age = (tX - s + X) % X;
+                const int age = slot_age(tX, s, X);
                 int b = (r * 2 + side) * PX + bucket_pos(P, side, p, age);
                 atomicAdd(&L.hcnt[b], 1);
                 atomicMin(&L.hmin[b], slot_rank(sl));
@@ -957,6 +966,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     }
 
     // settlement: every agent settles its own filled orders
+    const uint64_t mgX = 0xFFFFFFFFull / (uint64_t)X + 1ull;  // j / X = (j mgX) >> 32 for j < 2^27 (2^32 at X = 1)
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
         const int li = tid + k * NT;
@@ -967,7 +977,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             uint32_t sl = a.slot[s];
             if (!(s < X && slot_valid(sl))) continue;
             const int side = slot_side(sl), r = slot_r(sl), p = slot_p(sl);
-            const int age = (tX - s + X) % X;
+            const int age = slot_age(tX, s, X);
             const int b = (r * 2 + side) * PX + bucket_pos(P, side, p, age);
             const int g = L.hexc[b] + (slot_rank(sl) - L.hmin[b]);
             if (g >= L.kr[r]) continue;
@@ -985,8 +995,8 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
                 }
                 opos = lo;
             }
-            const int oage = X - 1 - (opos % X);
-            const int opl = opos / X;
+            const int opl = (int)(((uint64_t)(uint32_t)opos * mgX) >> 32);  // opos / X
+            const int oage = X - 1 - (opos - opl * X);
             const int op = side == 0 ? opl : P.P - 1 - opl;
             const int my_price = L.prices[p], other_price = L.prices[op];
             int q;
@@ -1259,7 +1269,7 @@ env_observe_kernel(const EnvParams P, const EnvState S, uint16_t* __restrict__ o
             uint32_t sl = ag[k].slot[s];
             if (s < X && slot_valid(sl)) {
                 int side = slot_side(sl), r = slot_r(sl), p = slot_p(sl);
-                int age = (tX - s + X) % X;
+                const int age = slot_age(tX, s, X);
                 atomicAdd(&L.hcnt[(r * 2 + side) * PX + bucket_pos(P, side, p, age)], 1);
             }
         }
