@@ -41,6 +41,7 @@ struct EnvParams {
     double eta, omega;
     uint64_t seed;
     uint64_t gov_seed;  // government levels drawn in the step when gov_draw != 0 and no levels are passed
+    uint64_t div_X, div_P;  // reciprocal multipliers 2^32 / X, 2^32 / P rounded up: j / X = (j div_X) >> 32 for j < 2^27
     int32_t gov_draw;
     int64_t Ntot;  // stride between two state fields
     int32_t prices[EJ_MAX_P];
@@ -265,7 +266,7 @@ __device__ inline Act decode_action(const EnvParams& P, int a)
         d.type = 4;
         b -= RP;
     }
-    d.r = b / P.P;
+    d.r = (int)(((uint64_t)(uint32_t)b * P.div_P) >> 32);  // b / P (b < 2 R P)
     d.p = b - d.r * P.P;
     return d;
 }
@@ -515,7 +516,7 @@ __device__ inline void market_stats(const EnvParams& P, const Lds& L, const int3
             count[u] = 0;
             k[u] = (sg < nseg && kr) ? kr[sg >> 1] : 0;
         }
-        const uint64_t mgX = 0xFFFFFFFFull / (uint64_t)P.X + 1ull;  // j / X = (j mgX) >> 32 for j < 2^27
+        const uint64_t mgX = P.div_X;
         for (int c = 0; c < PX; c += 64) {
             const int pos = c + lane;
             const int age = P.X - 1 - (pos - (int)(((uint64_t)(uint32_t)pos * mgX) >> 32) * P.X);
@@ -966,7 +967,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     }
 
     // settlement: every agent settles its own filled orders
-    const uint64_t mgX = 0xFFFFFFFFull / (uint64_t)X + 1ull;  // j / X = (j mgX) >> 32 for j < 2^27 (2^32 at X = 1)
+    const uint64_t mgX = P.div_X;
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
         const int li = tid + k * NT;
@@ -1475,6 +1476,9 @@ int ej_env_create(const ej_env_config* cfg, const int32_t* h_n_per_env, ej_env**
     EnvParams& P = h->P;
     std::memset(&P, 0, sizeof(P));
     P.N = cfg->N; P.R = cfg->R; P.P = cfg->P; P.X = cfg->X; P.max_orders = cfg->max_orders;
+    // exact for every numerator below 2^27 (the error of the rounded-up multiplier stays below 1 / divisor)
+    P.div_X = cfg->X > 0 ? 0xFFFFFFFFull / (uint64_t)cfg->X + 1ull : 0;
+    P.div_P = cfg->P > 0 ? 0xFFFFFFFFull / (uint64_t)cfg->P + 1ull : 0;
     P.P_tax = cfg->P_tax; P.K = cfg->K; P.T = cfg->T; P.R_kappa = cfg->R_kappa; P.R_d = cfg->R_d;
     P.kappa_c = cfg->kappa_c; P.start_coin = cfg->start_coin; P.labor_gather = cfg->labor_gather;
     P.labor_craft = cfg->labor_craft; P.labor_trade = cfg->labor_trade; P.allow_noop = cfg->allow_noop;
