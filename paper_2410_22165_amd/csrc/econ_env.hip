@@ -688,6 +688,7 @@ __device__ inline void write_mask_row(const EnvParams& P, const Lds& L, const Ag
     const bool craft = craft_possible(P, ag);
     const int base_buy = P.R + 2, base_sell = P.R + 2 + P.R * P.P;
     for (int wd = 0; wd < P.W; ++wd) {
+        const int w0 = 32 * wd, w1 = w0 + 32;
         uint32_t bits = 0;
         if (P.allow_noop) bits |= range_bits(wd, 0, 1);
         bits |= range_bits(wd, 1, P.R + 1);
@@ -695,9 +696,11 @@ __device__ inline void write_mask_row(const EnvParams& P, const Lds& L, const Ag
 #pragma unroll
         for (int r = 0; r < RM; ++r) {
             if (r < P.R) {
-                bits |= range_bits(wd, base_buy + r * P.P, base_buy + r * P.P + n_afford);
-                if (can_order && ag.res_inv[r] >= 1)
-                    bits |= range_bits(wd, base_sell + r * P.P, base_sell + (r + 1) * P.P);
+                // a resource's buy and sell ranges meet at most two words: the
+                // (uniform) range tests skip the others
+                const int bb = base_buy + r * P.P, sb = base_sell + r * P.P;
+                if (bb < w1 && bb + P.P > w0) bits |= range_bits(wd, bb, bb + n_afford);
+                if (sb < w1 && sb + P.P > w0 && can_order && ag.res_inv[r] >= 1) bits |= range_bits(wd, sb, sb + P.P);
             }
         }
         row[wd] = bits;
