@@ -14,12 +14,12 @@
  *   - Arrays named d_* are DEVICE pointers owned by the caller; the library
  *     never frees them and never keeps them beyond the call.  Arrays named h_*
  *     are host pointers.  State and scratch owned by a handle live inside it
- *     and are freed by the matching destroy call.  The policy and learner
- *     calls read parameters, weights and observations with 16-byte vector
- *     loads: d_params, d_work, d_obs (ej_ppo_batch.obs), d_grads and
- *     d_workspace must be 16-byte aligned (hipMalloc and torch allocations
- *     are; so is every observation row, D_stride being a multiple of 8), and
- *     a misaligned one returns EJ_EINVAL.
+ *     and are freed by the matching destroy call.  Parameters, weights and
+ *     observations move in 16-byte vector loads and stores: d_params, d_work,
+ *     d_obs (of the economy step, the policy and ej_ppo_batch.obs), d_grads
+ *     and d_workspace must be 16-byte aligned (hipMalloc and torch
+ *     allocations are; so is every observation row, D_stride being a
+ *     multiple of 8), and a misaligned one returns EJ_EINVAL.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Work is enqueued asynchronously on it; only calls documented as
  *     synchronous (get/set state, status) wait for it.

@@ -319,6 +319,50 @@ template <int U>
 __device__ inline void seg_exclusive_scan(const int32_t* src, int32_t* dst, int nseg, int len)
 {
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = lane_id();
+    if (len <= 256) {
+        // four consecutive entries per lane (one 16-byte word when len is a
+        // multiple of 4): a local prefix, then one wave scan of the lane
+        // totals per segment
+        const bool vec = (len & 3) == 0;
+        for (int s0 = w; s0 < nseg; s0 += U * nw) {
+            int32_t v[U][4], tot[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int sg = s0 + u * nw;
+                const bool seg = sg < nseg;
+                if (vec) {
+                    const int4 x = (seg && 4 * lane < len) ? *(const int4*)(src + sg * len + 4 * lane) : int4{0, 0, 0, 0};
+                    v[u][0] = x.x;
+                    v[u][1] = x.y;
+                    v[u][2] = x.z;
+                    v[u][3] = x.w;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int j = 4 * lane + i;
+                        v[u][i] = (seg && j < len) ? src[sg * len + j] : 0;
+                    }
+                }
+                tot[u] = v[u][0] + v[u][1] + v[u][2] + v[u][3];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int sg = s0 + u * nw;
+                const int32_t e0 = wave_scan_i(tot[u]) - tot[u];  // entries before this lane's four
+                const int32_t e1 = e0 + v[u][0], e2 = e1 + v[u][1], e3 = e2 + v[u][2];
+                if (sg >= nseg) continue;
+                if (vec) {
+                    if (4 * lane < len) *(int4*)(dst + sg * len + 4 * lane) = int4{e0, e1, e2, e3};
+                } else {
+                    const int32_t e[4] = {e0, e1, e2, e3};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (4 * lane + i < len) dst[sg * len + 4 * lane + i] = e[i];
+                }
+            }
+        }
+        return;
+    }
     for (int s0 = w; s0 < nseg; s0 += U * nw) {
         int32_t carry[U];
 #pragma unroll
@@ -1173,11 +1217,18 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     if (!staged) return;
     lds_barrier();
     if (obs) {
-        uint32_t* dst = (uint32_t*)(obs + row0 * (int64_t)P.Ds);
-        const uint32_t mg = 0xFFFFFFFFu / (uint32_t)dw + 1u;  // j / dw = umulhi(j, mg) for j < 2^16
-        for (int j = tid; j < n * dw; j += NT) {
-            const int row = (int)__umulhi((uint32_t)j, mg), c = j - row * dw;
-            dst[j] = c < c_own ? so[row * os + c] : L.tmpl[c];
+        // A row is dw = Ds / 2 words, a multiple of 4 (Ds is a multiple of 8),
+        // and the economy's rows are contiguous: its block leaves in 16-byte
+        // pieces, none of which straddles two rows.
+        uint4* dst = (uint4*)(obs + row0 * (int64_t)P.Ds);
+        const int q4 = dw >> 2;                                 // pieces per row
+        const uint64_t mg = 0xFFFFFFFFull / (uint64_t)q4 + 1ull;  // j / q4 = (j mg) >> 32 for j < 2^27
+        for (int j = tid; j < n * q4; j += NT) {
+            const int row = (int)(((uint64_t)(uint32_t)j * mg) >> 32), c0 = 4 * (j - row * q4);
+            uint32_t v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = c0 + i < c_own ? so[row * os + c0 + i] : L.tmpl[c0 + i];
+            dst[j] = uint4{v[0], v[1], v[2], v[3]};
         }
     }
     if (mask) {
@@ -1626,6 +1677,7 @@ int ej_env_step_range(ej_env* h, int32_t e_begin, int32_t e_end, const int32_t* 
 {
     if (!h || !d_act || !d_rew || !d_gov_rew || !d_done) return EJ_EINVAL;
     if (e_begin < 0 || e_end > h->E || e_begin > e_end) return EJ_EINVAL;
+    if (d_obs && !aligned16(d_obs)) return EJ_EINVAL;  // observation blocks leave in 16-byte stores
     if (e_begin == e_end) return EJ_OK;
     const bool whole = e_begin == 0 && e_end == h->E;
     if (h->P.K > 0 && !d_gov && !h->P.gov_draw) return EJ_EINVAL;

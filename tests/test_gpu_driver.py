@@ -186,3 +186,23 @@ def test_env_step_range_rejects_bad_ranges():
     env.step(bu["act"], None, bu["rew"], bu["gov_rew"], bu["done"], bu["obs"], bu["mask"], economies=(2, 2))
     torch.cuda.synchronize()
     env.close()
+
+
+def test_env_step_rejects_misaligned_observations():
+    """Observation blocks leave in 16-byte stores: an observation buffer that
+    is not 16-byte aligned returns EJ_EINVAL and the state does not advance."""
+    import torch
+    from paper_2410_22165_amd import binding
+    cfg = W.env_config(E=4, N=10, R=2, P=5, X=4, P_tax=5, K=3, T=20, seed=1)
+    env = binding.Env(cfg, W.obs_scales(cfg))
+    env.set_gov_draw(True, 1)
+    bu = env.buffers()
+    flat = torch.zeros(bu["obs"].numel() + 8, dtype=bu["obs"].dtype, device="cuda")
+    shifted = flat[4:4 + bu["obs"].numel()].view(bu["obs"].shape)  # 8 bytes past an aligned start
+    before = env.env_state(env.get_state(), 0)
+    with pytest.raises(binding.EconError):
+        env.step(bu["act"], None, bu["rew"], bu["gov_rew"], bu["done"], shifted, bu["mask"])
+    torch.cuda.synchronize()
+    after = env.env_state(env.get_state(), 0)
+    assert before["t"] == after["t"]
+    env.close()
