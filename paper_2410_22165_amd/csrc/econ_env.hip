@@ -863,8 +863,12 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         L.ncode[li] = -1;
         Act d = decode_action(P, eff[k]);
         Agent<RM, XM>& a = ag[k];
+        // one draw serves both the gathering luck and the order tie key (the
+        // same counter), taken once before the two branches split the wave
+        u64x4 w{0, 0, 0, 0};
+        if (d.type == 1 || d.type >= 3)
+            w = philox(P.seed, PURPOSE_ENV, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)li);
         if (d.type == 1) {  // gather: floor(SG + rho), rho ~ U[0, 1.1)
-            u64x4 w = philox(P.seed, PURPOSE_ENV, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)li);
             int64_t rho_q = (int64_t)(((w.x >> 32) * 72090ull) >> 32);
             int64_t amount = ((int64_t)rget(a.sg, d.r) + rho_q) >> 16;
             radd(a.res_inv, d.r, (int32_t)amount);
@@ -886,7 +890,6 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             a.coin_inv += (int32_t)(((int64_t)a.sc * P.kappa_c) >> 16);
             a.labor += P.labor_craft;
         } else if (d.type >= 3) {  // order with escrow
-            u64x4 w = philox(P.seed, PURPOSE_ENV, (uint64_t)e, (uint64_t)ep, (uint64_t)t, (uint64_t)li);
             const int side = d.type == 4;
             if (side == 0) {
                 a.coin_inv -= L.prices[d.p];
