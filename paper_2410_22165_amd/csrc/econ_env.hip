@@ -311,6 +311,28 @@ __device__ inline int64_t block_sum_i64(int64_t v, int64_t* red)
     return tot;
 }
 
+// three block-wide sums at the cost of one (two barriers); red holds 48 entries
+__device__ inline void block_sum3_i64(int64_t& a, int64_t& b, int64_t& c, int64_t* red)
+{
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    lds_barrier();
+    if (lane_id() == 0) {
+        red[w] = a;
+        red[16 + w] = b;
+        red[32 + w] = c;
+    }
+    lds_barrier();
+    a = b = c = 0;
+    for (int j = 0; j < nw; ++j) {
+        a += red[j];
+        b += red[16 + j];
+        c += red[32 + j];
+    }
+}
+
 // exclusive scans of `nseg` segments of `len` ints (src -> dst); waves take
 // segments round-robin; the caller synchronises before and after.
 // A wave takes U of its segments at once so that their load and scan
@@ -454,7 +476,7 @@ __host__ __device__ __forceinline__ size_t lds_layout(const EnvParams& P, int NL
     const size_t o_misc = align16(o_mstat + 16 * EJ_MAX_R);
     const size_t o_tmpl = align16(o_misc + 4 * 16);
     const size_t o_red = align16(o_tmpl + 2 * EJ_MAX_DS);
-    const size_t o_dred = align16(o_red + 8 * 32);
+    const size_t o_dred = align16(o_red + 8 * 48);
     const size_t total = align16(o_dred + 8 * 4);
     if (base) {
         L->hcnt = (int32_t*)(base + o_hcnt);
@@ -502,7 +524,10 @@ __device__ inline int bucket_pos(const EnvParams& P, int side, int p, int age)
 // welfare ranks by counting (n <= 256), the plain value for the sort
 __device__ inline int64_t welfare_key(int64_t C, int li, int n) { return n <= 256 ? C * 256 + li : C; }
 
-__device__ inline double social_welfare_block(const EnvParams& P, const Lds& L, int n, int S2)
+// `extra` (nullable): one more per-thread count, summed over the block in the
+// same reduction
+__device__ inline double social_welfare_block(const EnvParams& P, const Lds& L, int n, int S2,
+                                              int64_t* extra = nullptr)
 {
     int64_t num = 0, sum = 0;
     if (n <= 256) {
@@ -535,8 +560,9 @@ __device__ inline double social_welfare_block(const EnvParams& P, const Lds& L, 
             sum += x;
         }
     }
-    num = block_sum_i64(num, L.red);
-    sum = block_sum_i64(sum, L.red + 16);
+    int64_t x = extra ? *extra : 0;
+    block_sum3_i64(num, sum, x, L.red);
+    if (extra) *extra = x;
     double gini = 0.0;
     if (sum > 0) gini = (double)num / ((double)n * (double)sum);
     double eq = (1.0 - P.omega) + P.omega * (1.0 - gini);
@@ -1141,8 +1167,8 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         L.sortbuf[li] = welfare_key(C, li, n);
     }
     lds_barrier();
-    const double ug1 = social_welfare_block(P, L, n, S2);
-    const int64_t n_invalid = block_sum_i64(invalid, L.red);
+    int64_t n_invalid = invalid;  // summed over the block with the welfare
+    const double ug1 = social_welfare_block(P, L, n, S2, &n_invalid);
     if (tid == 0) {
         gov_rew[e] = (float)(ug1 - ug0);
         int bad_gov = 0;
