@@ -208,3 +208,61 @@ def test_misaligned_parameters_are_rejected():
     assert rc == -1
     torch.cuda.synchronize()
     assert all((t.cpu() == 7).all() for t in o)
+
+
+def test_sparse_masks_single_actions_and_empty_chunks():
+    """Masks that leave a single action (at either end of the action space or
+    at a 128-action chunk edge), or that empty whole chunks: a single allowed
+    action is always drawn with log-probability 0 and entropy 0; otherwise the
+    draw, its log-probability and the entropy agree with the oracle."""
+    import torch
+    from paper_2410_22165_amd import binding
+    D, Ds, H, A, M = 35, 40, 256, 300, 384  # three chunks, the last one partial
+    w = W.policy_weights(D, H, A, seed=9)
+    mlp = binding.Mlp(D, Ds, H, A, w)
+    obs = W.synthetic_obs(M, D, Ds, seed=9)
+    rng = np.random.default_rng(9)
+    allowed = np.zeros((M, A), bool)
+    singles = [0, A - 1, 127, 128, 255, 256]
+    for i in range(M):
+        kind = i % 4
+        if kind == 0:  # exactly one action
+            allowed[i, singles[(i // 4) % len(singles)]] = True
+        elif kind == 1:  # only the first chunk
+            allowed[i, :128] = rng.random(128) < 0.3
+            allowed[i, rng.integers(0, 128)] = True
+        elif kind == 2:  # only the last (partial) chunk
+            allowed[i, 256:] = rng.random(A - 256) < 0.5
+            allowed[i, rng.integers(256, A)] = True
+        else:  # the middle chunk, every action
+            allowed[i, 128:256] = True
+    Wd = (A + 31) // 32
+    mask = np.zeros((M, Wd), np.uint32)
+    for a in range(A):
+        mask[:, a // 32] |= allowed[:, a].astype(np.uint32) << np.uint32(a % 32)
+    dev = "cuda"
+    out = dict(act=torch.zeros(M, dtype=torch.int32, device=dev), logp=torch.zeros(M, device=dev),
+               val=torch.zeros(M, device=dev), ent=torch.zeros(M, device=dev))
+    mlp.forward(torch.from_numpy(obs.view(np.int16)).to(dev), torch.from_numpy(mask.view(np.int32)).to(dev), M,
+                77, 3, out["act"], out["logp"], out["val"], out["ent"])
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    assert allowed[np.arange(M), g["act"]].all()
+    one = allowed.sum(axis=1) == 1
+    assert np.array_equal(g["act"][one], np.argmax(allowed[one], axis=1))
+    assert np.abs(g["logp"][one]).max() <= 1e-6 and np.abs(g["ent"][one]).max() <= 1e-6
+    x = oe.bf16_bits_to_f32(obs[:, :D]).astype(np.float64)
+    wb = op.bf16_weights(w)
+    logits, _ = op.mlp(x, wb)
+    lp = op.masked_log_softmax(logits, allowed)
+    assert np.abs(g["ent"] - op.entropy(lp)).max() <= 2e-2
+    assert np.abs(g["logp"] - lp[np.arange(M), g["act"]]).max() <= 2e-2
+    l16, _ = op.mlp(x, wb, bf16_hidden=True)
+    lp16 = op.masked_log_softmax(l16, allowed)
+    NC = (A + 1 + 127) // 128
+    u1, u2 = oe.sample_uniforms(77, np.arange(M), 3, NC)
+    lp16p = np.concatenate([lp16, np.full((M, NC * 128 - A), -np.inf)], axis=1)
+    a_o, margin = op.sample_chunked(lp16p, u1, u2)
+    safe = margin > 1e-4
+    assert safe.mean() > 0.9
+    assert np.array_equal(g["act"][safe], a_o[safe]), np.flatnonzero(g["act"][safe] != a_o[safe])[:10]
