@@ -828,12 +828,20 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     // first step (kept in a register until after the first barrier, so that
     // the barrier does not wait for the loads)
     int rate = 0;
+    bool bad_level = false;  // a passed level outside 0..20 (counted, the previous rate kept)
     if (tid < K) {
         rate = S.env_rates[e * K + tid];
         if (t % P.P_tax == 0) {
             const int g = gov ? gov[e * K + tid] : gov_level_draw(P.gov_seed, e, ep, t, tid);
             if (g >= 0 && g < EJ_GOV_LEVELS) rate = g;
+            else bad_level = gov != nullptr;
         }
+    }
+    // the economy's rejection counters, updated by thread 0 at the end
+    int64_t inv_act = 0, inv_gov = 0;
+    if (tid == 0) {
+        inv_act = S.invalid[2 * e];
+        inv_gov = S.invalid[2 * e + 1];
     }
     // price grid and bracket cutoffs: read now, stored after the barrier
     // (NT >= 64 and P <= 128: at most two prices per thread)
@@ -853,6 +861,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     int invalid = 0;
 
     if (tid < K) L.rates[tid] = rate;
+    const int bad_gov = __popcll(__ballot(bad_level));  // thread 0's wave holds every bracket (K <= 16)
     if (tid < P.P) L.prices[tid] = pr0;
     if (tid + NT < P.P) L.prices[tid + NT] = pr1;
     if (tid < K - 1) L.cutoffs[tid] = cut;
@@ -1171,14 +1180,8 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     const double ug1 = social_welfare_block(P, L, n, S2, &n_invalid);
     if (tid == 0) {
         gov_rew[e] = (float)(ug1 - ug0);
-        int bad_gov = 0;
-        if (gov && t % P.P_tax == 0)
-            for (int b = 0; b < K; ++b) {
-                int g = gov[e * K + b];
-                bad_gov += (g < 0 || g >= EJ_GOV_LEVELS);
-            }
-        S.invalid[2 * e] += n_invalid;
-        S.invalid[2 * e + 1] += bad_gov;
+        S.invalid[2 * e] = inv_act + n_invalid;
+        S.invalid[2 * e + 1] = inv_gov + bad_gov;
     }
 
     // time advance; automatic reset at the episode end
