@@ -163,8 +163,11 @@ __device__ inline void load_agent(const EnvParams& P, const EnvState& S, int64_t
     for (int s = 0; s < XM; ++s) ag.slot[s] = s < P.X ? (uint32_t)f[F_SLOT(P.R, s) * st + g] : 0u;
 }
 
+// skills: also store the craft and gather skills (they change only when an
+// episode starts)
 template <int RM, int XM>
-__device__ inline void store_agent(const EnvParams& P, const EnvState& S, int64_t g, const Agent<RM, XM>& ag)
+__device__ inline void store_agent(const EnvParams& P, const EnvState& S, int64_t g, const Agent<RM, XM>& ag,
+                                   bool skills)
 {
     int32_t* f = S.field;
     const int64_t st = P.Ntot;
@@ -172,13 +175,13 @@ __device__ inline void store_agent(const EnvParams& P, const EnvState& S, int64_
     f[F_COIN_ESC() * st + g] = ag.coin_esc;
     f[F_LABOR() * st + g] = ag.labor;
     f[F_SNAP() * st + g] = ag.snap;
-    f[F_SC() * st + g] = ag.sc;
+    if (skills) f[F_SC() * st + g] = ag.sc;
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
         if (r < P.R) {
             f[F_RES_INV(P.R, r) * st + g] = ag.res_inv[r];
             f[F_RES_ESC(P.R, r) * st + g] = ag.res_esc[r];
-            f[F_SG(P.R, r) * st + g] = ag.sg[r];
+            if (skills) f[F_SG(P.R, r) * st + g] = ag.sg[r];
         }
     }
 #pragma unroll
@@ -1201,7 +1204,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     for (int k = 0; k < APT; ++k) {
         const int li = tid + k * NT;
         if (li >= n) continue;
-        store_agent(P, S, off + li, ag[k]);
+        store_agent(P, S, off + li, ag[k], done);  // skills are redrawn only at a reset
         done_out[row0 + li] = done ? 1 : 0;
     }
     if (tid == 0) {
@@ -1423,7 +1426,7 @@ __global__ void __launch_bounds__(1024 / APT) env_reset_kernel(const EnvParams P
         if (li >= n) continue;
         Agent<RM, XM> ag;
         reset_agent(P, e, ep, li, ag);
-        store_agent(P, S, off + li, ag);
+        store_agent(P, S, off + li, ag, true);
         S.u[off + li] = __builtin_nan("");
     }
     if (threadIdx.x == 0) {
