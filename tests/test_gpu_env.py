@@ -239,6 +239,11 @@ def test_determinism_and_checkpoint_resume():
     end3 = e3.get_state()
     for k in end1:
         assert np.array_equal(end1[k], end3[k]), k
+    # the same handle rewound: values the step caches from the state it last
+    # wrote (welfare, utilities) must not survive set_state
+    e1.set_state(mid)
+    r_rewound = run(e1, b1, 130)
+    assert np.array_equal(r_rewound, r_second)
     for e in (e1, e2, e3):
         e.close()
 
