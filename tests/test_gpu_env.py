@@ -260,3 +260,34 @@ def test_create_rejects_bad_configs():
             cfg["prices"] = W.default_prices(cfg["P"])
         with pytest.raises(binding.EconError):
             binding.Env(cfg, W.obs_scales(cfg))
+
+
+def test_reset_after_steps_equals_fresh_handle():
+    """ej_env_reset on a handle that has stepped: the following steps equal
+    those of a fresh handle bit for bit (no cached welfare or utility of the
+    old state survives the reset)."""
+    torch = _torch()
+    cfg = W.env_config(E=16, N=100, R=3, P=20, X=10, P_tax=100, K=7, T=1000)
+
+    def run(env, b, steps):
+        out = []
+        for _ in range(steps):
+            env.random_actions(9, b["act"], b["gov"])
+            env.step(b["act"], b["gov"], b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
+            out.append(torch.cat([b["rew"], b["gov_rew"]]).clone())
+        return torch.stack(out).cpu().numpy()
+
+    e1 = make_env(cfg)
+    b1 = e1.buffers()
+    run(e1, b1, 60)
+    e1.reset(0)
+    r1 = run(e1, b1, 40)
+    e2 = make_env(cfg)
+    b2 = e2.buffers()
+    r2 = run(e2, b2, 40)
+    assert np.array_equal(r1, r2)
+    s1, s2 = e1.get_state(), e2.get_state()
+    for k in s1:
+        assert np.array_equal(s1[k], s2[k]), k
+    for e in (e1, e2):
+        e.close()
