@@ -307,8 +307,8 @@ int ej_ppo_workspace_size(const ej_mlp_desc* m, int64_t rows, int64_t* bytes);
  * minibatch (population std + 1e-8), H the entropy of the masked policy.
  * The forward pass is recomputed from the stored observations (activations
  * of the rollout are never stored).  d_grads [n_params] is overwritten (not
- * accumulated); d_loss [4] receives mean surrogate, value, entropy terms and
- * the clipped fraction.  d_workspace: caller-owned device scratch of at
+ * accumulated); d_loss [5] receives the mean surrogate, value and entropy
+ * terms, the clipped fraction, and the minibatch loss L itself.  d_workspace: caller-owned device scratch of at
  * least ej_ppo_workspace_size bytes.  Deterministic: the weight gradients
  * are reduced over a fixed split in a fixed order. */
 int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const ej_ppo_batch* b,

@@ -188,7 +188,7 @@ def _round_bf16_straight_through(h):
 
 
 def ppo_loss_torch(params: dict, obs, allowed, act, logp_old, val_old, adv, ret, hp: dict,
-                   bf16_hidden: bool = False):
+                   bf16_hidden: bool = False, capture: dict | None = None):
     """PPO minibatch loss in float64 torch ops; returns (loss, terms).
 
     Advantages are normalised over the minibatch (population standard
@@ -197,15 +197,22 @@ def ppo_loss_torch(params: dict, obs, allowed, act, logp_old, val_old, adv, ret,
                               - c_e mean(H).
     bf16_hidden rounds the hidden activations to bf16 in the forward pass
     (straight-through in the backward pass): the clip decisions are then
-    taken in the precision of a bf16 kernel."""
+    taken in the precision of a bf16 kernel.  `capture`, when given,
+    receives the intermediate tensors (pre-activations z1, z2, activations
+    h1, h2, outputs out, ratio, V) for a test's tolerance bookkeeping; out
+    keeps its gradient after backward()."""
     x = torch.as_tensor(np.asarray(obs, np.float64))
-    h1 = torch.relu(x @ params["W1"] + params["b1"])
+    z1 = x @ params["W1"] + params["b1"]
+    h1 = torch.relu(z1)
     if bf16_hidden:
         h1 = _round_bf16_straight_through(h1)
-    h2 = torch.relu(h1 @ params["W2"] + params["b2"])
+    z2 = h1 @ params["W2"] + params["b2"]
+    h2 = torch.relu(z2)
     if bf16_hidden:
         h2 = _round_bf16_straight_through(h2)
     out = h2 @ params["W3"] + params["b3"]
+    if capture is not None and out.requires_grad:
+        out.retain_grad()
     logits, v = out[:, :-1], out[:, -1]
     allowed_t = torch.as_tensor(allowed)
     z = logits.masked_fill(~allowed_t, float("-inf"))
@@ -225,17 +232,19 @@ def ppo_loss_torch(params: dict, obs, allowed, act, logp_old, val_old, adv, ret,
     vl = 0.5 * torch.maximum((v - R) ** 2, (v_clip - R) ** 2).mean()
     en = ent.mean()
     loss = pg + hp["vf_coef"] * vl - hp["ent_coef"] * en
+    if capture is not None:
+        capture.update(z1=z1, z2=z2, h1=h1, h2=h2, out=out, ratio=ratio, V=v)
     return loss, dict(pg=pg, vf=vl, ent=en)
 
 
 def ppo_grads(w_f32: dict, obs, mask_words, act, logp_old, val_old, adv, ret, hp: dict,
-              bf16_hidden: bool = False):
+              bf16_hidden: bool = False, capture: dict | None = None):
     """Float64 loss and autograd gradients with respect to the bf16 weights."""
     w = bf16_weights(w_f32)
     A = w["W3"].shape[1] - 1
     params = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in w.items()}
     loss, terms = ppo_loss_torch(params, obs, unpack_mask(mask_words, A), act, logp_old, val_old, adv,
-                                 ret, hp, bf16_hidden=bf16_hidden)
+                                 ret, hp, bf16_hidden=bf16_hidden, capture=capture)
     loss.backward()
     return (float(loss.detach()), {k: float(v.detach()) for k, v in terms.items()},
             {k: params[k].grad.numpy().copy() for k in params})

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libecon_mi355x.so")
 
 EJ_MAX_P, EJ_MAX_K = 128, 16
+PPO_LOSS_TERMS = 5  # surrogate, value, entropy, clipped fraction, loss
 
 
 class EjObsScales(C.Structure):
@@ -347,7 +348,10 @@ def ppo_workspace_bytes(mlp: "Mlp", rows: int) -> int:
 
 def ppo_backward(mlp: "Mlp", storage: dict, M_total: int, perm_a: int, perm_c: int, row_begin: int, rows: int,
                  hp: dict, workspace, grads, loss, stream=None):
-    """storage: torch tensors obs, mask, act, logp_old, val_old, adv, ret indexed by sample."""
+    """storage: torch tensors obs, mask, act, logp_old, val_old, adv, ret indexed by sample;
+    loss: at least PPO_LOSS_TERMS floats."""
+    if loss.numel() < PPO_LOSS_TERMS:
+        raise EconError(f"ej_ppo_backward writes {PPO_LOSS_TERMS} loss terms; got {loss.numel()}")
     b = EjPpoBatch(*(ptr(storage[k]) for k in ("obs", "mask", "act", "logp_old", "val_old", "adv", "ret")),
                    M_total, perm_a, perm_c, row_begin, rows)
     h = EjPpoHparams(hp["clip"], hp["vclip"], hp["vf_coef"], hp["ent_coef"])

@@ -621,14 +621,22 @@ __global__ void __launch_bounds__(256) loss_slices_kernel(const float* __restric
     }
 }
 
+// out[0..3] = means of the surrogate, value and entropy terms and the clipped
+// fraction; out[4] = surrogate + c_v value - c_e entropy (the minibatch loss)
 __global__ void __launch_bounds__(256) loss_final_kernel(const double* __restrict__ slice_sums, int nslices,
-                                                         int64_t rows, float* __restrict__ out)
+                                                         int64_t rows, float vf_coef, float ent_coef,
+                                                         float* __restrict__ out)
 {
     double t[4];
     block_sum_records<4>(slice_sums, nslices, t);
     if (threadIdx.x == 0) {
+        double m[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) out[c] = (float)(t[c] / (double)rows);
+        for (int c = 0; c < 4; ++c) {
+            m[c] = t[c] / (double)rows;
+            out[c] = (float)m[c];
+        }
+        out[4] = (float)(m[0] + (double)vf_coef * m[1] - (double)ent_coef * m[2]);
     }
 }
 
@@ -817,7 +825,7 @@ int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t*
     double* lslices = (double*)(ws + w.o_lslices);
     loss_slices_kernel<<<nslices, 256, 0, st>>>(lparts, (int)w.ntiles, nslices, lslices);
     EJ_LAUNCH_CHECK();
-    loss_final_kernel<<<1, 256, 0, st>>>(lslices, nslices, b->rows, d_loss);
+    loss_final_kernel<<<1, 256, 0, st>>>(lslices, nslices, b->rows, hp->vf_coef, hp->ent_coef, d_loss);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }

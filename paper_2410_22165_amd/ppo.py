@@ -66,11 +66,11 @@ class PPOLoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, params, mlp, storage, M_total, perm_a, perm_c, row_begin, rows, hp, workspace):
         grads = torch.empty_like(params)
-        terms = torch.empty(4, device=params.device)
+        terms = torch.empty(binding.PPO_LOSS_TERMS, device=params.device)
         binding.ppo_backward(mlp, storage, M_total, perm_a, perm_c, row_begin, rows, hp, workspace, grads, terms)
         ctx.save_for_backward(grads)
         ctx.terms = terms
-        return terms[0] + hp["vf_coef"] * terms[1] - hp["ent_coef"] * terms[2]
+        return terms[4]  # the kernel's minibatch loss
 
     @staticmethod
     def backward(ctx, grad_out):
@@ -127,7 +127,7 @@ class PPOTrainer:
         self.grads = torch.zeros(n, device="cuda")
         self.adam_m = torch.zeros(n, device="cuda")
         self.adam_v = torch.zeros(n, device="cuda")
-        self.loss_terms = torch.zeros(4, device="cuda")
+        self.loss_terms = torch.zeros(binding.PPO_LOSS_TERMS, device="cuda")
         self.M_total = rollout * self.M
         self.mb_rows = self.M_total // minibatches
         self.workspace = torch.zeros(binding.ppo_workspace_bytes(self.mlp, self.mb_rows), dtype=torch.uint8,

@@ -37,6 +37,57 @@ def test_rollout_storage_is_consistent():
     tr.close()
 
 
+def test_rollout_store_replays_through_the_oracle():
+    """The stored rollout of two economies replayed by the oracle: the stored
+    actions and the step's own government draw (seed + 1) drive the oracle
+    economy through 48 steps (an episode end at 40 included).  Rewards within
+    1e-5 relative, done flags and every stored observation and mask exactly;
+    the stored log-probabilities, values and entropies of the policy within
+    2e-2 of the oracle network on the stored observations; GAE of the stored
+    rewards and values within 1e-4."""
+    import torch
+    from oracle import env as oe
+    from oracle import policy as op
+    tr = small_trainer(rollout=48)
+    tr.collect()
+    torch.cuda.synchronize()
+    s, env = tr.store, tr.env
+    cfg = W.env_config(E=8, N=20, R=3, P=6, X=4, P_tax=5, K=3, T=40, seed=3)
+    sc = W.obs_scales(cfg)
+    act = s.act.cpu().numpy()
+    rew = s.rew.cpu().numpy()
+    done = s.done.cpu().numpy()
+    obs = s.obs.cpu().numpy().view(np.uint16)
+    mask = s.mask.cpu().numpy().view(np.uint32)
+    assert done.any(), "the rollout crosses an episode end"
+    for e in (0, 5):
+        o = oe.OracleEnv(cfg, e=e, seed=cfg["seed"])
+        lo, hi = int(env.row_offsets[e]), int(env.row_offsets[e + 1])
+        o_obs, o_mask, _ = o.observe(sc, env.Ds, with_gov=False)
+        assert np.array_equal(obs[0, lo:hi], o_obs) and np.array_equal(mask[0, lo:hi], o_mask)
+        for t in range(tr.T):
+            _, gov = o.random_actions(tr.seed + 1)
+            r_o, _, d_o = o.step(act[t, lo:hi], gov)
+            where = f"economy {e} step {t}"
+            assert np.all(np.abs(rew[t, lo:hi] - r_o) <= 1e-5 * np.abs(r_o)), where
+            assert (done[t, lo:hi] == d_o).all(), where
+            o_obs, o_mask, _ = o.observe(sc, env.Ds, with_gov=False)
+            assert np.array_equal(obs[t + 1, lo:hi], o_obs), where + " obs"
+            assert np.array_equal(mask[t + 1, lo:hi], o_mask), where + " mask"
+    w = tr.mlp.unflat(tr.mlp.params.cpu().numpy())
+    x = oe.bf16_bits_to_f32(obs[:tr.T, :, :tr.D].reshape(-1, tr.D)).astype(np.float64)
+    logits, value = op.mlp(x, op.bf16_weights(w))
+    lp = op.masked_log_softmax(logits, op.unpack_mask(mask[:tr.T].reshape(-1, mask.shape[2]), tr.A))
+    a = act.reshape(-1)
+    assert np.abs(s.logp.cpu().numpy().reshape(-1) - lp[np.arange(len(a)), a]).max() <= 2e-2
+    assert np.abs(s.val.cpu().numpy().reshape(-1) - value).max() <= 2e-2
+    assert np.abs(s.ent.cpu().numpy().reshape(-1) - op.entropy(lp)).max() <= 2e-2
+    adv_o, ret_o = op.gae(rew, s.val.cpu().numpy(), done, s.last_val.cpu().numpy(), tr.gamma, tr.lam)
+    assert np.allclose(s.adv.cpu().numpy(), adv_o, rtol=1e-4, atol=1e-4)
+    assert np.allclose(s.ret.cpu().numpy(), ret_o, rtol=1e-4, atol=1e-4)
+    tr.close()
+
+
 def test_autograd_function_matches_kernel_gradient():
     import torch
     from paper_2410_22165_amd import binding
@@ -45,7 +96,7 @@ def test_autograd_function_matches_kernel_gradient():
     tr.collect()
     flat = tr.store.flat()
     g = torch.zeros_like(tr.grads)
-    terms = torch.zeros(4, device="cuda")
+    terms = torch.zeros(binding.PPO_LOSS_TERMS, device="cuda")
     binding.ppo_backward(tr.mlp, flat, tr.M_total, 1, 0, 0, tr.mb_rows, tr.hp, tr.workspace, g, terms)
     p = tr.mlp.params.detach().clone().requires_grad_(True)
     tr.mlp.params = p
@@ -53,7 +104,8 @@ def test_autograd_function_matches_kernel_gradient():
     loss.backward()
     assert torch.equal(p.grad, g)
     t = terms.cpu().numpy()
-    assert abs(loss.item() - (t[0] + tr.hp["vf_coef"] * t[1] - tr.hp["ent_coef"] * t[2])) < 1e-5
+    assert loss.item() == t[4]
+    assert abs(t[4] - (t[0] + tr.hp["vf_coef"] * t[1] - tr.hp["ent_coef"] * t[2])) < 1e-5
     tr.close()
 
 
@@ -63,12 +115,11 @@ def test_update_lowers_the_minibatch_loss():
     tr = small_trainer(epochs=1, minibatches=1, lr=3e-3)
     tr.collect()
     flat = tr.store.flat()
-    terms = torch.zeros(4, device="cuda")
+    terms = torch.zeros(binding.PPO_LOSS_TERMS, device="cuda")
 
     def loss_now():
         binding.ppo_backward(tr.mlp, flat, tr.M_total, 1, 0, 0, tr.M_total, tr.hp, tr.workspace, tr.grads, terms)
-        t = terms.cpu().numpy()
-        return t[0] + tr.hp["vf_coef"] * t[1] - tr.hp["ent_coef"] * t[2]
+        return float(terms[4].item())
 
     before = loss_now()
     for step in range(1, 11):

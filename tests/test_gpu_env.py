@@ -130,15 +130,19 @@ def test_parity_max_population():
 
 def _sampled_parity(cfg, steps, sample, n_per_env=None, act_seed=77, check_every=100):
     """Full-size batch driven by the synthetic action stream; the oracle
-    replays only the sampled economies (each side derives the actions)."""
+    replays only the sampled economies (each side derives the actions).
+    Every step also writes the next observations and masks (the launch
+    configuration of the throughput run); at every state check they are
+    compared with the oracle's, bf16 bits and mask words exactly."""
     torch = _torch()
     env = make_env(cfg, n_per_env)
     b = env.buffers()
     ns = [cfg["N"]] * cfg["E"] if n_per_env is None else list(n_per_env)
     orc = {e: oe.OracleEnv(cfg, e=e, seed=cfg["seed"], n_agents=ns[e]) for e in sample}
+    sc, Ds = W.obs_scales(cfg), env.Ds
     for step in range(steps):
         env.random_actions(act_seed, b["act"], b["gov"])
-        env.step(b["act"], b["gov"], b["rew"], b["gov_rew"], b["done"])
+        env.step(b["act"], b["gov"], b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
         rew = b["rew"].cpu().numpy()
         act = b["act"].cpu().numpy()
         grew = b["gov_rew"].cpu().numpy()
@@ -149,10 +153,17 @@ def _sampled_parity(cfg, steps, sample, n_per_env=None, act_seed=77, check_every
             r_o, gr_o, _ = o.step(a_o, g_o)
             assert_rew_close(rew[lo:hi], r_o, f"step {step} env {e}")
             assert_rew_close([grew[e]], [gr_o], f"step {step} env {e} gov")
-        if (step + 1) % check_every == 0 or step == steps - 1:
+        if (step + 1) % check_every == 0 or step == steps - 1 or step < 3:
             gst = env.get_state()
+            obs = b["obs"].cpu().numpy().view(np.uint16)
+            mask = b["mask"].cpu().numpy().view(np.uint32)
             for e, o in orc.items():
-                compare_state(env.env_state(gst, e), o.state(), f"step {step} env {e}")
+                where = f"step {step} env {e}"
+                compare_state(env.env_state(gst, e), o.state(), where)
+                lo, hi = int(env.row_offsets[e]), int(env.row_offsets[e + 1])
+                o_obs, o_mask, _ = o.observe(sc, Ds, with_gov=False)
+                assert np.array_equal(obs[lo:hi], o_obs), where + " obs"
+                assert np.array_equal(mask[lo:hi], o_mask), where + " mask"
     env.close()
 
 
