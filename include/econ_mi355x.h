@@ -42,6 +42,7 @@ extern "C" {
 #define EJ_ENOMEM (-2)       /* device or host allocation failed */
 #define EJ_EHIP (-3)         /* a HIP runtime call failed; see ej_last_hip_error() */
 #define EJ_EUNSUPPORTED (-4) /* configuration outside the limits below */
+#define EJ_ESCRATCH (-5)     /* request larger than EJ_PPO_STATIC_SCRATCH_BYTES */
 
 #define EJ_MAX_N 1024 /* agents per economy */
 #define EJ_MAX_R 8    /* resource types */
@@ -314,6 +315,23 @@ int ej_ppo_workspace_size(const ej_mlp_desc* m, int64_t rows, int64_t* bytes);
 int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const ej_ppo_batch* b,
                     const ej_ppo_hparams* hp, void* d_workspace, int64_t workspace_bytes, float* d_grads,
                     float* d_loss, void* stream);
+
+/* Allocation-free ej_ppo_backward, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as ej_ppo_backward,
+ * without the caller workspace: the workspace is a static device array of
+ * EJ_PPO_STATIC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends (its address is looked up once per device, on
+ * the first call there).  A minibatch whose ej_ppo_workspace_size exceeds it
+ * returns EJ_ESCRATCH before anything is launched (at 35 -> 256 -> 256 ->
+ * 125 + 1 that is about 3 800 rows).  The call itself allocates nothing.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (different streams, threads or handles) race and must be
+ * serialised by the caller. */
+#define EJ_PPO_STATIC_SCRATCH_BYTES (64u << 20)
+int ej_ppo_backward_static(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work,
+                           const ej_ppo_batch* b, const ej_ppo_hparams* hp, float* d_grads, float* d_loss,
+                           void* stream);
 
 /* Adam (Kingma & Ba) with bias correction on n fp32 parameters; `step` is
  * the 1-based update count. */

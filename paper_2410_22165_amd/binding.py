@@ -114,6 +114,8 @@ def _declare_learner(L):
         "ej_ppo_workspace_size": [C.POINTER(EjMlpDesc), i64, C.POINTER(i64)],
         "ej_ppo_backward": [C.POINTER(EjMlpDesc), vp, vp, C.POINTER(EjPpoBatch), C.POINTER(EjPpoHparams), vp, i64,
                             vp, vp, vp],
+        "ej_ppo_backward_static": [C.POINTER(EjMlpDesc), vp, vp, C.POINTER(EjPpoBatch), C.POINTER(EjPpoHparams),
+                                   vp, vp, vp],
         "ej_adam": [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp],
     }
     for name, args in table.items():
@@ -358,6 +360,23 @@ def ppo_backward(mlp: "Mlp", storage: dict, M_total: int, perm_a: int, perm_c: i
     check(lib().ej_ppo_backward(C.byref(mlp.desc), ptr(mlp.params), ptr(mlp.work), C.byref(b), C.byref(h),
                                 ptr(workspace), workspace.numel(), ptr(grads), ptr(loss), stream_ptr(stream)),
           "ej_ppo_backward")
+
+
+EJ_ESCRATCH = -5
+PPO_STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def ppo_backward_static(mlp: "Mlp", storage: dict, M_total: int, perm_a: int, perm_c: int, row_begin: int,
+                        rows: int, hp: dict, grads, loss, stream=None):
+    """ej_ppo_backward without a caller workspace (the library's static
+    device scratch); raises when the minibatch needs more than it holds."""
+    if loss.numel() < PPO_LOSS_TERMS:
+        raise EconError(f"ej_ppo_backward_static writes {PPO_LOSS_TERMS} loss terms; got {loss.numel()}")
+    b = EjPpoBatch(*(ptr(storage[k]) for k in ("obs", "mask", "act", "logp_old", "val_old", "adv", "ret")),
+                   M_total, perm_a, perm_c, row_begin, rows)
+    h = EjPpoHparams(hp["clip"], hp["vclip"], hp["vf_coef"], hp["ent_coef"])
+    check(lib().ej_ppo_backward_static(C.byref(mlp.desc), ptr(mlp.params), ptr(mlp.work), C.byref(b), C.byref(h),
+                                       ptr(grads), ptr(loss), stream_ptr(stream)), "ej_ppo_backward_static")
 
 
 def counter_add(counter, inc: int, stream=None):

@@ -1526,6 +1526,7 @@ const char* ej_strerror(int code)
     case EJ_ENOMEM: return "out of memory";
     case EJ_EHIP: return "HIP runtime error";
     case EJ_EUNSUPPORTED: return "configuration outside the supported limits";
+    case EJ_ESCRATCH: return "request larger than the static scratch of the allocation-free entry point";
     default: return "unknown error";
     }
 }

@@ -22,6 +22,8 @@
 //   dw_reduce_kernel sums the partials in a fixed order (deterministic).
 #include "econ_mlp.h"
 
+#include <mutex>
+
 namespace econ {
 
 struct PpoBatchDev {
@@ -695,6 +697,42 @@ static int ppo_workspace(const MlpDims& d, int64_t rows, PpoWorkspace* w)
     return EJ_OK;
 }
 
+// Workspace of ej_ppo_backward_static: one array per device, which each
+// device holds until the process ends.  Host code never passes `scratch`
+// itself to a kernel or a copy (in host code the name is a stand-in, not a
+// device address): it uses the address hipGetSymbolAddress returns for the
+// current device, taken once per device on its first call.  Nothing in it
+// needs to start at zero: every kernel of the backward writes what it
+// later reads within the same call.
+static __device__ __align__(256) unsigned char scratch[EJ_PPO_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static void* g_scratch_addr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static int static_scratch_address(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_last_hip_error(e);
+        return EJ_EHIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) return EJ_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_last_hip_error(e);
+            return EJ_EHIP;
+        }
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return EJ_OK;
+}
+
 static int launch_dw(const uint16_t* Tx, int J, const uint16_t* Ty, int N, int64_t nmb, int G, float* part,
                      float* colsum, hipStream_t st)
 {
@@ -761,9 +799,9 @@ int ej_ppo_workspace_size(const ej_mlp_desc* m, int64_t rows, int64_t* bytes)
     return EJ_OK;
 }
 
-int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const ej_ppo_batch* b,
-                    const ej_ppo_hparams* hp, void* d_workspace, int64_t workspace_bytes, float* d_grads,
-                    float* d_loss, void* stream)
+static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work,
+                             const ej_ppo_batch* b, const ej_ppo_hparams* hp, void* d_workspace,
+                             int64_t workspace_bytes, float* d_grads, float* d_loss, void* stream)
 {
     if (!m || !d_params || !d_work || !b || !hp || !d_workspace || !d_grads || !d_loss) return EJ_EINVAL;
     if (!b->obs || !b->mask || !b->act || !b->logp_old || !b->val_old || !b->adv || !b->ret) return EJ_EINVAL;
@@ -828,6 +866,28 @@ int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t*
     loss_final_kernel<<<1, 256, 0, st>>>(lslices, nslices, b->rows, hp->vf_coef, hp->ent_coef, d_loss);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
+}
+
+int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const ej_ppo_batch* b,
+                    const ej_ppo_hparams* hp, void* d_workspace, int64_t workspace_bytes, float* d_grads,
+                    float* d_loss, void* stream)
+{
+    return ppo_backward_impl(m, d_params, d_work, b, hp, d_workspace, workspace_bytes, d_grads, d_loss, stream);
+}
+
+int ej_ppo_backward_static(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work,
+                           const ej_ppo_batch* b, const ej_ppo_hparams* hp, float* d_grads, float* d_loss,
+                           void* stream)
+{
+    if (!m || !b) return EJ_EINVAL;
+    int64_t need = 0;
+    int rc = ej_ppo_workspace_size(m, b->rows, &need);
+    if (rc != EJ_OK) return rc;
+    if (need > (int64_t)EJ_PPO_STATIC_SCRATCH_BYTES) return EJ_ESCRATCH;
+    void* ws = nullptr;
+    if ((rc = static_scratch_address(&ws)) != EJ_OK) return rc;
+    return ppo_backward_impl(m, d_params, d_work, b, hp, ws, (int64_t)EJ_PPO_STATIC_SCRATCH_BYTES, d_grads, d_loss,
+                             stream);
 }
 
 int ej_adam(float* d_params, const float* d_grads, float* d_m, float* d_v, int64_t n, int32_t step, float lr,

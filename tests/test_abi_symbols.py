@@ -37,3 +37,21 @@ def test_strerror_without_gpu():
     lib = binding.lib()
     assert lib.ej_strerror(0) == b"ok"
     assert lib.ej_strerror(-4).startswith(b"configuration")
+
+
+def test_static_scratch_backward_rejects_oversize_on_the_host():
+    """ej_ppo_backward_static sizes the minibatch's workspace before any HIP
+    call: one that does not fit the static scratch returns EJ_ESCRATCH (no
+    device needed), and a NULL descriptor returns EJ_EINVAL."""
+    import ctypes as C
+    from paper_2410_22165_amd import binding
+    L = binding.lib()
+    desc = binding.EjMlpDesc(35, 40, 256, 125, 64)
+    need = C.c_int64(0)
+    assert L.ej_ppo_workspace_size(C.byref(desc), 100000, C.byref(need)) == 0
+    assert need.value > binding.PPO_STATIC_SCRATCH_BYTES
+    b = binding.EjPpoBatch(*([None] * 7), 100000, 1, 0, 0, 100000)
+    h = binding.EjPpoHparams(0.2, 10.0, 0.25, 0.01)
+    rc = L.ej_ppo_backward_static(C.byref(desc), None, None, C.byref(b), C.byref(h), None, None, None)
+    assert rc == binding.EJ_ESCRATCH
+    assert L.ej_ppo_backward_static(None, None, None, C.byref(b), C.byref(h), None, None, None) == -1
