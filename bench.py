@@ -153,15 +153,52 @@ def ppo_benchmark(updates: int = 1, groups: int = 4):
             "last_loss_terms": [round(x, 5) for x in terms]}
 
 
-def rollout_benchmark(name: str, H: int, steps: int = 40, graph_steps: int = 20, n_per_env=None,
+def timed_launches(fn, reps: int) -> float:
+    """Milliseconds per call of fn, from HIP events on the current stream."""
+    import torch
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(s)
+    for _ in range(reps):
+        fn()
+    b.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def graph_rollouts(env, mlp, T: int, reps: int, group_counts, seed: int = 1):
+    """The rollout of T steps as the library captures it (ej_rollout_capture,
+    carry on: each replay continues from the last), against the same
+    launches issued one by one with one group (plain per-step launches).
+    Returns (plain ms/step, {groups: graph ms/step})."""
+    from paper_2410_22165_amd import binding
+
+    bufs = binding.rollout_storage(env, T)
+    plain = binding.Rollout(env, mlp, bufs, T, seed, groups=1, last_value=False, carry=True)
+    plain.launch_plain()
+    ms_plain = timed_launches(plain.launch_plain, reps) / T
+    plain.close()
+    graph_ms = {}
+    for ng in group_counts:
+        r = binding.Rollout(env, mlp, bufs, T, seed, groups=ng, last_value=False, carry=True)
+        r.launch()
+        graph_ms[ng] = timed_launches(r.launch, reps) / T
+        r.close()
+    del bufs
+    return ms_plain, graph_ms
+
+
+def rollout_benchmark(name: str, H: int, graph_steps: int = 20, reps: int = 2, n_per_env=None,
                       group_counts=(1, 2, 4)):
     """Rollout steps (policy forward + economy step with its government draw)
     on one workload: plain per-step launches with one workgroup per economy
-    against the autotuned launch shapes replayed from a captured graph, with
-    the economies in 1, 2 or 4 groups on their own streams (fastest kept)."""
+    against the autotuned launch shapes replayed from the library's captured
+    graph of `graph_steps` steps, with the economies in 1, 2 or 4 groups on
+    their own streams (fastest kept)."""
     import torch
 
-    from paper_2410_22165_amd import autotune, binding
+    from paper_2410_22165_amd import binding
 
     wl = W.workload(name)
     cfg = wl["env"]
@@ -172,70 +209,22 @@ def rollout_benchmark(name: str, H: int, steps: int = 40, graph_steps: int = 20,
     dev = torch.device("cuda")
     act = torch.zeros(M, dtype=torch.int32, device=dev)
     logp, val, ent = (torch.zeros(M, device=dev) for _ in range(3))
-    ctr_base = torch.zeros(1, dtype=torch.int64, device=dev)
-    stream = torch.cuda.current_stream()
     env.observe(b["obs"], b["mask"])
-
     env.set_gov_draw(True, 2)
-
-    def step(i):
-        mlp.forward(b["obs"], b["mask"], M, 1, i, act, logp, val, ent, ctr_base=ctr_base)
-        env.step(act, None, b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
-
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def timed(fn, reps):
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(reps):
-            fn()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1)
-
     env.set_launch(0, 0)
-    for i in range(5):
-        step(i)
-    ms_plain = timed(lambda: step(0), steps) / steps
-    tuned_env = autotune.tune_env(env, dict(b, act=act), use_cache=False)
-    tuned_pol = autotune.tune_policy(mlp, b["obs"], b["mask"], M, (act, logp, val, ent), use_cache=False)
-    for i in range(3):
-        step(i)
-    torch.cuda.synchronize()
-    from paper_2410_22165_amd.ppo import GroupStreams, economy_groups
-
-    def grouped_step(i, groups, gs):
-        for g, (e0, e1, r0, r1) in enumerate(groups):
-            with gs.stream(g):
-                mlp.forward(b["obs"][r0:r1], b["mask"][r0:r1], r1 - r0, 1, i, act[r0:r1], logp[r0:r1], val[r0:r1],
-                            ent[r0:r1], ctr_base=ctr_base, row_base=r0)
-                env.step(act, None, b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"], economies=(e0, e1))
-
-    reps = max(1, steps // graph_steps)
-    graph_ms = {}
-    for ng in group_counts:
-        groups = economy_groups(env, ng)
-        gs = GroupStreams(len(groups))
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            gs.fork()
-            for i in range(graph_steps):
-                grouped_step(i, groups, gs)
-            gs.join()
-            binding.counter_add(ctr_base, graph_steps)
-        graph.replay()
-        graph_ms[ng] = timed(graph.replay, reps) / (reps * graph_steps)
-        del graph
+    ms_plain, _ = graph_rollouts(env, mlp, graph_steps, reps, ())
+    tuned = binding.autotune(env, mlp, dict(obs=b["obs"], mask=b["mask"], act=act, logp=logp, val=val, ent=ent,
+                                            rew=b["rew"], gov_rew=b["gov_rew"], done=b["done"]))
+    _, graph_ms = graph_rollouts(env, mlp, graph_steps, reps, group_counts)
     best = min(graph_ms, key=graph_ms.get)
     ms_graph = graph_ms[best]
     env.close()
     return {"workload": name, "economies": cfg["E"], "agents": int(M), "hidden": H,
             "value": round(M / (ms_graph / 1e3), 1), "unit": "agent-steps/s",
             "plain_ms_per_step": round(ms_plain, 5), "graph_ms_per_step": round(ms_graph, 5),
-            "x_vs_plain": round(ms_plain / ms_graph, 4), "groups": best,
+            "graph_steps": graph_steps, "x_vs_plain": round(ms_plain / ms_graph, 4), "groups": best,
             "graph_ms_per_step_by_groups": {str(k): round(v, 5) for k, v in graph_ms.items()},
-            "env_launch": {"mode": tuned_env["mode"], "workgroups": tuned_env["workgroups"]},
-            "policy_tile_rows": tuned_pol["tile_rows"]}
+            "autotune": tuned}
 
 
 def main():
@@ -260,7 +249,7 @@ def main():
 
     import torch
 
-    from paper_2410_22165_amd import autotune, binding
+    from paper_2410_22165_amd import binding
 
     torch.cuda.set_device(0)
     if args.calib_copy_mib:
@@ -292,61 +281,22 @@ def main():
     def economy():
         env.step(act, None, b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
 
-    # launch shapes chosen by the autotuner (state restored afterwards)
-    tuned_env = autotune.tune_env(env, dict(b, act=act), use_cache=False)
-    tuned_pol = autotune.tune_policy(mlp, b["obs"], b["mask"], M, (act, logp, val, ent), use_cache=False)
+    # launch shapes chosen by the autotuner (everything a trial changes is restored)
+    tuned = binding.autotune(env, mlp, dict(obs=b["obs"], mask=b["mask"], act=act, logp=logp, val=val, ent=ent,
+                                            rew=b["rew"], gov_rew=b["gov_rew"], done=b["done"]))
 
     for i in range(args.warmup):
         policy(i)
         economy()
     torch.cuda.synchronize()
 
-    # plain: one launch per kernel per step from the host
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for i in range(args.steps):
-        policy(i)
-        economy()
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms_plain = start.elapsed_time(stop) / args.steps
-
-    # graph: G steps captured once and replayed (the sampling counter lives on
-    # the device), the economies split into groups whose policy -> step chains
-    # run on their own streams (one group's policy overlaps another's step);
-    # the group count giving the fastest replay is kept
-    from paper_2410_22165_amd.ppo import GroupStreams, economy_groups
-
-    def grouped_step(i, groups, gs):
-        for g, (e0, e1, r0, r1) in enumerate(groups):
-            with gs.stream(g):
-                mlp.forward(b["obs"][r0:r1], b["mask"][r0:r1], r1 - r0, 1, i, act[r0:r1], logp[r0:r1], val[r0:r1],
-                            ent[r0:r1], ctr_base=ctr_base, row_base=r0)
-                env.step(act, None, b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"], economies=(e0, e1))
-
+    # plain: one launch per kernel per step; graph: the rollout of G steps as
+    # the library captures it, the economies split into groups whose policy ->
+    # step chains run on their own streams (one group's policy overlaps
+    # another's step); the group count giving the fastest replay is kept
     G = max(1, min(args.graph_steps, args.steps))
     reps = max(1, args.steps // G)
-    graph_ms = {}
-    for ng in args.groups:
-        groups = economy_groups(env, ng)
-        gs = GroupStreams(len(groups))
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            gs.fork()
-            for i in range(G):
-                grouped_step(i, groups, gs)
-            gs.join()
-            binding.counter_add(ctr_base, G)
-        graph.replay()
-        torch.cuda.synchronize()
-        start.record(stream)
-        for _ in range(reps):
-            graph.replay()
-        stop.record(stream)
-        torch.cuda.synchronize()
-        graph_ms[ng] = start.elapsed_time(stop) / (reps * G)
-        del graph
+    ms_plain, graph_ms = graph_rollouts(env, mlp, G, reps, args.groups)
     best_groups = min(graph_ms, key=graph_ms.get)
     ms_graph = graph_ms[best_groups]
     timed_steps = reps * G
@@ -372,7 +322,7 @@ def main():
     pol_flops = policy_flops_per_row(D, H, A) * M
     env_gbs = env_bytes / (ms_env / 1e3) / 1e9
     pol_tflops = pol_flops / (ms_pol / 1e3) / 1e12
-    env_kernel = "env_step_persistent_kernel" if tuned_env["mode"] == 1 else "env_step_kernel"
+    env_kernel = "env_step_persistent_kernel" if tuned["env_mode"] == 1 else "env_step_kernel"
     kernels = {
         env_kernel: {"bound": "hbm", "achieved": env_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": env_gbs / HBM_PEAK_GBS, "ms": ms_env,
@@ -406,8 +356,7 @@ def main():
                    "policy": f"{D}->{H}->{H}->{A}+1", "parallelism": "one workgroup per economy",
                    "launch": (f"hipGraph of {G} steps, {best_groups} economy group(s) on their own streams"
                               if ms_graph <= ms_plain else "per-step launches"),
-                   "env_launch": {"mode": tuned_env["mode"], "workgroups": tuned_env["workgroups"]},
-                   "policy_tile_rows": tuned_pol["tile_rows"]},
+                   "autotune": tuned},
         "x_vs_plain": round(ms_plain / ms_graph, 4),
         "plain_ms_per_step": round(ms_plain, 5),
         "graph_ms_per_step": round(ms_graph, 5),
@@ -423,7 +372,7 @@ def main():
     if not args.no_extra:
         wl4 = W.workload("econ_e512_uneven")
         ns = W.uneven_populations(wl4["env"]["E"], wl4["n_min"], wl4["n_max"], seed=0)
-        out["uneven"] = rollout_benchmark("econ_e512_uneven", 256, n_per_env=ns)
+        out["uneven"] = rollout_benchmark("econ_e512_uneven", 256, graph_steps=1000, reps=1, n_per_env=ns)
         out["large"] = rollout_benchmark("econ_e256_n1000_ppo", W.workload("econ_e256_n1000_ppo")["hidden"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, weights, args.cpu_budget)

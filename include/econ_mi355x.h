@@ -97,6 +97,7 @@ typedef struct ej_env_dims_t {
     int32_t D_stride;   /* bf16 elements per observation row (D rounded up to 8) */
     int32_t D_gov;      /* government observation floats: 3 (3 + R) + K + 1 + 4 R */
     int32_t K;          /* government action entries per economy */
+    int32_t E;          /* economies */
 } ej_env_dims_t;
 
 typedef struct ej_env ej_env;
@@ -174,6 +175,13 @@ int ej_env_step_range(ej_env* env, int32_t e_begin, int32_t e_end, const int32_t
  * the queue resets itself at the end of every launch, so the call can be
  * captured in a graph and replayed.  Results are identical in both modes. */
 int ej_env_set_launch(ej_env* env, int32_t mode, int32_t workgroups);
+
+/* Agents per wavefront of ej_env_step: 64 (default), 32 or 16.  Wave w of
+ * an economy's workgroup takes agents w * apw .. w * apw + apw - 1 and the
+ * lanes beyond apw stay idle, so a smaller value spreads an economy over
+ * more waves (ceil(n / apw) waves; at most 16).  Results are identical for
+ * every value.  EJ_EUNSUPPORTED when N needs more than 16 waves. */
+int ej_env_set_agents_per_wave(ej_env* env, int32_t agents_per_wave);
 
 /* Government levels drawn by the step itself (ej_env_step with d_gov = NULL):
  * uniform over 0..20, exactly the levels ej_env_random_actions(env, seed, ...)
@@ -315,6 +323,97 @@ int ej_ppo_workspace_size(const ej_mlp_desc* m, int64_t rows, int64_t* bytes);
 int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const ej_ppo_batch* b,
                     const ej_ppo_hparams* hp, void* d_workspace, int64_t workspace_bytes, float* d_grads,
                     float* d_loss, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Rollout graph and autotuner (the batching forms around the kernels).
+ * ------------------------------------------------------------------------ */
+
+/* Storage of a T-step rollout (Table 2: rollout length), every array a
+ * device pointer owned by the caller, time-major:
+ *   d_obs  [(T + 1) * M * D_stride] bf16 bits: d_obs[0] holds the
+ *          observation of the current state (ej_env_observe) before the first
+ *          launch; step t writes the observation after it to d_obs[t + 1]
+ *   d_mask [(T + 1) * M * mask_words], likewise
+ *   d_act, d_logp, d_val, d_ent, d_rew [T * M]; d_done [T * M] uint8
+ *   d_gov_rew [T * E]  the government's reward of every step
+ *   d_last_val [M]     value of the state after the last step
+ *   d_adv, d_ret [T * M] nullable together: GAE(gamma, lam) when given
+ *   d_tmp [3 * M] fp32 scratch (the last-value forward's discarded outputs)
+ *   d_ctr [1] uint64  sampling counter, advanced by T + 1 per launch */
+typedef struct ej_rollout_buffers {
+    uint16_t* d_obs;
+    uint32_t* d_mask;
+    int32_t* d_act;
+    float *d_logp, *d_val, *d_ent, *d_rew;
+    uint8_t* d_done;
+    float* d_gov_rew;
+    float* d_last_val;
+    float *d_adv, *d_ret;
+    float* d_tmp;
+    uint64_t* d_ctr;
+} ej_rollout_buffers;
+
+/* T steps; economies split into `groups` contiguous ranges whose policy ->
+ * step chains run on their own streams inside the graph (one group's policy
+ * overlaps another's economy step); sampler seed; GAE gamma, lam;
+ * last_value = 0 skips the last-value forward and GAE; carry = 1 ends every
+ * launch by copying slot T of d_obs and d_mask to slot 0, so that launches
+ * follow each other without the caller (slot 0 of the stored rollout is then
+ * overwritten: a learner that reads the storage keeps carry = 0 and copies
+ * after its update). */
+typedef struct ej_rollout_config {
+    int32_t T, groups, last_value, carry;
+    uint64_t seed;
+    float gamma, lam;
+} ej_rollout_config;
+
+typedef struct ej_rollout ej_rollout;
+
+/* Captures the whole rollout -- T x (policy forward of every group, economy
+ * step of its economies), then the last-value forward, GAE and the counter
+ * advance -- as one HIP graph (stream capture on streams the library
+ * creates), instantiates it, and returns the handle.  Nothing runs at
+ * capture.  The economy's government must draw its own levels
+ * (ej_env_set_gov_draw) and its launch shape is the one set at capture.
+ * The graph keeps every pointer: env, the weights and the buffers must
+ * outlive the handle.  Replays give exactly the storage of the same calls
+ * launched one by one (same seeds, same counters). */
+int ej_rollout_capture(ej_env* env, const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work,
+                       const ej_rollout_config* cfg, const ej_rollout_buffers* bufs, ej_rollout** out);
+
+/* Replays the captured rollout on `stream` (asynchronous). */
+int ej_rollout_launch(ej_rollout* r, void* stream);
+
+/* The same rollout from one launch per kernel (no graph), for comparison. */
+int ej_rollout_launch_plain(ej_rollout* r, void* stream);
+
+int ej_rollout_destroy(ej_rollout* r);
+
+/* Result of ej_autotune: the chosen economy-step launch (mode and
+ * persistent workgroups as in ej_env_set_launch; agents per wavefront) and
+ * policy row tile, with their mean times per launch in milliseconds. */
+typedef struct ej_autotune_result {
+    int32_t env_mode, env_workgroups, agents_per_wave, policy_tile_rows;
+    float env_ms, policy_ms;
+    int32_t candidates; /* launch shapes timed */
+} ej_autotune_result;
+
+/* Times the launch shapes of the rollout kernels with HIP events on
+ * `stream` (reps launches each after one warm-up launch) and applies the
+ * fastest: for the economy step, one workgroup per economy or a persistent
+ * launch with 1, 2 or 4 workgroups per compute unit, each at 64, 32 and 16
+ * agents per wavefront; for the policy forward, 64- or 128-row tiles
+ * (H <= 256), written to m->tile_rows.  The buffers are a rollout step's
+ * (as ej_env_step and ej_policy_forward take them; d_gov nullable when the
+ * step draws its own levels).  Everything a trial step changes -- the
+ * economy state, rejection counters and cached utilities, and the d_obs,
+ * d_mask, d_act, d_rew, d_gov_rew and d_done buffers -- is restored before
+ * the call returns, so tuning changes no result.  m may be NULL (economy
+ * only).  Allocates temporary device copies; synchronous. */
+int ej_autotune(ej_env* env, ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, uint16_t* d_obs,
+                uint32_t* d_mask, int32_t* d_act, const int32_t* d_gov, float* d_logp, float* d_val, float* d_ent,
+                float* d_rew, float* d_gov_rew, uint8_t* d_done, int32_t reps, ej_autotune_result* out,
+                void* stream);
 
 /* Allocation-free ej_ppo_backward, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that

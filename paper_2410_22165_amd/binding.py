@@ -34,7 +34,7 @@ class EjEnvConfig(C.Structure):
 
 class EjEnvDims(C.Structure):
     _fields_ = [("M", C.c_int64), ("A", C.c_int32), ("mask_words", C.c_int32), ("D", C.c_int32),
-                ("D_stride", C.c_int32), ("D_gov", C.c_int32), ("K", C.c_int32)]
+                ("D_stride", C.c_int32), ("D_gov", C.c_int32), ("K", C.c_int32), ("E", C.c_int32)]
 
 
 _STATE_FIELDS = ("t", "ep", "rates", "coin_inv", "coin_esc", "labor", "snap", "sc", "res_inv", "res_esc", "sg",
@@ -61,6 +61,22 @@ class EjPpoBatch(C.Structure):
 
 class EjPpoHparams(C.Structure):
     _fields_ = [(n, C.c_float) for n in ("clip", "vclip", "vf_coef", "ent_coef")]
+
+
+class EjRolloutBuffers(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("obs", "mask", "act", "logp", "val", "ent", "rew", "done", "gov_rew",
+                                           "last_val", "adv", "ret", "tmp", "ctr")]
+
+
+class EjRolloutConfig(C.Structure):
+    _fields_ = [("T", C.c_int32), ("groups", C.c_int32), ("last_value", C.c_int32), ("carry", C.c_int32),
+                ("seed", C.c_uint64), ("gamma", C.c_float), ("lam", C.c_float)]
+
+
+class EjAutotuneResult(C.Structure):
+    _fields_ = [("env_mode", C.c_int32), ("env_workgroups", C.c_int32), ("agents_per_wave", C.c_int32),
+                ("policy_tile_rows", C.c_int32), ("env_ms", C.c_float), ("policy_ms", C.c_float),
+                ("candidates", C.c_int32)]
 
 
 class EconError(RuntimeError):
@@ -97,6 +113,7 @@ def lib():
     L.ej_env_status.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), vp]
     L.ej_env_set_launch.argtypes = [vp, i32, i32]
     L.ej_env_set_gov_draw.argtypes = [vp, i32, C.c_uint64]
+    L.ej_env_set_agents_per_wave.argtypes = [vp, i32]
     _declare_learner(L)
     _lib = L
     return L
@@ -117,6 +134,13 @@ def _declare_learner(L):
         "ej_ppo_backward_static": [C.POINTER(EjMlpDesc), vp, vp, C.POINTER(EjPpoBatch), C.POINTER(EjPpoHparams),
                                    vp, vp, vp],
         "ej_adam": [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp],
+        "ej_rollout_capture": [vp, C.POINTER(EjMlpDesc), vp, vp, C.POINTER(EjRolloutConfig),
+                               C.POINTER(EjRolloutBuffers), C.POINTER(vp)],
+        "ej_rollout_launch": [vp, vp],
+        "ej_rollout_launch_plain": [vp, vp],
+        "ej_rollout_destroy": [vp],
+        "ej_autotune": [vp, C.POINTER(EjMlpDesc), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32,
+                        C.POINTER(EjAutotuneResult), vp],
     }
     for name, args in table.items():
         fn = getattr(L, name, None)
@@ -230,6 +254,10 @@ class Env:
     def random_actions(self, act_seed: int, act, gov, stream=None):
         check(lib().ej_env_random_actions(self._h, act_seed, ptr(act), ptr(gov), stream_ptr(stream)),
               "ej_env_random_actions")
+
+    def set_agents_per_wave(self, apw: int):
+        """Agents per wavefront of the step (64, 32 or 16; same results)."""
+        check(lib().ej_env_set_agents_per_wave(self._h, apw), "ej_env_set_agents_per_wave")
 
     def set_launch(self, mode: int, workgroups: int = 0):
         """mode 0: one workgroup per economy; 1: persistent work queue."""
@@ -381,3 +409,72 @@ def ppo_backward_static(mlp: "Mlp", storage: dict, M_total: int, perm_a: int, pe
 
 def counter_add(counter, inc: int, stream=None):
     check(lib().ej_counter_add(ptr(counter), inc, stream_ptr(stream)), "ej_counter_add")
+
+
+class Rollout:
+    """A T-step rollout captured by the library as one HIP graph
+    (ej_rollout_capture): policy forward + economy step per step, economy
+    groups on their own streams, then the last-value forward, GAE and the
+    sampling-counter advance.  `bufs` holds the torch storage it writes
+    (kept alive here, since the graph keeps the pointers)."""
+
+    def __init__(self, env: "Env", mlp: "Mlp", bufs: dict, T: int, seed: int, groups: int = 1,
+                 last_value: bool = True, gamma: float = 0.99, lam: float = 0.95, carry: bool = False):
+        self.env, self.mlp, self.bufs = env, mlp, bufs
+        b = EjRolloutBuffers(*(ptr(bufs.get(k)) for k in ("obs", "mask", "act", "logp", "val", "ent", "rew", "done",
+                                                           "gov_rew", "last_val", "adv", "ret", "tmp", "ctr")))
+        cfg = EjRolloutConfig(T, groups, 1 if last_value else 0, 1 if carry else 0, seed, gamma, lam)
+        h = C.c_void_p()
+        check(lib().ej_rollout_capture(env._h, C.byref(mlp.desc), ptr(mlp.params), ptr(mlp.work), C.byref(cfg),
+                                       C.byref(b), C.byref(h)), "ej_rollout_capture")
+        self._h = h
+
+    def launch(self, stream=None):
+        check(lib().ej_rollout_launch(self._h, stream_ptr(stream)), "ej_rollout_launch")
+
+    def launch_plain(self, stream=None):
+        check(lib().ej_rollout_launch_plain(self._h, stream_ptr(stream)), "ej_rollout_launch_plain")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ej_rollout_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(env: "Env", mlp: "Mlp | None", buf: dict, reps: int = 10, stream=None) -> dict:
+    """ej_autotune: times the economy-step launch shapes (and the policy row
+    tile when mlp is given) and applies the fastest; everything a trial step
+    changes is restored."""
+    r = EjAutotuneResult()
+    check(lib().ej_autotune(env._h, C.byref(mlp.desc) if mlp is not None else None,
+                            ptr(mlp.params) if mlp is not None else None, ptr(mlp.work) if mlp is not None else None,
+                            ptr(buf["obs"]), ptr(buf["mask"]), ptr(buf["act"]), ptr(buf.get("gov")),
+                            ptr(buf.get("logp")), ptr(buf.get("val")), ptr(buf.get("ent")), ptr(buf["rew"]),
+                            ptr(buf["gov_rew"]), ptr(buf["done"]), reps, C.byref(r), stream_ptr(stream)),
+          "ej_autotune")
+    return {n: (float(getattr(r, n)) if n.endswith("_ms") else int(getattr(r, n))) for n, _ in r._fields_}
+
+
+def rollout_storage(env: "Env", T: int, last_value: bool = False) -> dict:
+    """Device arrays of a T-step rollout in the layout ej_rollout_capture
+    writes; obs[0] / mask[0] hold the observation of the current state."""
+    import torch
+    z = dict(device="cuda")
+    M, E = env.M, env.E
+    b = dict(obs=torch.zeros((T + 1, M, env.Ds), dtype=torch.int16, **z),
+             mask=torch.zeros((T + 1, M, env.W), dtype=torch.int32, **z),
+             act=torch.zeros((T, M), dtype=torch.int32, **z), logp=torch.zeros((T, M), **z),
+             val=torch.zeros((T, M), **z), ent=torch.zeros((T, M), **z), rew=torch.zeros((T, M), **z),
+             done=torch.zeros((T, M), dtype=torch.uint8, **z), gov_rew=torch.zeros((T, E), **z),
+             ctr=torch.zeros(1, dtype=torch.int64, **z))
+    if last_value:
+        b.update(last_val=torch.zeros(M, **z), adv=torch.zeros((T, M), **z), ret=torch.zeros((T, M), **z),
+                 tmp=torch.zeros(3 * M, **z))
+    env.observe(b["obs"][0], b["mask"][0])
+    return b

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libecon_mi355x.so")
-SOURCES = ["econ_env.hip", "econ_policy.hip", "econ_ppo.hip"]
+SOURCES = ["econ_env.hip", "econ_policy.hip", "econ_ppo.hip", "econ_rollout.hip"]
 ARCH = os.environ.get("ECON_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

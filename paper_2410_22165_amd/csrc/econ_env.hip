@@ -43,6 +43,7 @@ struct EnvParams {
     uint64_t gov_seed;  // government levels drawn in the step when gov_draw != 0 and no levels are passed
     uint64_t div_X, div_P;  // reciprocal multipliers 2^32 / X, 2^32 / P rounded up: j / X = (j div_X) >> 32 for j < 2^27
     int32_t gov_draw;
+    int32_t apw;   // agents per wavefront in the step (64, 32 or 16; lanes beyond it idle)
     int64_t Ntot;  // stride between two state fields
     int32_t prices[EJ_MAX_P];
     int32_t cutoffs[EJ_MAX_K];
@@ -798,7 +799,12 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
                                              uint32_t* __restrict__ mask, unsigned char* smem)
 {
     const int NT = blockDim.x, tid = threadIdx.x;
-    const int NL = NT * APT;
+    // agents per wavefront: in round k, wave w takes agents k NR + w apw ..
+    // + apw - 1 (lanes apw .. 63 idle); NL agent slots in all
+    const int apw = P.apw;
+    const int NR = (NT >> 6) * apw;
+    const int NL = NR * APT;
+    const int lane_slot = (tid & 63) < apw ? (tid >> 6) * apw + (tid & 63) : (1 << 30);
     Lds L;
     lds_layout(P, NL, smem, &L);
     const int n = S.env_n[e];
@@ -818,7 +824,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     const double cached_ug = S.ug[e];  // social welfare of the step-start state, NaN when unknown
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-        const int li = tid + k * NT;
+        const int li = lane_slot + k * NR;
         a_in[k] = 0;
         u0[k] = 0.0;
         if (li < n) {
@@ -871,7 +877,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     // utilities of the step-start state
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-        const int li = tid + k * NT;
+        const int li = lane_slot + k * NR;
         eff[k] = 0;
         my_rank[k] = 0;
         if (li < n) {
@@ -885,7 +891,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     // action validation against the step-start mask
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-        const int li = tid + k * NT;
+        const int li = lane_slot + k * NR;
         if (li >= n) continue;
         const int a = a_in[k];
         if (action_allowed(P, ag[k], n_active(ag[k], X), a, L.prices)) eff[k] = a;
@@ -896,7 +902,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     const int slot_new = t % X;
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-        const int li = tid + k * NT;
+        const int li = lane_slot + k * NR;
         if (li >= n) continue;
         L.ncode[li] = -1;
         Act d = decode_action(P, eff[k]);
@@ -951,7 +957,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     int32_t* ntmp = (int32_t*)L.sortbuf;
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-        const int li = tid + k * NT;
+        const int li = lane_slot + k * NR;
         if (li < n && L.ncode[li] >= 0) ntmp[L.nboff[L.ncode[li]] + my_rank[k]] = li;
     }
     lds_barrier();
@@ -962,7 +968,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     const int tX = t % X;
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-        const int li = tid + k * NT;
+        const int li = lane_slot + k * NR;
         if (li >= n) continue;
         const int code = L.ncode[li];
         if (code >= 0) {
@@ -1058,7 +1064,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     const uint64_t mgX = P.div_X;
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-        const int li = tid + k * NT;
+        const int li = lane_slot + k * NR;
         if (li >= n) continue;
         Agent<RM, XM>& a = ag[k];
 #pragma unroll
@@ -1140,7 +1146,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             int64_t mine = 0;
 #pragma unroll
             for (int k = 0; k < APT; ++k) {
-                const int li = tid + k * NT;
+                const int li = lane_slot + k * NR;
                 if (li >= n) continue;
                 Agent<RM, XM>& a = ag[k];
                 int64_t C = (int64_t)a.coin_inv + a.coin_esc;
@@ -1154,7 +1160,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             const int64_t share = pool / n, rem = pool % n;
 #pragma unroll
             for (int k = 0; k < APT; ++k) {
-                const int li = tid + k * NT;
+                const int li = lane_slot + k * NR;
                 if (li >= n) continue;
                 int64_t rot = (((int64_t)li - period) % n + n) % n;
                 ag[k].coin_inv += (int32_t)(share + (rot < rem ? 1 : 0));
@@ -1170,7 +1176,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     lds_barrier();
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-        const int li = tid + k * NT;
+        const int li = lane_slot + k * NR;
         if (li >= n) continue;
         const int64_t C = (int64_t)ag[k].coin_inv + ag[k].coin_esc;
         const double u1 = utility(C, ag[k].labor, P.eta);
@@ -1196,13 +1202,13 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         if (tid < K) L.rates[tid] = 0;
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
-            const int li = tid + k * NT;
+            const int li = lane_slot + k * NR;
             if (li < n) reset_agent(P, e, ep_next, li, ag[k]);
         }
     }
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-        const int li = tid + k * NT;
+        const int li = lane_slot + k * NR;
         if (li >= n) continue;
         store_agent(P, S, off + li, ag[k], done);  // skills are redrawn only at a reset
         done_out[row0 + li] = done ? 1 : 0;
@@ -1239,7 +1245,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         for (int c = c_own + tid; c < dw; c += NT) L.tmpl[c] = obs_shared_word(P, L, c, t_next);
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-        const int li = tid + k * NT;
+        const int li = lane_slot + k * NR;
         if (li >= n) continue;
         if (staged) {  // separate calls keep the LDS and global address spaces apart
             if (obs) write_obs_own_words(P, L, ag[k], t_next, so + li * os);
@@ -1490,6 +1496,8 @@ struct ej_env {
     int32_t* d_order = nullptr;
     int mode = 0, persistent_wg = 0;  // mode 0: one workgroup per economy; 1: persistent work queue
     size_t lds = 0;
+    int step_NT = 64;      // workgroup size of the step: ceil(N / apw) waves
+    size_t step_lds = 0;
     EnvState state() const
     {
         return EnvState{d_field, d_t, d_ep, d_rates, d_n, d_off, d_row, d_invalid, d_ug, d_u, d_queue, d_order, E};
@@ -1505,6 +1513,21 @@ static int choose_launch(ej_env* h, int apt)
     h->APT = apt;
     h->NT = nt;
     h->lds = lds_layout(h->P, nt * apt, nullptr, nullptr);
+    h->P.apw = 64;
+    h->step_NT = h->NT;
+    h->step_lds = h->lds;
+    return EJ_OK;
+}
+
+// step workgroup for `apw` agents per wavefront: ceil(N / apw) waves
+static int choose_step_shape(ej_env* h, int apw)
+{
+    if (apw != 64 && apw != 32 && apw != 16) return EJ_EINVAL;
+    const int waves = (h->P.N + apw - 1) / apw;
+    if (waves * 64 > 1024) return EJ_EUNSUPPORTED;
+    h->P.apw = apw;
+    h->step_NT = waves * 64;
+    h->step_lds = lds_layout(h->P, waves * apw * h->APT, nullptr, nullptr);
     return EJ_OK;
 }
 
@@ -1685,6 +1708,7 @@ int ej_env_dims(const ej_env* h, ej_env_dims_t* out)
     out->D_stride = h->P.Ds;
     out->D_gov = h->P.Dg;
     out->K = h->P.K;
+    out->E = h->E;
     return EJ_OK;
 }
 
@@ -1719,21 +1743,23 @@ int ej_env_step_range(ej_env* h, int32_t e_begin, int32_t e_end, const int32_t* 
     if (h->P.K > 0 && !d_gov && !h->P.gov_draw) return EJ_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     EnvState S = h->state();
-#define EJ_STEP_LAUNCH(KERNEL, G)                                                                           \
-    do {                                                                                                    \
-        const bool small = h->NT <= 256;                                                                    \
-        if (h->variant == 0 && small)                                                                       \
-            KERNEL<4, 16, 1, 256><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done,  \
-                                                            d_obs, d_mask, e_begin);                        \
-        else if (h->variant == 0)                                                                           \
-            KERNEL<4, 16, 1, 1024><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, \
-                                                             d_obs, d_mask, e_begin);                       \
-        else if (small)                                                                                     \
-            KERNEL<8, 32, 1, 256><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done,  \
-                                                            d_obs, d_mask, e_begin);                        \
-        else                                                                                                \
-            KERNEL<8, 32, 1, 1024><<<G, h->NT, h->lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, \
-                                                             d_obs, d_mask, e_begin);                       \
+#define EJ_STEP_LAUNCH(KERNEL, G)                                                                            \
+    do {                                                                                                     \
+        const int nt = h->step_NT;                                                                           \
+        const size_t lds = h->step_lds;                                                                      \
+        const bool small = nt <= 256;                                                                        \
+        if (h->variant == 0 && small)                                                                        \
+            KERNEL<4, 16, 1, 256><<<G, nt, lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs,  \
+                                                      d_mask, e_begin);                                      \
+        else if (h->variant == 0)                                                                            \
+            KERNEL<4, 16, 1, 1024><<<G, nt, lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs, \
+                                                       d_mask, e_begin);                                     \
+        else if (small)                                                                                      \
+            KERNEL<8, 32, 1, 256><<<G, nt, lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs,  \
+                                                      d_mask, e_begin);                                      \
+        else                                                                                                 \
+            KERNEL<8, 32, 1, 1024><<<G, nt, lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs, \
+                                                       d_mask, e_begin);                                     \
     } while (0)
     if (h->mode == 1 && whole) {
         const unsigned G = (unsigned)h->persistent_wg;
@@ -1767,6 +1793,12 @@ int ej_env_set_launch(ej_env* h, int32_t mode, int32_t workgroups)
     }
     h->mode = mode;
     return EJ_OK;
+}
+
+int ej_env_set_agents_per_wave(ej_env* h, int32_t agents_per_wave)
+{
+    if (!h) return EJ_EINVAL;
+    return choose_step_shape(h, agents_per_wave);
 }
 
 int ej_env_observe(ej_env* h, uint16_t* d_obs, uint32_t* d_mask, float* d_gov_obs, void* stream)
@@ -1917,3 +1949,162 @@ int ej_env_status(ej_env* h, int64_t* h_invalid_actions, int64_t* h_invalid_gov,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuner: launch shapes of the rollout kernels, timed with HIP events
+// ---------------------------------------------------------------------------
+namespace {
+
+// device copies of everything a trial step changes: the handle's state and
+// the caller's per-step buffers; restored afterwards so tuning changes no result
+struct Snapshot {
+    struct Piece {
+        void* dst;
+        void* save;
+        size_t bytes;
+    };
+    std::vector<Piece> pieces;
+    hipStream_t st = nullptr;
+
+    int add(void* p, size_t bytes)
+    {
+        if (!p || bytes == 0) return EJ_OK;
+        void* save = nullptr;
+        if (hipMalloc(&save, bytes) != hipSuccess) return EJ_ENOMEM;
+        pieces.push_back({p, save, bytes});
+        EJ_HIP(hipMemcpyAsync(save, p, bytes, hipMemcpyDeviceToDevice, st));
+        return EJ_OK;
+    }
+    int restore()
+    {
+        for (auto& q : pieces) EJ_HIP(hipMemcpyAsync(q.dst, q.save, q.bytes, hipMemcpyDeviceToDevice, st));
+        return EJ_OK;
+    }
+    ~Snapshot()
+    {
+        (void)hipStreamSynchronize(st);
+        for (auto& q : pieces) (void)hipFree(q.save);
+    }
+};
+
+template <typename F>
+static int time_launches(F&& launch, int reps, hipStream_t st, float* ms)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    EJ_HIP(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return EJ_EHIP;
+    }
+    int rc = launch();  // warm-up (first use of a shape)
+    if (rc == EJ_OK && hipEventRecord(a, st) != hipSuccess) rc = EJ_EHIP;
+    for (int i = 0; i < reps && rc == EJ_OK; ++i) rc = launch();
+    if (rc == EJ_OK && hipEventRecord(b, st) != hipSuccess) rc = EJ_EHIP;
+    if (rc == EJ_OK && hipEventSynchronize(b) != hipSuccess) rc = EJ_EHIP;
+    float t = 0.f;
+    if (rc == EJ_OK && hipEventElapsedTime(&t, a, b) != hipSuccess) rc = EJ_EHIP;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = t / (float)reps;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int ej_autotune(ej_env* h, ej_mlp_desc* m, const float* d_params, const uint16_t* d_work,
+                           uint16_t* d_obs, uint32_t* d_mask, int32_t* d_act, const int32_t* d_gov, float* d_logp,
+                           float* d_val, float* d_ent, float* d_rew, float* d_gov_rew, uint8_t* d_done, int32_t reps,
+                           ej_autotune_result* out, void* stream)
+{
+    if (!out || !h || reps <= 0) return EJ_EINVAL;
+    if (!d_obs || !d_mask || !d_act || !d_rew || !d_gov_rew || !d_done) return EJ_EINVAL;
+    if (m && (!d_params || !d_work || !d_logp || !d_val || !d_ent)) return EJ_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    std::memset(out, 0, sizeof(*out));
+    const EnvParams& P = h->P;
+    const size_t slots = (size_t)P.Ntot, E = (size_t)h->E, M = (size_t)h->M;
+    const size_t kk = (size_t)(P.K > 0 ? P.K : 1);
+    int rc = EJ_OK;
+    {
+        Snapshot snap;  // everything a trial launch changes; restored below
+        snap.st = st;
+        if ((rc = snap.add(h->d_field, (size_t)n_fields(P.R, P.X) * slots * 4)) != EJ_OK ||
+            (rc = snap.add(h->d_t, 4 * E)) != EJ_OK || (rc = snap.add(h->d_ep, 4 * E)) != EJ_OK ||
+            (rc = snap.add(h->d_rates, 4 * E * kk)) != EJ_OK || (rc = snap.add(h->d_invalid, 16 * E)) != EJ_OK ||
+            (rc = snap.add(h->d_ug, 8 * E)) != EJ_OK || (rc = snap.add(h->d_u, 8 * slots)) != EJ_OK ||
+            (rc = snap.add(d_obs, 2 * M * (size_t)P.Ds)) != EJ_OK ||
+            (rc = snap.add(d_mask, 4 * M * (size_t)P.W)) != EJ_OK || (rc = snap.add(d_act, 4 * M)) != EJ_OK ||
+            (rc = snap.add(d_rew, 4 * M)) != EJ_OK || (rc = snap.add(d_gov_rew, 4 * E)) != EJ_OK ||
+            (rc = snap.add(d_done, M)) != EJ_OK)
+            return rc;
+        if (m && ((rc = snap.add(d_logp, 4 * M)) != EJ_OK || (rc = snap.add(d_val, 4 * M)) != EJ_OK ||
+                  (rc = snap.add(d_ent, 4 * M)) != EJ_OK))
+            return rc;
+        int dev = 0, cus = 0;
+        EJ_HIP(hipGetDevice(&dev));
+        EJ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const int old_mode = h->mode, old_wg = h->persistent_wg, old_apw = h->P.apw;
+        float best = 3.4e38f;
+        int bmode = old_mode, bwg = old_wg, bapw = old_apw;
+        const int apws[3] = {64, 32, 16};
+        const int wgs[4] = {0, cus, 2 * cus, 4 * cus};
+        for (int ai = 0; ai < 3 && rc == EJ_OK; ++ai) {
+            if (choose_step_shape(h, apws[ai]) != EJ_OK) continue;  // more than 16 waves per economy
+            for (int wi = 0; wi < 4 && rc == EJ_OK; ++wi) {
+                const int mode = wi == 0 ? 0 : 1;
+                if ((rc = ej_env_set_launch(h, mode, wgs[wi])) != EJ_OK) break;
+                float ms = 0.f;
+                rc = time_launches([&] { return ej_env_step(h, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs,
+                                                            d_mask, stream); },
+                                   reps, st, &ms);
+                if (rc != EJ_OK) break;
+                ++out->candidates;
+                if (ms < best) {
+                    best = ms;
+                    bmode = mode;
+                    bwg = h->persistent_wg;
+                    bapw = apws[ai];
+                }
+            }
+        }
+        if (rc != EJ_OK) {
+            bmode = old_mode;
+            bwg = old_wg;
+            bapw = old_apw;
+        }
+        choose_step_shape(h, bapw);
+        h->mode = bmode;
+        h->persistent_wg = bwg;
+        out->env_mode = bmode;
+        out->env_workgroups = bmode == 1 ? bwg : 0;
+        out->agents_per_wave = bapw;
+        out->env_ms = best;
+        if (m && rc == EJ_OK) {
+            const int old_rows = m->tile_rows;
+            float pbest = 3.4e38f;
+            int brows = old_rows;
+            const int cand[2] = {64, 128};
+            for (int ci = 0; ci < 2 && rc == EJ_OK; ++ci) {
+                if (cand[ci] == 128 && m->H > 256) continue;
+                m->tile_rows = cand[ci];
+                float ms = 0.f;
+                rc = time_launches([&] { return ej_policy_forward(m, d_params, d_work, d_obs, d_mask, (int64_t)M, 0, 0,
+                                                                  0, nullptr, d_act, d_logp, d_val, d_ent, nullptr,
+                                                                  stream); },
+                                   reps, st, &ms);
+                if (rc != EJ_OK) break;
+                ++out->candidates;
+                if (ms < pbest) {
+                    pbest = ms;
+                    brows = cand[ci];
+                }
+            }
+            m->tile_rows = rc == EJ_OK ? brows : old_rows;
+            out->policy_tile_rows = m->tile_rows;
+            out->policy_ms = pbest;
+        }
+        const int rc2 = snap.restore();
+        if (rc == EJ_OK) rc = rc2;
+    }  // the snapshot waits for the restore before it frees its copies
+    return rc;
+}

@@ -3,7 +3,8 @@
 Rollout: every step the shared policy samples all agents' actions
 (ej_policy_forward) and the economy step (ej_env_step, which also draws the
 government's uniform tax levels) writes rewards, done flags and the next
-observation and mask straight into the rollout storage.  Update: GAE (ej_gae), then epochs x
+observation and mask straight into the rollout storage; the library captures
+the whole rollout as one HIP graph (ej_rollout_capture).  Update: GAE (ej_gae), then epochs x
 minibatches of the hand-written backward (ej_ppo_backward) and Adam
 (ej_adam), with the bf16 work copy refreshed after every step
 (ej_mlp_sync_weights).  Table 2 of the paper lists the PPO settings; the
@@ -21,42 +22,6 @@ import numpy as np
 import torch
 
 from . import binding
-
-
-def economy_groups(env, groups: int):
-    """Split the economies into `groups` contiguous ranges:
-    [(e_begin, e_end, row_begin, row_end)] (rows from the env's row offsets)."""
-    E = env.E
-    groups = max(1, min(int(groups), E))
-    out = []
-    for g in range(groups):
-        e0, e1 = E * g // groups, E * (g + 1) // groups
-        out.append((e0, e1, int(env.row_offsets[e0]), int(env.row_offsets[e1])))
-    return out
-
-
-class GroupStreams:
-    """One stream per economy group (default priority).  Economies never
-    interact, so each group's policy -> step chain runs on its own stream and
-    one group's policy overlaps another's economy step.  fork() / join()
-    order the streams after / before the current stream's work (also inside
-    graph capture)."""
-
-    def __init__(self, n: int):
-        self.streams = [torch.cuda.Stream() for _ in range(n)] if n > 1 else []
-
-    def fork(self):
-        cur = torch.cuda.current_stream()
-        for st in self.streams:
-            st.wait_stream(cur)
-
-    def join(self):
-        cur = torch.cuda.current_stream()
-        for st in self.streams:
-            cur.wait_stream(st)
-
-    def stream(self, g: int):
-        return torch.cuda.stream(self.streams[g]) if self.streams else torch.cuda.stream(torch.cuda.current_stream())
 
 
 class PPOLoss(torch.autograd.Function):
@@ -79,9 +44,10 @@ class PPOLoss(torch.autograd.Function):
 
 
 class RolloutStorage:
-    def __init__(self, T: int, M: int, Ds: int, W: int, device="cuda"):
+    def __init__(self, T: int, M: int, Ds: int, W: int, E: int, device="cuda"):
         self.T, self.M = T, M
         z = dict(device=device)
+        self.gov_rew = torch.zeros((T, E), **z)
         self.obs = torch.zeros((T + 1, M, Ds), dtype=torch.int16, **z)  # obs[T] = the state after the rollout
         self.mask = torch.zeros((T + 1, M, W), dtype=torch.int32, **z)
         self.act = torch.zeros((T, M), dtype=torch.int32, **z)
@@ -93,8 +59,13 @@ class RolloutStorage:
         self.adv = torch.zeros((T, M), **z)
         self.ret = torch.zeros((T, M), **z)
         self.last_val = torch.zeros(M, **z)
-        self.scratch_act = torch.zeros(M, dtype=torch.int32, **z)
-        self.scratch = torch.zeros((2, M), **z)
+        self.tmp = torch.zeros(3 * M, **z)  # discarded outputs of the last-value forward
+
+    def buffers(self, ctr) -> dict:
+        """The arrays ej_rollout_capture writes (the graph keeps them)."""
+        return dict(obs=self.obs, mask=self.mask, act=self.act, logp=self.logp, val=self.val, ent=self.ent,
+                    rew=self.rew, done=self.done, gov_rew=self.gov_rew, last_val=self.last_val, adv=self.adv,
+                    ret=self.ret, tmp=self.tmp, ctr=ctr)
 
     def flat(self) -> dict:
         T, M = self.T, self.M
@@ -120,9 +91,7 @@ class PPOTrainer:
         self.hp = dict(clip=clip, vclip=vclip, vf_coef=vf_coef, ent_coef=ent_coef)
         self.seed = seed
         self.total_updates = total_updates
-        self.store = RolloutStorage(rollout, self.M, self.Ds, self.Wm)
-        self.gov = torch.zeros(max(e.E * e.K, 1), dtype=torch.int32, device="cuda")
-        self.gov_rew = torch.zeros(e.E, device="cuda")
+        self.store = RolloutStorage(rollout, self.M, self.Ds, self.Wm, e.E)
         n = self.mlp.layout["n_params"]
         self.grads = torch.zeros(n, device="cuda")
         self.adam_m = torch.zeros(n, device="cuda")
@@ -137,55 +106,24 @@ class PPOTrainer:
         self.ctr_base = torch.zeros(1, dtype=torch.int64, device="cuda")
         self.updates = 0
         self.adam_step = 0
-        self.graph = None
-        self.groups = economy_groups(self.env, groups)  # rollout pipelined over economy groups
-        self.group_streams = GroupStreams(len(self.groups))
         self.env.set_gov_draw(True, seed + 1)
         self.env.observe(self.store.obs[0], self.store.mask[0])
+        # the whole rollout as one HIP graph captured by the library, the
+        # economies pipelined over `groups` streams
+        self.rollout = binding.Rollout(self.env, self.mlp, self.store.buffers(self.ctr_base), rollout, seed,
+                                       groups=groups, last_value=True, gamma=gamma, lam=lam)
 
     # ---- rollout ----
-    def rollout_step(self, t: int):
-        """Policy and economy step for every group (the government's uniform
-        levels are drawn inside the step, seed + 1).  A group's rows are a
-        slice of the batch; row_base keeps the sampler's row numbering, so
-        any grouping gives the same rollout."""
-        s = self.store
-        for g, (e0, e1, r0, r1) in enumerate(self.groups):
-            with self.group_streams.stream(g):
-                self.mlp.forward(s.obs[t][r0:r1], s.mask[t][r0:r1], r1 - r0, self.seed, t, s.act[t][r0:r1],
-                                 s.logp[t][r0:r1], s.val[t][r0:r1], s.ent[t][r0:r1], ctr_base=self.ctr_base,
-                                 row_base=r0)
-                self.env.step(s.act[t], None, s.rew[t], self.gov_rew, s.done[t], s.obs[t + 1], s.mask[t + 1],
-                              economies=(e0, e1))
-
-    def _collect_launches(self):
-        self.group_streams.fork()
-        for t in range(self.T):
-            self.rollout_step(t)
-        self.group_streams.join()
-        s = self.store
-        self.mlp.forward(s.obs[self.T], s.mask[self.T], self.M, self.seed, self.T, s.scratch_act, s.scratch[0],
-                         s.last_val, s.scratch[1], ctr_base=self.ctr_base)
-        binding.gae(s.rew, s.val, s.done, s.last_val, self.T, self.M, self.gamma, self.lam, s.adv, s.ret)
-        binding.counter_add(self.ctr_base, self.T + 1)
-
     def collect(self, graph: bool = False):
-        """One rollout of T steps, then GAE.  graph=True replays the whole
-        rollout as one captured HIP graph (captured on first use; the kernels
-        must have run once before, so the first call with graph=True runs the
-        plain launches and captures afterwards)."""
-        if not graph:
-            self._collect_launches()
-            return
-        if self.graph is None:
-            self._collect_launches()
-            torch.cuda.synchronize()
-            # record the rollout for the following calls (capture executes nothing)
-            self.graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(self.graph):
-                self._collect_launches()
+        """One rollout of T steps (policy forward and economy step of every
+        group per step; the government's uniform levels are drawn inside the
+        step, seed + 1), the last value and GAE.  graph=True replays the
+        captured HIP graph; graph=False issues the same launches one by one
+        (identical results)."""
+        if graph:
+            self.rollout.launch()
         else:
-            self.graph.replay()
+            self.rollout.launch_plain()
 
     # ---- update ----
     def schedules(self):
@@ -216,4 +154,5 @@ class PPOTrainer:
         self.store.mask[0].copy_(self.store.mask[self.T])
 
     def close(self):
+        self.rollout.close()
         self.env.close()

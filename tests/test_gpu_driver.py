@@ -144,7 +144,7 @@ def test_graph_rollout_equals_plain_launches():
         a.collect(graph=False)
         b.collect(graph=True)
         torch.cuda.synchronize()
-        for name in ("obs", "mask", "act", "logp", "val", "rew", "done", "adv", "ret"):
+        for name in ("obs", "mask", "act", "logp", "val", "ent", "rew", "done", "gov_rew", "adv", "ret", "last_val"):
             assert torch.equal(getattr(a.store, name), getattr(b.store, name)), (k, name)
         a.next_rollout()
         b.next_rollout()
@@ -257,3 +257,134 @@ def test_env_step_rejects_misaligned_observations():
     after = env.env_state(env.get_state(), 0)
     assert before["t"] == after["t"]
     env.close()
+
+
+def test_agents_per_wavefront_variants_are_bit_identical():
+    """64, 32 and 16 agents per wavefront (ceil(n / apw) waves per economy,
+    idle lanes beyond apw) give the same state, rewards, observations and
+    masks, with uneven populations, over an episode end; each variant also
+    in the persistent launch."""
+    import torch
+    from paper_2410_22165_amd import binding
+    cfg = W.env_config(E=9, N=150, R=3, P=12, X=6, P_tax=8, K=5, T=30, seed=6)
+    ns = W.uneven_populations(9, 1, 150, seed=2)
+    shapes = [(64, 0), (32, 0), (16, 0), (16, 1), (32, 1)]
+    envs = [binding.Env(cfg, W.obs_scales(cfg), ns) for _ in shapes]
+    for e, (apw, mode) in zip(envs, shapes):
+        print(f"[gpu] agents per wave {apw} launch mode {mode}", flush=True)
+        e.set_agents_per_wave(apw)
+        e.set_launch(mode, 4)
+    bufs = [e.buffers() for e in envs]
+    for step in range(40):
+        for e, b in zip(envs, bufs):
+            e.random_actions(3, b["act"], b["gov"])
+            e.step(b["act"], b["gov"], b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
+        torch.cuda.synchronize()
+        for i in range(1, len(envs)):
+            for k in ("rew", "gov_rew", "done", "obs", "mask"):
+                assert torch.equal(bufs[0][k], bufs[i][k]), (step, shapes[i], k)
+    s0 = envs[0].get_state()
+    for e in envs[1:]:
+        si = e.get_state()
+        for k in s0:
+            assert np.array_equal(s0[k], si[k]), k
+    with pytest.raises(binding.EconError):
+        envs[0].set_agents_per_wave(48)
+    big = binding.Env(W.env_config(E=1, N=1000, R=2, P=4, X=4, P_tax=5, K=2, T=10), W.obs_scales(cfg))
+    with pytest.raises(binding.EconError):  # 63 waves: more than one workgroup holds
+        big.set_agents_per_wave(16)
+    big.close()
+    for e in envs:
+        e.close()
+
+
+def test_autotune_restores_state_and_buffers():
+    """ej_autotune times every launch shape (economy modes x agents per
+    wavefront, policy row tiles) and applies the fastest; the economy state,
+    its rejection counters and every buffer a trial step writes are as they
+    were, so the following steps equal those of an untuned economy."""
+    import torch
+    from paper_2410_22165_amd import binding
+    cfg = W.env_config(E=40, N=100, R=3, P=20, X=10, P_tax=10, K=7, T=50, seed=4)
+    envs = [binding.Env(cfg, W.obs_scales(cfg)) for _ in range(2)]
+    mlps = [binding.Mlp(e.D, e.Ds, 64, e.A, W.policy_weights(e.D, 64, e.A, seed=1)) for e in envs]
+    bufs = [e.buffers() for e in envs]
+    outs = []
+    for e, b in zip(envs, bufs):
+        e.set_gov_draw(True, 5)
+        outs.append(dict(act=torch.zeros(e.M, dtype=torch.int32, device="cuda"),
+                         logp=torch.zeros(e.M, device="cuda"), val=torch.zeros(e.M, device="cuda"),
+                         ent=torch.zeros(e.M, device="cuda")))
+    for e, m, b, o in zip(envs, mlps, bufs, outs):
+        e.observe(b["obs"], b["mask"])
+        for t in range(7):
+            m.forward(b["obs"], b["mask"], e.M, 2, t, o["act"], o["logp"], o["val"], o["ent"])
+            e.step(o["act"], None, b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
+    torch.cuda.synchronize()
+    before = {k: v.clone() for k, v in dict(bufs[1], **outs[1]).items()}
+    st_before = envs[1].get_state()
+    stat_before = envs[1].status()
+    res = binding.autotune(envs[1], mlps[1], dict(obs=bufs[1]["obs"], mask=bufs[1]["mask"], rew=bufs[1]["rew"],
+                                                  gov_rew=bufs[1]["gov_rew"], done=bufs[1]["done"], **outs[1]))
+    torch.cuda.synchronize()
+    print("[gpu] autotune", res, flush=True)
+    assert res["candidates"] >= 12 + 2
+    assert res["agents_per_wave"] in (64, 32, 16) and res["policy_tile_rows"] in (64, 128)
+    for k, v in before.items():
+        assert torch.equal(v, dict(bufs[1], **outs[1])[k]), k
+    st_after = envs[1].get_state()
+    for k in st_before:
+        assert np.array_equal(st_before[k], st_after[k]), k
+    assert envs[1].status() == stat_before
+    for t in range(7, 30):
+        for e, m, b, o in zip(envs, mlps, bufs, outs):
+            m.forward(b["obs"], b["mask"], e.M, 2, t, o["act"], o["logp"], o["val"], o["ent"])
+            e.step(o["act"], None, b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
+        torch.cuda.synchronize()
+        for k in ("rew", "gov_rew", "done", "obs", "mask"):
+            assert torch.equal(bufs[0][k], bufs[1][k]), (t, k)
+        assert torch.equal(outs[0]["act"], outs[1]["act"]), t
+    for e in envs:
+        e.close()
+
+
+def test_library_rollout_graph_with_carry_equals_host_loop():
+    """ej_rollout_capture with carry (each launch continues from the last,
+    no last value): two replays of a 9-step graph in 3 groups give exactly
+    the economy and the actions of 18 policy + step calls issued from the
+    host on one buffer."""
+    import torch
+    from paper_2410_22165_amd import binding
+    cfg = W.env_config(E=11, N=40, R=3, P=6, X=4, P_tax=5, K=3, T=12, seed=8)
+    envs = [binding.Env(cfg, W.obs_scales(cfg)) for _ in range(2)]
+    mlps = [binding.Mlp(e.D, e.Ds, 128, e.A, W.policy_weights(e.D, 128, e.A, seed=3)) for e in envs]
+    for e in envs:
+        e.set_gov_draw(True, 7)
+    T = 9
+    st = binding.rollout_storage(envs[0], T)
+    r = binding.Rollout(envs[0], mlps[0], st, T, seed=4, groups=3, last_value=False, carry=True)
+    b = envs[1].buffers()
+    o = dict(act=torch.zeros(envs[1].M, dtype=torch.int32, device="cuda"), logp=torch.zeros(envs[1].M, device="cuda"),
+             val=torch.zeros(envs[1].M, device="cuda"), ent=torch.zeros(envs[1].M, device="cuda"))
+    ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    envs[1].observe(b["obs"], b["mask"])
+    for k in range(2):
+        r.launch()
+        acts = []
+        for t in range(T):
+            mlps[1].forward(b["obs"], b["mask"], envs[1].M, 4, t, o["act"], o["logp"], o["val"], o["ent"],
+                            ctr_base=ctr)
+            envs[1].step(o["act"], None, b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
+            acts.append(o["act"].clone())
+        binding.counter_add(ctr, T + 1)
+        torch.cuda.synchronize()
+        for t in range(T):
+            assert torch.equal(st["act"][t], acts[t]), (k, t)
+        assert torch.equal(st["obs"][0], b["obs"]) and torch.equal(st["mask"][0], b["mask"]), k
+        assert torch.equal(st["rew"][T - 1], b["rew"]) and torch.equal(st["gov_rew"][T - 1], b["gov_rew"]), k
+    s0, s1 = envs[0].get_state(), envs[1].get_state()
+    for k in s0:
+        assert np.array_equal(s0[k], s1[k]), k
+    r.close()
+    for e in envs:
+        e.close()
