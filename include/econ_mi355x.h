@@ -98,6 +98,7 @@ typedef struct ej_env_dims_t {
     int32_t D_gov;      /* government observation floats: 3 (3 + R) + K + 1 + 4 R */
     int32_t K;          /* government action entries per economy */
     int32_t E;          /* economies */
+    int32_t D_metrics;  /* doubles per economy in ej_env_episode_metrics: 5 R + 9 */
 } ej_env_dims_t;
 
 typedef struct ej_env ej_env;
@@ -182,6 +183,29 @@ int ej_env_set_launch(ej_env* env, int32_t mode, int32_t workgroups);
  * more waves (ceil(n / apw) waves; at most 16).  Results are identical for
  * every value.  EJ_EUNSUPPORTED when N needs more than 16 waves. */
 int ej_env_set_agents_per_wave(ej_env* env, int32_t agents_per_wave);
+
+/* Episode statistics, the measures the paper reports at the end of an
+ * episode (Sec. 4 results; Figs. 2, 3 and 6): enabled = 1 makes every
+ * following step count, per economy, the actions taken by category and the
+ * trades and their prices per resource, and at each episode end write the
+ * economy's record.  Allocates the counters on first use (counts start at
+ * the next step); 0 stops counting.  Rewards and state are unchanged. */
+int ej_env_enable_metrics(ej_env* env, int32_t enabled);
+
+/* Record of the last completed episode of every economy -> d_out
+ * [E * (5 R + 9)] doubles, economy-major:
+ *   [0] index of that episode (-1: none completed since enabling)
+ *   [1] productivity Prod = sum_i C_i at its end (Eq. (5))
+ *   [2] equality 1 - gini(C)
+ *   [3] government utility Eq * Prod (Eqs. (3), (4))
+ *   [4] mean and [5] lower median over the population of the episode
+ *       return, the sum of an agent's rewards = its utility at the end
+ *       minus its utility at the reset state (Eq. (2))
+ *   [6 + j] actions of category j: 0 NOOP, 1 + r gather r, 1 + R craft,
+ *       2 + R + r buy r, 2 + 2R + r sell r, 2 + 3R rejected (became NOOP)
+ *   [9 + 3R + r] trades of resource r, [9 + 4R + r] the sum of their prices
+ * EJ_EINVAL unless ej_env_enable_metrics was called. */
+int ej_env_episode_metrics(ej_env* env, double* d_out, void* stream);
 
 /* Government levels drawn by the step itself (ej_env_step with d_gov = NULL):
  * uniform over 0..20, exactly the levels ej_env_random_actions(env, seed, ...)

@@ -66,6 +66,10 @@ typedef struct {
     oc_order* book;
     int32_t n_book, cap_book;
     int64_t invalid_actions, invalid_gov;
+    /* episode statistics: counts of this episode so far and the record of
+     * the last completed one (layout at oc_env_episode_metrics) */
+    int64_t macc[5 * OC_MAXR + 3];
+    double mlast[5 * OC_MAXR + 9];
 } oc_env;
 
 /* ---------------------------------------------------------------------------
@@ -206,6 +210,7 @@ static void reset_episode_state(oc_env* env)
         }
     }
     env->n_book = 0;
+    for (int j = 0; j < 5 * OC_MAXR + 3; ++j) env->macc[j] = 0;
 }
 
 oc_env* oc_env_create(const oc_config* cfg, uint64_t seed, int32_t e)
@@ -228,6 +233,8 @@ oc_env* oc_env_create(const oc_config* cfg, uint64_t seed, int32_t e)
     env->book = (oc_order*)calloc((size_t)env->cap_book, sizeof(oc_order));
     env->ep = 0;
     reset_episode_state(env);
+    for (int j = 0; j < 5 * OC_MAXR + 9; ++j) env->mlast[j] = 0.0;
+    env->mlast[0] = -1.0;
     return env;
 }
 
@@ -369,6 +376,59 @@ static void remove_order(oc_env* env, int32_t j)
  *   redistribution at the last step of a period; rewards; time advance with
  *   automatic reset at the episode end.
  * ------------------------------------------------------------------------- */
+/* ---------------------------------------------------------------------------
+ * Episode statistics, the measures the paper reports at the end of an
+ * episode (Sec. 4 results): productivity (Eq. (5)), equality 1 - gini, the
+ * government utility Eq * Prod (Eq. (3)), the mean and median episode
+ * return of the population, the distribution of actions taken and the
+ * trades and their prices per resource.  The return of an agent over an
+ * episode is the sum of its rewards, i.e. (Eq. (2) telescopes) its utility
+ * at the end minus its utility at the reset state.
+ * Record (doubles): [0] index of the episode, [1] Prod, [2] 1 - gini,
+ * [3] Eq * Prod, [4] mean return, [5] lower median return, [6 + j] actions of
+ * category j (j = 0 NOOP, 1 + r gather r, 1 + R craft, 2 + R + r buy r,
+ * 2 + 2R + r sell r, 2 + 3R rejected), [9 + 3R + r] trades of resource r,
+ * [9 + 4R + r] the sum of their prices.
+ * ------------------------------------------------------------------------- */
+static int cmp_f64(const void* a, const void* b)
+{
+    double x = *(const double*)a, y = *(const double*)b;
+    return (x > y) - (x < y);
+}
+
+static void episode_record(oc_env* env, const int64_t* coins, double ug)
+{
+    const oc_config* c = &env->c;
+    const int32_t N = c->N, R = c->R;
+    int64_t prod = 0;
+    for (int32_t i = 0; i < N; ++i) prod += coins[i];
+    double gini = prod > 0 ? (double)oc_gini_numerator(coins, N) / ((double)N * (double)prod) : 0.0;
+    double u_start = oc_utility(c->start_coin, 0, c->eta);
+    double* ret = (double*)malloc(sizeof(double) * (size_t)N);
+    double sum = 0.0;
+    for (int32_t i = 0; i < N; ++i) {
+        ret[i] = oc_utility(coins[i], env->labor[i], c->eta) - u_start;
+        sum += ret[i];
+    }
+    qsort(ret, (size_t)N, sizeof(double), cmp_f64);
+    double* m = env->mlast;
+    m[0] = (double)env->ep;
+    m[1] = (double)prod;
+    m[2] = 1.0 - gini;
+    m[3] = ug;
+    m[4] = sum / (double)N;
+    m[5] = ret[(N - 1) / 2];
+    for (int32_t j = 0; j < 5 * R + 3; ++j) m[6 + j] = (double)env->macc[j];
+    free(ret);
+}
+
+int32_t oc_metrics_len(int32_t R) { return 5 * R + 9; }
+
+void oc_env_episode_metrics(const oc_env* env, double* out)
+{
+    memcpy(out, env->mlast, sizeof(double) * (size_t)oc_metrics_len(env->c.R));
+}
+
 int32_t oc_env_step(oc_env* env, const int32_t* act, const int32_t* gov, float* rew, float* gov_rew,
                     int32_t* done)
 {
@@ -385,10 +445,21 @@ int32_t oc_env_step(oc_env* env, const int32_t* act, const int32_t* gov, float* 
     }
     double ug0 = oc_social_welfare(coins, N, c->omega);
 
-    /* validation against the step-start state */
+    /* validation against the step-start state; every agent's action is
+     * counted in its category for the episode statistics */
     for (int32_t i = 0; i < N; ++i) {
-        if (action_valid(env, i, act[i])) eff[i] = act[i];
-        else { eff[i] = 0; env->invalid_actions += 1; }
+        if (action_valid(env, i, act[i])) {
+            int32_t type, r, p;
+            eff[i] = act[i];
+            decode(c, eff[i], &type, &r, &p);
+            int32_t cat = type == A_NOOP ? 0 : type == A_GATHER ? 1 + r : type == A_CRAFT ? 1 + R
+                          : type == A_BUY ? 2 + R + r : 2 + 2 * R + r;
+            env->macc[cat] += 1;
+        } else {
+            eff[i] = 0;
+            env->invalid_actions += 1;
+            env->macc[2 + 3 * R] += 1;
+        }
     }
 
     /* government: new rates at the first step of each period */
@@ -462,6 +533,8 @@ int32_t oc_env_step(oc_env* env, const int32_t* act, const int32_t* gov, float* 
                     env->coin_esc[i] -= c->prices[o->p];
                     env->coin_inv[i] += c->prices[o->p] - paid[j];
                     AG(env->res_inv, o->r, i) += 1;
+                    env->macc[3 + 3 * R + o->r] += 1;        /* one trade, counted on its bid */
+                    env->macc[3 + 4 * R + o->r] += paid[j];  /* at its price */
                 } else { /* seller: escrowed unit leaves, trade price received */
                     AG(env->res_esc, o->r, i) -= 1;
                     env->coin_inv[i] += paid[j];
@@ -527,6 +600,7 @@ int32_t oc_env_step(oc_env* env, const int32_t* act, const int32_t* gov, float* 
     env->t = t + 1;
     *done = 0;
     if (env->t >= c->T) {
+        episode_record(env, coins, ug1);
         *done = 1;
         env->ep += 1;
         reset_episode_state(env);
@@ -703,6 +777,7 @@ void oc_env_set_state(oc_env* env, const int32_t* scalars, const int32_t* coin_i
     memcpy(env->res_esc, res_esc, 4 * (size_t)N * (size_t)R);
     memcpy(env->sg, sg, 4 * (size_t)N * (size_t)R);
     env->n_book = 0;
+    for (int q = 0; q < 5 * OC_MAXR + 3; ++q) env->macc[q] = 0; /* episode-to-date counts unknown */
     for (int32_t i = 0; i < N; ++i) env->n_active[i] = 0;
     for (int32_t s = 0; s < X; ++s) {
         for (int32_t i = 0; i < N; ++i) {

@@ -73,6 +73,9 @@ def lib():
         L.oc_random_actions.argtypes = [C.POINTER(OcConfig), C.c_uint64, C.c_int32, C.c_int32, C.c_int32,
                                         P32, P32]
         L.oc_env_run_random.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]
+        L.oc_metrics_len.argtypes = [C.c_int32]
+        L.oc_metrics_len.restype = C.c_int32
+        L.oc_env_episode_metrics.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -230,6 +233,15 @@ class OracleEnv:
         lib().oc_env_observe(self._h, C.byref(s), stride, _p(obs, C.c_uint16), _p(mask, C.c_uint32),
                              _p(gov, C.c_float) if with_gov else None)
         return obs, mask, gov
+
+    def episode_metrics(self) -> np.ndarray:
+        """Record of the last completed episode (layout in econ_oracle.c:
+        episode, productivity, equality, government utility, mean and median
+        return, action counts per category, trades and price sums per
+        resource)."""
+        out = np.zeros(lib().oc_metrics_len(self.R), np.float64)
+        lib().oc_env_episode_metrics(self._h, _p(out, C.c_double))
+        return out
 
     def invalid_counts(self):
         return int(lib().oc_env_invalid_actions(self._h)), int(lib().oc_env_invalid_gov(self._h))

@@ -34,7 +34,8 @@ class EjEnvConfig(C.Structure):
 
 class EjEnvDims(C.Structure):
     _fields_ = [("M", C.c_int64), ("A", C.c_int32), ("mask_words", C.c_int32), ("D", C.c_int32),
-                ("D_stride", C.c_int32), ("D_gov", C.c_int32), ("K", C.c_int32), ("E", C.c_int32)]
+                ("D_stride", C.c_int32), ("D_gov", C.c_int32), ("K", C.c_int32), ("E", C.c_int32),
+                ("D_metrics", C.c_int32)]
 
 
 _STATE_FIELDS = ("t", "ep", "rates", "coin_inv", "coin_esc", "labor", "snap", "sc", "res_inv", "res_esc", "sg",
@@ -114,6 +115,8 @@ def lib():
     L.ej_env_set_launch.argtypes = [vp, i32, i32]
     L.ej_env_set_gov_draw.argtypes = [vp, i32, C.c_uint64]
     L.ej_env_set_agents_per_wave.argtypes = [vp, i32]
+    L.ej_env_enable_metrics.argtypes = [vp, i32]
+    L.ej_env_episode_metrics.argtypes = [vp, vp, vp]
     _declare_learner(L)
     _lib = L
     return L
@@ -254,6 +257,18 @@ class Env:
     def random_actions(self, act_seed: int, act, gov, stream=None):
         check(lib().ej_env_random_actions(self._h, act_seed, ptr(act), ptr(gov), stream_ptr(stream)),
               "ej_env_random_actions")
+
+    def enable_metrics(self, enabled: bool = True):
+        check(lib().ej_env_enable_metrics(self._h, 1 if enabled else 0), "ej_env_enable_metrics")
+
+    def episode_metrics(self, out=None, stream=None):
+        """[E, 5 R + 9] float64 device tensor: every economy's record of its
+        last completed episode (layout in the header)."""
+        import torch
+        if out is None:
+            out = torch.zeros((self.E, 5 * self.cfg["R"] + 9), dtype=torch.float64, device="cuda")
+        check(lib().ej_env_episode_metrics(self._h, ptr(out), stream_ptr(stream)), "ej_env_episode_metrics")
+        return out
 
     def set_agents_per_wave(self, apw: int):
         """Agents per wavefront of the step (64, 32 or 16; same results)."""

@@ -44,6 +44,7 @@ struct EnvParams {
     uint64_t div_X, div_P;  // reciprocal multipliers 2^32 / X, 2^32 / P rounded up: j / X = (j div_X) >> 32 for j < 2^27
     int32_t gov_draw;
     int32_t apw;   // agents per wavefront in the step (64, 32 or 16; lanes beyond it idle)
+    int32_t metrics;  // episode statistics accumulated by the step (ej_env_enable_metrics)
     int64_t Ntot;  // stride between two state fields
     int32_t prices[EJ_MAX_P];
     int32_t cutoffs[EJ_MAX_K];
@@ -67,7 +68,14 @@ struct EnvState {
     unsigned int* queue;     // [2]   persistent launch: next queue slot, finished workgroups
     const int32_t* order;    // [E]   persistent launch: economies by decreasing population
     int32_t E;
+    int64_t* macc;           // [E][EJ_NACC] this episode's action counts, trades, price sums
+    double* mlast;           // [E][EJ_NMET] record of the last completed episode
 };
+
+// episode statistics: counts per economy (action categories 3R + 3, trades R,
+// price sums R) and the record layout (6 measures, then those counts)
+constexpr int EJ_NACC = 5 * EJ_MAX_R + 3;
+constexpr int EJ_NMET = EJ_NACC + 6;
 
 // state field indices
 __host__ __device__ inline int F_COIN_INV() { return 0; }
@@ -315,6 +323,31 @@ __device__ inline int64_t block_sum_i64(int64_t v, int64_t* red)
     return tot;
 }
 
+__device__ inline double block_sum_f64(double v, int64_t* red)
+{
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double* dr = (double*)red;
+    v = wave_sum(v);
+    lds_barrier();
+    if (lane_id() == 0) dr[w] = v;
+    lds_barrier();
+    double tot = 0.0;
+    for (int j = 0; j < nw; ++j) tot += dr[j];
+    return tot;
+}
+
+// int64 key with the order of the double (finite values): the sign-magnitude
+// bits of a negative double are flipped so that larger keys are larger values
+__device__ inline int64_t f64_order_key(double d)
+{
+    const int64_t b = __double_as_longlong(d);
+    return b < 0 ? (b ^ 0x7FFFFFFFFFFFFFFFll) : b;
+}
+__device__ inline double f64_from_order_key(int64_t k)
+{
+    return __longlong_as_double(k < 0 ? (k ^ 0x7FFFFFFFFFFFFFFFll) : k);
+}
+
 // three block-wide sums at the cost of one (two barriers); red holds 48 entries
 __device__ inline void block_sum3_i64(int64_t& a, int64_t& b, int64_t& c, int64_t* red)
 {
@@ -454,6 +487,7 @@ struct Lds {
     uint32_t* tmpl;                  // [EJ_MAX_DS / 2] economy-wide words of an observation row
     int64_t* red;                    // [32]
     double* dred;                    // [4]
+    int32_t* met;                    // [EJ_NACC] this step's action counts, trades, price sums
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -481,7 +515,8 @@ __host__ __device__ __forceinline__ size_t lds_layout(const EnvParams& P, int NL
     const size_t o_tmpl = align16(o_misc + 4 * 16);
     const size_t o_red = align16(o_tmpl + 2 * EJ_MAX_DS);
     const size_t o_dred = align16(o_red + 8 * 48);
-    const size_t total = align16(o_dred + 8 * 4);
+    const size_t o_met = align16(o_dred + 8 * 4);
+    const size_t total = align16(o_met + 4 * EJ_NACC);
     if (base) {
         L->hcnt = (int32_t*)(base + o_hcnt);
         L->hmin = (int32_t*)(base + o_hmin);
@@ -501,6 +536,7 @@ __host__ __device__ __forceinline__ size_t lds_layout(const EnvParams& P, int NL
         L->tmpl = (uint32_t*)(base + o_tmpl);
         L->red = (int64_t*)(base + o_red);
         L->dred = (double*)(base + o_dred);
+        L->met = (int32_t*)(base + o_met);
     }
     return total;
 }
@@ -531,7 +567,7 @@ __device__ inline int64_t welfare_key(int64_t C, int li, int n) { return n <= 25
 // `extra` (nullable): one more per-thread count, summed over the block in the
 // same reduction
 __device__ inline double social_welfare_block(const EnvParams& P, const Lds& L, int n, int S2,
-                                              int64_t* extra = nullptr)
+                                              int64_t* extra = nullptr, int64_t* num_sum = nullptr)
 {
     int64_t num = 0, sum = 0;
     if (n <= 256) {
@@ -567,6 +603,10 @@ __device__ inline double social_welfare_block(const EnvParams& P, const Lds& L, 
     int64_t x = extra ? *extra : 0;
     block_sum3_i64(num, sum, x, L.red);
     if (extra) *extra = x;
+    if (num_sum) {
+        num_sum[0] = num;
+        num_sum[1] = sum;
+    }
     double gini = 0.0;
     if (sum > 0) gini = (double)num / ((double)n * (double)sum);
     double eq = (1.0 - P.omega) + P.omega * (1.0 - gini);
@@ -863,6 +903,8 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     }
     for (int j = tid; j < 2 * R * P.P; j += NT) L.nbcnt[j] = 0;
     for (int j = tid; j < S2; j += NT) L.sortbuf[j] = INT64_MAX;
+    if (P.metrics)
+        for (int j = tid; j < 5 * R + 3; j += NT) L.met[j] = 0;
     lds_barrier();
 
     int eff[APT];
@@ -894,8 +936,16 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
         const int li = lane_slot + k * NR;
         if (li >= n) continue;
         const int a = a_in[k];
-        if (action_allowed(P, ag[k], n_active(ag[k], X), a, L.prices)) eff[k] = a;
+        const bool ok = action_allowed(P, ag[k], n_active(ag[k], X), a, L.prices);
+        if (ok) eff[k] = a;
         else ++invalid;
+        if (P.metrics) {  // category of the action taken: NOOP, gather r, craft, buy r, sell r, rejected
+            const Act d = decode_action(P, eff[k]);
+            const int cat = !ok ? 2 + 3 * R
+                                : d.type == 0 ? 0 : d.type == 1 ? 1 + d.r : d.type == 2 ? 1 + R
+                                                                          : (d.type == 3 ? 2 + R : 2 + 2 * R) + d.r;
+            atomicAdd(&L.met[cat], 1);
+        }
     }
 
     // apply every agent's action; new orders go to slot t mod X
@@ -1115,6 +1165,10 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
                 a.coin_esc -= my_price;
                 a.coin_inv += my_price - q;
                 radd(a.res_inv, r, 1);
+                if (P.metrics) {  // the trade, counted on its bid, at price q
+                    atomicAdd(&L.met[3 + 3 * R + r], 1);
+                    atomicAdd(&L.met[3 + 4 * R + r], q);
+                }
             } else {
                 radd(a.res_esc, r, -1);
                 a.coin_inv += q;
@@ -1174,19 +1228,23 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     lds_barrier();
     for (int j = tid; j < S2; j += NT) L.sortbuf[j] = INT64_MAX;
     lds_barrier();
+    double u1v[APT];
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
         const int li = lane_slot + k * NR;
+        u1v[k] = 0.0;
         if (li >= n) continue;
         const int64_t C = (int64_t)ag[k].coin_inv + ag[k].coin_esc;
         const double u1 = utility(C, ag[k].labor, P.eta);
+        u1v[k] = u1;
         rew[row0 + li] = (float)(u1 - u0[k]);
         S.u[off + li] = t + 1 >= P.T ? __builtin_nan("") : u1;  // the next step starts from this state
         L.sortbuf[li] = welfare_key(C, li, n);
     }
     lds_barrier();
     int64_t n_invalid = invalid;  // summed over the block with the welfare
-    const double ug1 = social_welfare_block(P, L, n, S2, &n_invalid);
+    int64_t num_sum[2];
+    const double ug1 = social_welfare_block(P, L, n, S2, &n_invalid, num_sum);
     if (tid == 0) {
         gov_rew[e] = (float)(ug1 - ug0);
         S.invalid[2 * e] = inv_act + n_invalid;
@@ -1196,6 +1254,46 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     // time advance; automatic reset at the episode end
     const int t1 = t + 1;
     const bool done = t1 >= P.T;
+    if (P.metrics) {
+        // episode statistics: this step's counts join the episode's; at its
+        // end the record (productivity, 1 - gini, Eq * Prod, mean and lower
+        // median return = end utility minus the reset-state utility)
+        double mean_ret = 0.0, med_ret = 0.0;
+        if (done) {
+            const double u_start = utility(P.start_coin, 0, P.eta);
+            lds_barrier();  // the welfare is done with the sort buffer
+            for (int j = tid; j < S2; j += NT) L.sortbuf[j] = INT64_MAX;
+            lds_barrier();
+            double part = 0.0;
+#pragma unroll
+            for (int k = 0; k < APT; ++k) {
+                const int li = lane_slot + k * NR;
+                if (li >= n) continue;
+                part += u1v[k] - u_start;
+                L.sortbuf[li] = f64_order_key(u1v[k] - u_start);
+            }
+            mean_ret = block_sum_f64(part, L.red) / (double)n;
+            bitonic_sort_i64(L.sortbuf, S2);
+            med_ret = f64_from_order_key(L.sortbuf[(n - 1) >> 1]);
+        }
+        const int nm = 5 * R + 3;
+        int64_t* acc = S.macc + (int64_t)e * EJ_NACC;
+        double* rec = S.mlast + (int64_t)e * EJ_NMET;
+        for (int j = tid; j < nm; j += NT) {
+            const int64_t v = acc[j] + L.met[j];
+            acc[j] = done ? 0 : v;
+            if (done) rec[6 + j] = (double)v;
+        }
+        if (done && tid == 0) {
+            const double gini = num_sum[1] > 0 ? (double)num_sum[0] / ((double)n * (double)num_sum[1]) : 0.0;
+            rec[0] = (double)ep;
+            rec[1] = (double)num_sum[1];
+            rec[2] = 1.0 - gini;
+            rec[3] = ug1;
+            rec[4] = mean_ret;
+            rec[5] = med_ret;
+        }
+    }
     const int t_next = done ? 0 : t1;
     const int ep_next = done ? ep + 1 : ep;
     if (done) {
@@ -1441,6 +1539,17 @@ __global__ void __launch_bounds__(1024 / APT) env_reset_kernel(const EnvParams P
         S.ug[e] = __builtin_nan("");
     }
     if ((int)threadIdx.x < P.K) S.env_rates[e * P.K + threadIdx.x] = 0;
+    if (S.macc && (int)threadIdx.x < EJ_NACC) S.macc[(int64_t)e * EJ_NACC + threadIdx.x] = 0;  // a new episode
+}
+
+// record of the last completed episode of every economy, packed to 5 R + 9 doubles
+__global__ void env_metrics_copy_kernel(const double* __restrict__ mlast, int E, int len, double* __restrict__ out)
+{
+    const int64_t n = (int64_t)E * len;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = i / len, j = i - e * len;
+        out[i] = mlast[e * EJ_NMET + j];
+    }
 }
 
 __global__ void env_random_actions_kernel(const EnvParams P, const EnvState S, uint64_t act_seed,
@@ -1494,13 +1603,16 @@ struct ej_env {
     double* d_u = nullptr;
     unsigned int* d_queue = nullptr;
     int32_t* d_order = nullptr;
+    int64_t* d_macc = nullptr;  // episode statistics (allocated by ej_env_enable_metrics)
+    double* d_mlast = nullptr;
     int mode = 0, persistent_wg = 0;  // mode 0: one workgroup per economy; 1: persistent work queue
     size_t lds = 0;
     int step_NT = 64;      // workgroup size of the step: ceil(N / apw) waves
     size_t step_lds = 0;
     EnvState state() const
     {
-        return EnvState{d_field, d_t, d_ep, d_rates, d_n, d_off, d_row, d_invalid, d_ug, d_u, d_queue, d_order, E};
+        return EnvState{d_field, d_t, d_ep, d_rates, d_n,   d_off,   d_row, d_invalid,
+                        d_ug,    d_u, d_queue, d_order, E, d_macc, d_mlast};
     }
 };
 
@@ -1694,6 +1806,8 @@ int ej_env_destroy(ej_env* h)
     (void)hipFree(h->d_u);
     (void)hipFree(h->d_queue);
     (void)hipFree(h->d_order);
+    (void)hipFree(h->d_macc);
+    (void)hipFree(h->d_mlast);
     delete h;
     return EJ_OK;
 }
@@ -1709,6 +1823,7 @@ int ej_env_dims(const ej_env* h, ej_env_dims_t* out)
     out->D_gov = h->P.Dg;
     out->K = h->P.K;
     out->E = h->E;
+    out->D_metrics = 5 * h->P.R + 9;
     return EJ_OK;
 }
 
@@ -1792,6 +1907,38 @@ int ej_env_set_launch(ej_env* h, int32_t mode, int32_t workgroups)
         h->persistent_wg = g;
     }
     h->mode = mode;
+    return EJ_OK;
+}
+
+int ej_env_enable_metrics(ej_env* h, int32_t enabled)
+{
+    if (!h) return EJ_EINVAL;
+    if (enabled && !h->d_macc) {
+        const size_t E = (size_t)h->E;
+        if (hipMalloc(&h->d_macc, 8 * E * EJ_NACC) != hipSuccess) return EJ_ENOMEM;
+        if (hipMalloc(&h->d_mlast, 8 * E * EJ_NMET) != hipSuccess) {
+            (void)hipFree(h->d_macc);
+            h->d_macc = nullptr;
+            return EJ_ENOMEM;
+        }
+        std::vector<double> rec(E * EJ_NMET, 0.0);
+        for (size_t e = 0; e < E; ++e) rec[e * EJ_NMET] = -1.0;  // no episode completed yet
+        EJ_HIP(hipMemset(h->d_macc, 0, 8 * E * EJ_NACC));
+        EJ_HIP(hipMemcpy(h->d_mlast, rec.data(), 8 * E * EJ_NMET, hipMemcpyHostToDevice));
+    }
+    h->P.metrics = enabled ? 1 : 0;
+    return EJ_OK;
+}
+
+int ej_env_episode_metrics(ej_env* h, double* d_out, void* stream)
+{
+    if (!h || !d_out || !h->d_mlast) return EJ_EINVAL;
+    const int len = 5 * h->P.R + 9;
+    const int64_t n = (int64_t)h->E * len;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    env_metrics_copy_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(h->d_mlast, h->E, len, d_out);
+    EJ_LAUNCH_CHECK();
     return EJ_OK;
 }
 
@@ -1929,6 +2076,7 @@ int ej_env_set_state(ej_env* h, const ej_state_view* v, void* stream)
     std::vector<double> unknown((size_t)E, __builtin_nan(""));
     EJ_HIP(hipMemcpy(h->d_ug, unknown.data(), 8 * (size_t)E, hipMemcpyHostToDevice));
     EJ_HIP(hipMemset(h->d_u, 0xFF, 8 * (size_t)h->P.Ntot));  // all-ones: NaN, utility not known
+    if (h->d_macc) EJ_HIP(hipMemset(h->d_macc, 0, 8 * (size_t)E * EJ_NACC));  // episode-to-date counts unknown
     return EJ_OK;
 }
 

@@ -302,3 +302,56 @@ def test_reset_after_steps_equals_fresh_handle():
         assert np.array_equal(s1[k], s2[k]), k
     for e in (e1, e2):
         e.close()
+
+
+@pytest.mark.parametrize("variant", range(3))
+def test_episode_metrics_match_oracle(variant):
+    """Episode statistics (ej_env_enable_metrics / ej_env_episode_metrics)
+    against the oracle's record at every episode end over 2.5 episodes:
+    episode index, productivity, action counts, trades and price sums
+    exactly; equality and Eq * Prod exactly (the same integer Gini sums);
+    mean return within 1e-12 relative (summation order) and the median
+    within 1e-9 (utilities by each side's pow).  Uneven populations, invalid
+    actions, one economy above 256 agents (the sorted-welfare path)."""
+    torch = _torch()
+    cases = [
+        (W.env_config(E=3, N=37, R=3, P=6, X=4, P_tax=5, K=3, T=23, seed=1), [37, 5, 20]),
+        (W.env_config(E=2, N=300, R=2, P=5, X=3, P_tax=4, K=2, T=14, seed=2), [300, 257]),
+        (W.env_config(E=2, N=9, R=5, P=3, X=6, P_tax=7, K=0, T=11, seed=3), None),
+    ]
+    cfg, ns = cases[variant]
+    env = make_env(cfg, ns)
+    env.enable_metrics()
+    E = cfg["E"]
+    ns = [cfg["N"]] * E if ns is None else ns
+    orc = [oe.OracleEnv(cfg, e=e, seed=cfg["seed"], n_agents=ns[e]) for e in range(E)]
+    b = env.buffers()
+    rng = np.random.default_rng(variant)
+    A = env.A
+    assert (env.episode_metrics().cpu().numpy()[:, 0] == -1).all()
+    ends = 0
+    for step in range(int(2.5 * cfg["T"])):
+        acts = [rng.integers(-1, A + 1, size=ns[e]).astype(np.int32) for e in range(E)]
+        govs = [rng.integers(0, 21, size=max(cfg["K"], 1)).astype(np.int32) for e in range(E)]
+        b["act"].copy_(torch.from_numpy(np.concatenate(acts)))
+        if cfg["K"] > 0:
+            b["gov"].copy_(torch.from_numpy(np.concatenate([g[:cfg["K"]] for g in govs])))
+        env.step(b["act"], b["gov"], b["rew"], b["gov_rew"], b["done"], b["obs"], b["mask"])
+        done = False
+        for e in range(E):
+            _, _, d = orc[e].step(acts[e], govs[e][:cfg["K"]])
+            done = done or bool(d)
+        if not done:
+            continue
+        ends += 1
+        g = env.episode_metrics().cpu().numpy()
+        R = cfg["R"]
+        for e in range(E):
+            o = orc[e].episode_metrics()
+            where = f"step {step} economy {e}"
+            exact = np.r_[0, 1, 2, 3, np.arange(6, 9 + 5 * R)]
+            assert np.array_equal(g[e][exact], o[exact]), (where, g[e][exact], o[exact])
+            assert abs(g[e][4] - o[4]) <= 1e-12 * max(1.0, abs(o[4])), (where, g[e][4], o[4])
+            assert abs(g[e][5] - o[5]) <= 1e-9 * max(1.0, abs(o[5])), (where, g[e][5], o[5])
+    assert ends == 2
+    env.close()
