@@ -50,6 +50,8 @@ extern "C" {
 #define EJ_MAX_K 16   /* tax brackets */
 #define EJ_MAX_X 32   /* order lifetime in steps */
 #define EJ_GOV_LEVELS 21 /* tax levels 0 %, 5 %, ..., 100 % */
+#define EJ_SKILL_NORMAL 1 /* skill_mode bits (the multi-agent variant, Sec. 5) */
+#define EJ_SKILL_GROWTH 2
 
 /* Observation feature-group scales (float multipliers applied before the
  * bf16 rounding of the population observation). */
@@ -72,6 +74,12 @@ typedef struct ej_obs_scales {
  *   start_coin   coin at reset (Table 2: 15)
  *   labor_*      labor per action in units of 1/20 (Table 2: 20, 20, 1)
  *   allow_noop   NOOP allowed (Table 2: true)
+ *   skill_mode   0: skills Pareto(4) clipped to 5, fixed within an episode.
+ *                The multi-agent variant of Sec. 5: EJ_SKILL_NORMAL draws them
+ *                near 1 with spread 1 (the sum of twelve uniforms minus six,
+ *                plus 1, clipped to [0, 5]); EJ_SKILL_GROWTH raises a skill
+ *                by 0.5 % times (1 - skill / 5) each time it is used (gather
+ *                of that resource, craft), rounded down in Q16
  *   eta, omega   utility curvature (Eq. (1), 0.27) and equality weight (Eq. (4), 1)
  *   seed         key of the counter-based generator for skills, gathering
  *                luck and order tie keys */
@@ -80,7 +88,7 @@ typedef struct ej_env_config {
     int32_t R_kappa, R_d, kappa_c, start_coin;
     int32_t labor_gather, labor_craft, labor_trade;
     int32_t allow_noop;
-    int32_t reserved0;
+    int32_t skill_mode; /* EJ_SKILL_NORMAL | EJ_SKILL_GROWTH (the Sec. 5 variant); 0: Pareto skills, fixed */
     double eta, omega;
     uint64_t seed;
     int32_t prices[EJ_MAX_P];

@@ -45,6 +45,7 @@ typedef struct {
     int32_t R_kappa, R_d, kappa_c, start_coin;
     int32_t labor_gather, labor_craft, labor_trade; /* units of 1/20 labor */
     int32_t allow_noop;
+    int32_t skill_mode; /* bit 0: skills ~ N(1, 1) clipped to [0, 5]; bit 1: skills grow with use */
     double eta, omega;
     int32_t prices[OC_MAXP];
     int32_t cutoffs[OC_MAXK];
@@ -184,6 +185,43 @@ static int32_t skill_q16_from_word(uint64_t w)
     return (int32_t)(x * 65536.0 + 0.5);
 }
 
+/* The multi-agent variant (Sec. 5): skills start near 1 with spread 1 and
+ * grow by 0.5 % with every gather (that resource's skill) or craft (the
+ * crafting skill), the bonus shrinking to zero at the maximum 5.
+ *
+ * Normal skills: the sum of twelve uniforms minus six, whose mean is 0 and
+ * variance 1 (the classical uniform-sum approximation of the standard
+ * normal, Irwin-Hall with n = 12), taken in exact integer arithmetic: twelve
+ * 24-bit uniforms (the top 24 bits of both 32-bit halves of six words from
+ * two draws) sum to S, and x = 1 + S / 2^24 - 6, i.e. x in Q16 =
+ * floor(S / 2^8) - 5 * 2^16, clipped to [0, 5]. */
+static int32_t normal_skill_q16(uint64_t seed, int32_t e, int32_t ep, int32_t i, int32_t s)
+{
+    uint64_t w0[4], w1[4];
+    draw(seed, OC_PURPOSE_SKILL, (uint64_t)e, (uint64_t)ep, (uint64_t)i, (uint64_t)(64 + 2 * s), w0);
+    draw(seed, OC_PURPOSE_SKILL, (uint64_t)e, (uint64_t)ep, (uint64_t)i, (uint64_t)(65 + 2 * s), w1);
+    uint64_t words[6] = {w0[0], w0[1], w0[2], w0[3], w1[0], w1[1]};
+    int64_t S = 0;
+    for (int k = 0; k < 6; ++k) {
+        S += (int64_t)(words[k] >> 40);                  /* top 24 bits of the high half */
+        S += (int64_t)((words[k] & 0xFFFFFFFFull) >> 8); /* top 24 bits of the low half */
+    }
+    int64_t q = (S >> 8) - 5 * 65536;
+    if (q < 0) q = 0;
+    if (q > 5 * 65536) q = 5 * 65536;
+    return (int32_t)q;
+}
+
+/* s <- s + 0.005 s (1 - s / 5), rounded down in Q16: the 0.5 % bonus times
+ * the remaining fraction of the range up to 5 (never above 5). */
+static int32_t grown_skill_q16(int32_t s)
+{
+    const int64_t smax = 5 * 65536;
+    int64_t d = ((int64_t)s * (smax - (int64_t)s)) / (200 * smax);
+    int64_t v = (int64_t)s + (d > 0 ? d : 0);
+    return (int32_t)(v > smax ? smax : v);
+}
+
 static void reset_episode_state(oc_env* env)
 {
     const oc_config* c = &env->c;
@@ -204,7 +242,8 @@ static void reset_episode_state(oc_env* env)
             uint64_t out[4];
             draw(env->seed, OC_PURPOSE_SKILL, (uint64_t)env->e, (uint64_t)env->ep, (uint64_t)i,
                  (uint64_t)(s / 4), out);
-            int32_t q = skill_q16_from_word(out[s % 4]);
+            int32_t q = (c->skill_mode & 1) ? normal_skill_q16(env->seed, env->e, env->ep, i, s)
+                                            : skill_q16_from_word(out[s % 4]);
             if (s < c->R) AG(env->sg, s, i) = q;
             else env->sc[i] = q;
         }
@@ -484,6 +523,7 @@ int32_t oc_env_step(oc_env* env, const int32_t* act, const int32_t* gov, float* 
             int64_t amount = ((int64_t)AG(env->sg, r, i) + rho_q) >> 16; /* floor(SG + rho) */
             AG(env->res_inv, r, i) += (int32_t)amount;
             env->labor[i] += c->labor_gather;
+            if (c->skill_mode & 2) AG(env->sg, r, i) = grown_skill_q16(AG(env->sg, r, i));
         } else if (type == A_CRAFT) {
             /* pick R_d types with at least R_kappa units, fullest first, ties to the lower id */
             int32_t used[OC_MAXR] = {0};
@@ -498,6 +538,7 @@ int32_t oc_env_step(oc_env* env, const int32_t* act, const int32_t* gov, float* 
             }
             env->coin_inv[i] += (int32_t)(((int64_t)env->sc[i] * c->kappa_c) >> 16);
             env->labor[i] += c->labor_craft;
+            if (c->skill_mode & 2) env->sc[i] = grown_skill_q16(env->sc[i]);
         } else {
             uint64_t w[4];
             draw(env->seed, OC_PURPOSE_ENV, (uint64_t)env->e, (uint64_t)env->ep, (uint64_t)t,

@@ -18,7 +18,7 @@ _MAXR, _MAXP, _MAXK = 16, 128, 16
 class OcConfig(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("N", "R", "P", "X", "max_orders", "P_tax", "K", "T", "R_kappa",
                                           "R_d", "kappa_c", "start_coin", "labor_gather", "labor_craft",
-                                          "labor_trade", "allow_noop")] + [
+                                          "labor_trade", "allow_noop", "skill_mode")] + [
         ("eta", C.c_double), ("omega", C.c_double),
         ("prices", C.c_int32 * _MAXP), ("cutoffs", C.c_int32 * _MAXK)]
 
@@ -89,6 +89,7 @@ def make_config(cfg: dict) -> OcConfig:
     for n in ("N", "R", "P", "X", "max_orders", "P_tax", "K", "T", "R_kappa", "R_d", "kappa_c",
               "start_coin", "labor_gather", "labor_craft", "labor_trade", "allow_noop"):
         setattr(c, n, int(cfg[n]))
+    c.skill_mode = int(cfg.get("skill_mode", 0))
     c.eta = float(cfg["eta"])
     c.omega = float(cfg["omega"])
     for i, v in enumerate(cfg["prices"]):

@@ -27,7 +27,7 @@ class EjObsScales(C.Structure):
 class EjEnvConfig(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("E", "N", "R", "P", "X", "max_orders", "P_tax", "K", "T", "R_kappa",
                                           "R_d", "kappa_c", "start_coin", "labor_gather", "labor_craft",
-                                          "labor_trade", "allow_noop", "reserved0")] + [
+                                          "labor_trade", "allow_noop", "skill_mode")] + [
         ("eta", C.c_double), ("omega", C.c_double), ("seed", C.c_uint64),
         ("prices", C.c_int32 * EJ_MAX_P), ("cutoffs", C.c_int32 * EJ_MAX_K), ("scales", EjObsScales)]
 
@@ -176,6 +176,7 @@ def make_env_config(cfg: dict, scales: dict) -> EjEnvConfig:
     for n in ("E", "N", "R", "P", "X", "max_orders", "P_tax", "K", "T", "R_kappa", "R_d", "kappa_c",
               "start_coin", "labor_gather", "labor_craft", "labor_trade", "allow_noop"):
         setattr(c, n, int(cfg[n]))
+    c.skill_mode = int(cfg.get("skill_mode", 0))
     c.eta, c.omega, c.seed = float(cfg["eta"]), float(cfg["omega"]), int(cfg.get("seed", 0))
     for i, v in enumerate(cfg["prices"]):
         c.prices[i] = int(v)

@@ -45,6 +45,7 @@ struct EnvParams {
     int32_t gov_draw;
     int32_t apw;   // agents per wavefront in the step (64, 32 or 16; lanes beyond it idle)
     int32_t metrics;  // episode statistics accumulated by the step (ej_env_enable_metrics)
+    int32_t skill_mode;  // EJ_SKILL_NORMAL / EJ_SKILL_GROWTH bits
     int64_t Ntot;  // stride between two state fields
     int32_t prices[EJ_MAX_P];
     int32_t cutoffs[EJ_MAX_K];
@@ -107,6 +108,33 @@ __host__ __device__ inline int32_t skill_q16(uint64_t w)
     double x = 1.0 / sqrt(sqrt(u));
     x = x > 5.0 ? 5.0 : x;
     return (int32_t)(x * 65536.0 + 0.5);
+}
+
+// Skills of the multi-agent variant: near 1 with spread 1 as the sum of
+// twelve 24-bit uniforms (both 32-bit halves of six words of two draws, top
+// 24 bits each) minus six, plus one: floor(S / 2^8) - 5 * 2^16 in Q16, clipped
+// to [0, 5].  Integer arithmetic only, so every device and host agrees.
+__device__ inline int32_t normal_skill_q16(uint64_t seed, int e, int ep, int i, int s)
+{
+    const u64x4 a = philox(seed, PURPOSE_SKILL, (uint64_t)e, (uint64_t)ep, (uint64_t)i, (uint64_t)(64 + 2 * s));
+    const u64x4 b = philox(seed, PURPOSE_SKILL, (uint64_t)e, (uint64_t)ep, (uint64_t)i, (uint64_t)(65 + 2 * s));
+    const uint64_t w[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+    int64_t S = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) S += (int64_t)(w[k] >> 40) + (int64_t)((w[k] & 0xFFFFFFFFull) >> 8);
+    int64_t q = (S >> 8) - 5 * 65536;
+    q = q < 0 ? 0 : (q > 5 * 65536 ? 5 * 65536 : q);
+    return (int32_t)q;
+}
+
+// skill growth with use: s + floor(s (5 - s) / (200 * 5)) in Q16 (0.5 %
+// shrinking to nothing at the maximum 5)
+__device__ inline int32_t grown_skill_q16(int32_t s)
+{
+    const int64_t smax = 5 * 65536;
+    const int64_t d = ((int64_t)s * (smax - (int64_t)s)) / (200 * smax);
+    const int64_t v = (int64_t)s + (d > 0 ? d : 0);
+    return (int32_t)(v > smax ? smax : v);
 }
 
 // ---------------------------------------------------------------------------
@@ -219,7 +247,8 @@ __device__ inline void reset_agent(const EnvParams& P, int e, int ep, int i, Age
     for (int s = 0; s <= RM; ++s) {
         if (s > P.R) break;
         if (s > 0 && (s & 3) == 0) w = philox(P.seed, PURPOSE_SKILL, (uint64_t)e, (uint64_t)ep, (uint64_t)i, (uint64_t)(s >> 2));
-        int32_t q = skill_q16(word_of(w, s & 3));
+        int32_t q = (P.skill_mode & EJ_SKILL_NORMAL) ? normal_skill_q16(P.seed, e, ep, i, s)
+                                                    : skill_q16(word_of(w, s & 3));
         if (s < P.R) {
 #pragma unroll
             for (int r = 0; r < RM; ++r)
@@ -967,6 +996,11 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             int64_t amount = ((int64_t)rget(a.sg, d.r) + rho_q) >> 16;
             radd(a.res_inv, d.r, (int32_t)amount);
             a.labor += P.labor_gather;
+            if (P.skill_mode & EJ_SKILL_GROWTH) {
+#pragma unroll
+                for (int r = 0; r < RM; ++r)
+                    if (r == d.r) a.sg[r] = grown_skill_q16(a.sg[r]);
+            }
         } else if (d.type == 2) {  // craft: R_d fullest eligible types, ties to the lower id
             uint32_t used = 0;
             for (int c = 0; c < P.R_d; ++c) {
@@ -983,6 +1017,7 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
             }
             a.coin_inv += (int32_t)(((int64_t)a.sc * P.kappa_c) >> 16);
             a.labor += P.labor_craft;
+            if (P.skill_mode & EJ_SKILL_GROWTH) a.sc = grown_skill_q16(a.sc);
         } else if (d.type >= 3) {  // order with escrow
             const int side = d.type == 4;
             if (side == 0) {
@@ -1308,7 +1343,8 @@ __device__ __forceinline__ void env_step_one(const EnvParams& P, const EnvState&
     for (int k = 0; k < APT; ++k) {
         const int li = lane_slot + k * NR;
         if (li >= n) continue;
-        store_agent(P, S, off + li, ag[k], done);  // skills are redrawn only at a reset
+        // skills change only at a reset, unless they grow with use
+        store_agent(P, S, off + li, ag[k], done || (P.skill_mode & EJ_SKILL_GROWTH) != 0);
         done_out[row0 + li] = done ? 1 : 0;
     }
     if (tid == 0) {
@@ -1678,6 +1714,7 @@ static int validate(const ej_env_config* c)
     if ((int64_t)c->R * 2 * c->P * c->X > 8192) return EJ_EUNSUPPORTED;
     if (c->R_d < 0 || c->R_d > c->R || c->R_kappa < 1 || c->max_orders < 0 || c->start_coin < 0) return EJ_EINVAL;
     if (c->labor_gather < 0 || c->labor_craft < 0 || c->labor_trade < 0) return EJ_EINVAL;
+    if (c->skill_mode & ~(EJ_SKILL_NORMAL | EJ_SKILL_GROWTH)) return EJ_EINVAL;
     if (!(c->eta >= 0.0) || c->eta == 1.0 || !(c->omega >= 0.0 && c->omega <= 1.0)) return EJ_EINVAL;
     for (int p = 0; p < c->P; ++p) {
         if (c->prices[p] <= 0) return EJ_EINVAL;
@@ -1707,6 +1744,7 @@ int ej_env_create(const ej_env_config* cfg, const int32_t* h_n_per_env, ej_env**
     P.P_tax = cfg->P_tax; P.K = cfg->K; P.T = cfg->T; P.R_kappa = cfg->R_kappa; P.R_d = cfg->R_d;
     P.kappa_c = cfg->kappa_c; P.start_coin = cfg->start_coin; P.labor_gather = cfg->labor_gather;
     P.labor_craft = cfg->labor_craft; P.labor_trade = cfg->labor_trade; P.allow_noop = cfg->allow_noop;
+    P.skill_mode = cfg->skill_mode;
     P.A = 2 + P.R + 2 * P.R * P.P;
     P.W = (P.A + 31) / 32;
     P.D = 7 + 7 * P.R + P.K;

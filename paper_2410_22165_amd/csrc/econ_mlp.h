@@ -165,9 +165,15 @@ __device__ inline void relu_store_t(const f32x4 (&acc)[TR][CTW], uint16_t* hbuf,
 
 // fp32 logit chunk in LDS: a row's 128 columns as four 32-column quarters,
 // each padded to ZQ words, so that the four lanes reading one row's quarters
-// (and the rows a wave reads together) fall on distinct banks
+// (and the rows a wave reads together) fall on distinct banks.
 constexpr int ZQ = 36, ZS = 4 * ZQ;
-__device__ inline int zcol(int cc) { return (cc >> 5) * ZQ + (cc & 31); }
+// The 16 rows of a transposed MFMA tile store the same four columns at once:
+// with a row stride of ZS = 144 words rows r and r + 4 would share banks, so
+// the 4-column group g (0..7) inside a quarter sits at g ^ zsw(row).  The
+// four consecutive rows that a wave's quad reads together share zsw, so
+// their reads stay conflict-free too.
+__device__ inline int zsw(int row) { return (row >> 2) & 3; }
+__device__ inline int zcol(int row, int cc) { return (cc >> 5) * ZQ + ((((cc >> 2) & 7) ^ zsw(row)) << 2) + (cc & 3); }
 
 // b1 [H], b2 [H], b3 [A1p] (zero beyond A1) -> sbias, by a 256-thread
 // workgroup; all loads are issued before the first store (A1p <= 1024)

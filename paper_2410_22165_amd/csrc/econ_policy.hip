@@ -139,7 +139,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
                 const float4 b = *(const float4*)(sb3 + c * 128 + cc);
 #pragma unroll
                 for (int rt = 0; rt < TR; ++rt)
-                    *(float4*)(zbuf + (rt * 16 + (l & 15)) * ZS + zcol(cc)) =
+                    *(float4*)(zbuf + (rt * 16 + (l & 15)) * ZS + zcol(l & 15, cc)) =
                         float4{acc3[rt][ct][0] + b.x, acc3[rt][ct][1] + b.y, acc3[rt][ct][2] + b.z,
                                acc3[rt][ct][3] + b.w};
             }
@@ -153,7 +153,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
             float z[32];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                const float4 v = *(const float4*)(zrow + q * ZQ + 4 * j);
+                const float4 v = *(const float4*)(zrow + q * ZQ + 4 * (j ^ zsw(rloc)));
                 z[4 * j] = v.x;
                 z[4 * j + 1] = v.y;
                 z[4 * j + 2] = v.z;
@@ -218,12 +218,12 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
             key = quad_min_i(key);
             const int top = quad_max_i(mw ? 32 * q + 31 - __builtin_clz(mw) : -1);
             key = key == NONE ? top : key;  // rounding put the target at the top
-            const float zk = zrow[zcol(key < 0 ? 0 : key)];  // the chosen action's logit
+            const float zk = zrow[zcol(rloc, key < 0 ? 0 : key)];  // the chosen action's logit
             sM[k] = mn;
             sS[k] = Sn;
             sT[k] = Tn;
             sW[k] = Wn;
-            if (c == d.NC - 1) sV[k] = zrow[zcol(d.A - c * 128)];  // the value head sits right after the logits
+            if (c == d.NC - 1) sV[k] = zrow[zcol(rloc, d.A - c * 128)];  // the value head sits right after the logits
             sA[k] = take ? c * 128 + key : sA[k];
             sZ[k] = take ? zk : sZ[k];
         }

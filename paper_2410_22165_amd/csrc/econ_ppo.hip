@@ -357,14 +357,14 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
             const float4 b = *(const float4*)(sbias + 2 * H + c * 128 + cc);
 #pragma unroll
             for (int rt = 0; rt < TR; ++rt)
-                *(float4*)(zbuf + (rt * 16 + (l & 15)) * ZS + zcol(cc)) =
+                *(float4*)(zbuf + (rt * 16 + (l & 15)) * ZS + zcol(l & 15, cc)) =
                     float4{acc3[rt][ct][0] + b.x, acc3[rt][ct][1] + b.y, acc3[rt][ct][2] + b.z, acc3[rt][ct][3] + b.w};
         }
     };
     auto load_row = [&](float (&z)[32]) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const float4 v = *(const float4*)(zbuf + srow * ZS + q * ZQ + 4 * j);
+            const float4 v = *(const float4*)(zbuf + srow * ZS + q * ZQ + 4 * (j ^ zsw(srow)));
             z[4 * j] = v.x;
             z[4 * j + 1] = v.y;
             z[4 * j + 2] = v.z;

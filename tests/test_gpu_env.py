@@ -355,3 +355,21 @@ def test_episode_metrics_match_oracle(variant):
             assert abs(g[e][5] - o[5]) <= 1e-9 * max(1.0, abs(o[5])), (where, g[e][5], o[5])
     assert ends == 2
     env.close()
+
+
+@pytest.mark.parametrize("R", [4, 8])
+def test_parity_multi_agent_variant_lockstep(R):
+    """The multi-agent variant (Sec. 5): skills near 1 with spread 1 that
+    grow with every gather and craft, taxes off, prices 3, 6, 9, R_d from R;
+    state (skills included), rewards, observations and masks against the
+    oracle after every step, over an episode end (new skills drawn)."""
+    cfg = W.variant_config(R=R, N=23, E=3, X=7, T=35, seed=4)
+    run_lockstep(cfg, 50, actions="masked", seed=R, n_per_env=[23, 9, 16])
+
+
+@pytest.mark.slow
+def test_parity_multi_agent_variant_sampled():
+    """64 economies of 100 agents with 4 resources (30 actions), order
+    lifetime 30, 1100 steps (an episode end at 1000), 2 sampled economies."""
+    cfg = W.variant_config(R=4, N=100, E=64, seed=2)
+    _sampled_parity(cfg, 1100, sample=[0, 41])

@@ -30,14 +30,25 @@ def default_prices(p: int) -> list[int]:
 
 def env_config(E=1, N=4, R=2, P=10, X=10, max_orders=15, P_tax=10, K=7, T=100, R_kappa=2, R_d=2,
                kappa_c=10, start_coin=15, labor_gather=20, labor_craft=20, labor_trade=1,
-               allow_noop=1, eta=0.27, omega=1.0, prices=None, cutoffs=None, seed=0):
+               allow_noop=1, eta=0.27, omega=1.0, prices=None, cutoffs=None, seed=0, skill_mode=0):
     cfg = dict(E=E, N=N, R=R, P=P, X=X, max_orders=max_orders, P_tax=P_tax, K=K, T=T,
                R_kappa=R_kappa, R_d=R_d, kappa_c=kappa_c, start_coin=start_coin,
                labor_gather=labor_gather, labor_craft=labor_craft, labor_trade=labor_trade,
-               allow_noop=allow_noop, eta=eta, omega=omega, seed=seed)
+               allow_noop=allow_noop, eta=eta, omega=omega, seed=seed, skill_mode=skill_mode)
     cfg["prices"] = list(prices) if prices is not None else default_prices(P)
     cfg["cutoffs"] = list(cutoffs) if cutoffs is not None else default_cutoffs(P_tax, K)
     return cfg
+
+
+SKILL_NORMAL, SKILL_GROWTH = 1, 2
+
+
+def variant_config(R: int, N: int = 100, E: int = 1, X: int = 30, T: int = 1000, seed: int = 0):
+    """The multi-agent experiments' economy (Sec. 5): R resources, taxes off,
+    R_d = max(1, floor(log2 R)), trade prices 3, 6 and 9, skills near 1 with
+    spread 1 that grow with use; otherwise Table 2 (order lifetime 30)."""
+    return env_config(E=E, N=N, R=R, P=3, X=X, P_tax=100, K=0, T=T, R_d=max(1, int(math.floor(math.log2(R)))),
+                      prices=[3, 6, 9], seed=seed, skill_mode=SKILL_NORMAL | SKILL_GROWTH)
 
 
 def num_actions(cfg) -> int:
