@@ -357,6 +357,48 @@ int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t*
                     float* d_loss, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Government policy (Sec. 3 "Government Agent", "Setting tax rates"; Sec. 4:
+ * trained with PPO at the same time as the population).  The same network
+ * as the population's (ej_mlp_desc with D = D_gov features, D_stride =
+ * D_gov rounded up to 8, H <= 256, A = 21 K) on the economy's government
+ * observation, with K independent categorical heads over the 21 tax levels
+ * (bracket k: logits 21 k .. 21 k + 20) and the value as the last output;
+ * K <= 12.  log pi(levels) is the sum of the heads' log-probabilities and
+ * the entropy the sum of the heads' entropies.  Weights, layout and
+ * ej_mlp_sync_weights as for the population.
+ * ------------------------------------------------------------------------ */
+
+/* One row per economy: d_gov_obs [E * D_gov] fp32 (ej_env_observe), each
+ * feature multiplied by d_scale [D_gov] and rounded to bf16 (these rows go to
+ * d_obs_bf16 [E * D_stride] when given, for the learner).  Writes the levels
+ * d_levels [E * K] (0..20, the input of ej_env_step), their log-probability
+ * d_logp [E], the value d_val [E] and the entropy d_ent [E]; d_logits
+ * [E * 21 K] nullable (tests).  Level k of economy e is the inverse CDF of
+ * head k in level order at the uniform of word k % 4 of the counter-based
+ * generator keyed (seed, government sampling; e, ctr + *d_ctr_base, k / 4). */
+int ej_gov_policy_forward(const ej_mlp_desc* m, int32_t K, const float* d_params, const uint16_t* d_work,
+                          const float* d_gov_obs, const float* d_scale, int64_t E, uint64_t seed, uint64_t ctr,
+                          const uint64_t* d_ctr_base, int32_t* d_levels, float* d_logp, float* d_val, float* d_ent,
+                          uint16_t* d_obs_bf16, float* d_logits, void* stream);
+
+/* Bytes of device scratch ej_gov_ppo_backward needs for `rows` rows. */
+int ej_gov_ppo_workspace_size(const ej_mlp_desc* m, int32_t K, int64_t rows, int64_t* bytes);
+
+/* The government's PPO minibatch loss and gradient, as ej_ppo_backward
+ * (Table 2 settings, advantages normalised over the minibatch): b->obs the
+ * bf16 rows written by ej_gov_policy_forward, b->act [M_total * K] the
+ * levels taken, b->mask unused (NULL); d_grads overwritten; d_loss [5] as
+ * for the population.  Deterministic. */
+int ej_gov_ppo_backward(const ej_mlp_desc* m, int32_t K, const float* d_params, const uint16_t* d_work,
+                        const ej_ppo_batch* b, const ej_ppo_hparams* hp, void* d_workspace, int64_t workspace_bytes,
+                        float* d_grads, float* d_loss, void* stream);
+
+/* d_out[e] = sum over t in [t_begin, t_end) of d_x[t * E + e] (fp32, in time
+ * order): the government's reward of a tax period from the per-step rewards
+ * [T * E] of ej_rollout_buffers.d_gov_rew. */
+int ej_sum_steps(const float* d_x, int32_t t_begin, int32_t t_end, int64_t E, float* d_out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Rollout graph and autotuner (the batching forms around the kernels).
  * ------------------------------------------------------------------------ */
 

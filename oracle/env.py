@@ -125,6 +125,21 @@ def sample_uniforms(seed: int, rows, ctr: int, n_chunks: int):
     return u1, u2
 
 
+def gov_uniforms(seed: int, rows, ctr: int, K: int) -> np.ndarray:
+    """The government sampler's uniform per (economy row, bracket k): word
+    k mod 4 of Philox(seed, purpose 6; row, ctr, k / 4, 0),
+    u = (top 24 bits + 1/2) / 2^24."""
+    rows = np.asarray(rows, dtype=np.int64)
+    u = np.zeros((len(rows), K))
+    for m, r in enumerate(rows):
+        for q in range((K + 3) // 4):
+            w = philox4x64([int(r), int(ctr), q, 0], [int(seed), 6])
+            for j in range(4):
+                if 4 * q + j < K:
+                    u[m, 4 * q + j] = ((int(w[j]) >> 40) + 0.5) / 16777216.0
+    return u
+
+
 def utility(coin: int, labor_q: int, eta: float) -> float:
     return lib().oc_utility(int(coin), int(labor_q), float(eta))
 

@@ -257,3 +257,105 @@ def adam_step(w, g, m, v, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return w - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ---------------------------------------------------------------------------
+# The government agent (Sec. 3 "Government Agent", "Setting tax rates"): one
+# level in 0..20 per tax bracket, K independent categorical heads on the same
+# kind of network, trained with the same PPO loss (Sec. 4: the government
+# learns at the same time as the population).
+# ---------------------------------------------------------------------------
+GOV_LEVELS = 21
+
+
+def gov_obs_rows(gov_obs, scale, Ds: int) -> np.ndarray:
+    """bf16 bit patterns [E, Ds] of the government features times their
+    scale (the product in float32, then rounded to bf16; zero padding)."""
+    x = np.asarray(gov_obs, np.float32) * np.asarray(scale, np.float32)[None, :]
+    b = bf16_round(x).view(np.uint32) >> 16
+    out = np.zeros((x.shape[0], Ds), np.uint16)
+    out[:, :x.shape[1]] = b.astype(np.uint16)
+    return out
+
+
+def gov_head_log_softmax(logits: np.ndarray, K: int) -> np.ndarray:
+    """log pi_k(level) [E, K, 21] of every bracket head."""
+    z = np.asarray(logits, np.float64)[:, :K * GOV_LEVELS].reshape(-1, K, GOV_LEVELS)
+    m = z.max(axis=2, keepdims=True)
+    return z - (m + np.log(np.exp(z - m).sum(axis=2, keepdims=True)))
+
+
+def gov_forward(x, w: dict, K: int, u: np.ndarray, bf16_hidden: bool = False):
+    """Levels drawn head by head (inverse CDF in level order at u[e, k]),
+    their summed log-probability, the summed entropy, the value; plus the
+    smallest distance of any draw from its threshold (relative to the head's
+    total), so that a test can skip decisions rounding could flip."""
+    logits, value = mlp(x, w, bf16_hidden=bf16_hidden)
+    lp = gov_head_log_softmax(logits, K)
+    p = np.exp(lp)
+    E = lp.shape[0]
+    levels = np.zeros((E, K), np.int64)
+    margin = np.full((E, K), np.inf)
+    for e in range(E):
+        for k in range(K):
+            cdf = np.cumsum(p[e, k])
+            j = int(np.searchsorted(cdf, u[e, k] * cdf[-1], side="right"))
+            j = min(j, GOV_LEVELS - 1)
+            levels[e, k] = j
+            lo = cdf[j - 1] if j > 0 else 0.0
+            margin[e, k] = min(abs(u[e, k] * cdf[-1] - lo), abs(cdf[j] - u[e, k] * cdf[-1])) / cdf[-1]
+    logp = np.take_along_axis(lp, levels[:, :, None], axis=2)[:, :, 0].sum(axis=1)
+    ent = -(p * lp).sum(axis=(1, 2))
+    return dict(logits=logits, value=value, levels=levels, logp=logp, entropy=ent, margin=margin.min(axis=1),
+                margin_heads=margin)
+
+
+def gov_ppo_loss_torch(params: dict, obs, levels, logp_old, val_old, adv, ret, hp: dict, K: int,
+                       bf16_hidden: bool = False, capture: dict | None = None):
+    """The PPO loss of ppo_loss_torch with the multi-discrete policy: the
+    ratio uses the sum over brackets of log pi_k(level_k), the entropy is the
+    sum of the brackets' entropies."""
+    x = torch.as_tensor(np.asarray(obs, np.float64))
+    z1 = x @ params["W1"] + params["b1"]
+    h1 = torch.relu(z1)
+    if bf16_hidden:
+        h1 = _round_bf16_straight_through(h1)
+    z2 = h1 @ params["W2"] + params["b2"]
+    h2 = torch.relu(z2)
+    if bf16_hidden:
+        h2 = _round_bf16_straight_through(h2)
+    out = h2 @ params["W3"] + params["b3"]
+    if capture is not None and out.requires_grad:
+        out.retain_grad()
+    heads = out[:, :K * GOV_LEVELS].reshape(-1, K, GOV_LEVELS)
+    v = out[:, K * GOV_LEVELS]
+    lp_all = torch.log_softmax(heads, dim=2)
+    lv = torch.as_tensor(np.asarray(levels, np.int64))
+    logp = lp_all.gather(2, lv[:, :, None])[:, :, 0].sum(dim=1)
+    ent = -(torch.exp(lp_all) * lp_all).sum(dim=(1, 2))
+    A = torch.as_tensor(np.asarray(adv, np.float64))
+    A = (A - A.mean()) / (torch.sqrt(((A - A.mean()) ** 2).mean()) + 1e-8)
+    ratio = torch.exp(logp - torch.as_tensor(np.asarray(logp_old, np.float64)))
+    eps = hp["clip"]
+    pg = -torch.minimum(ratio * A, torch.clamp(ratio, 1.0 - eps, 1.0 + eps) * A).mean()
+    vo = torch.as_tensor(np.asarray(val_old, np.float64))
+    R = torch.as_tensor(np.asarray(ret, np.float64))
+    v_clip = vo + torch.clamp(v - vo, -hp["vclip"], hp["vclip"])
+    vl = 0.5 * torch.maximum((v - R) ** 2, (v_clip - R) ** 2).mean()
+    en = ent.mean()
+    loss = pg + hp["vf_coef"] * vl - hp["ent_coef"] * en
+    if capture is not None:
+        capture.update(z1=z1, z2=z2, h1=h1, h2=h2, out=out, ratio=ratio, V=v)
+    return loss, dict(pg=pg, vf=vl, ent=en)
+
+
+def gov_ppo_grads(w_f32: dict, obs, levels, logp_old, val_old, adv, ret, hp: dict, K: int,
+                  bf16_hidden: bool = False, capture: dict | None = None):
+    """Float64 loss and autograd gradients with respect to the bf16 weights."""
+    w = bf16_weights(w_f32)
+    params = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in w.items()}
+    loss, terms = gov_ppo_loss_torch(params, obs, levels, logp_old, val_old, adv, ret, hp, K,
+                                     bf16_hidden=bf16_hidden, capture=capture)
+    loss.backward()
+    return (float(loss.detach()), {k: float(v.detach()) for k, v in terms.items()},
+            {k: params[k].grad.numpy().copy() for k in params})

@@ -137,6 +137,12 @@ def _declare_learner(L):
         "ej_ppo_backward_static": [C.POINTER(EjMlpDesc), vp, vp, C.POINTER(EjPpoBatch), C.POINTER(EjPpoHparams),
                                    vp, vp, vp],
         "ej_adam": [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp],
+        "ej_gov_policy_forward": [C.POINTER(EjMlpDesc), i32, vp, vp, vp, vp, i64, u64, u64, vp, vp, vp, vp, vp, vp,
+                                  vp, vp],
+        "ej_gov_ppo_workspace_size": [C.POINTER(EjMlpDesc), i32, i64, C.POINTER(i64)],
+        "ej_gov_ppo_backward": [C.POINTER(EjMlpDesc), i32, vp, vp, C.POINTER(EjPpoBatch), C.POINTER(EjPpoHparams),
+                                vp, i64, vp, vp, vp],
+        "ej_sum_steps": [vp, i32, i32, i64, vp, vp],
         "ej_rollout_capture": [vp, C.POINTER(EjMlpDesc), vp, vp, C.POINTER(EjRolloutConfig),
                                C.POINTER(EjRolloutBuffers), C.POINTER(vp)],
         "ej_rollout_launch": [vp, vp],
@@ -494,3 +500,35 @@ def rollout_storage(env: "Env", T: int, last_value: bool = False) -> dict:
                  tmp=torch.zeros(3 * M, **z))
     env.observe(b["obs"][0], b["mask"][0])
     return b
+
+
+def gov_policy_forward(mlp: "Mlp", K: int, gov_obs, scale, E: int, seed: int, ctr: int, levels, logp, val, ent,
+                       obs_bf16=None, logits=None, ctr_base=None, stream=None):
+    """ej_gov_policy_forward: the government's K tax levels per economy."""
+    check(lib().ej_gov_policy_forward(C.byref(mlp.desc), K, ptr(mlp.params), ptr(mlp.work), ptr(gov_obs), ptr(scale),
+                                      E, seed, ctr, ptr(ctr_base), ptr(levels), ptr(logp), ptr(val), ptr(ent),
+                                      ptr(obs_bf16), ptr(logits), stream_ptr(stream)), "ej_gov_policy_forward")
+
+
+def gov_ppo_workspace_bytes(mlp: "Mlp", K: int, rows: int) -> int:
+    out = C.c_int64()
+    check(lib().ej_gov_ppo_workspace_size(C.byref(mlp.desc), K, rows, C.byref(out)), "ej_gov_ppo_workspace_size")
+    return int(out.value)
+
+
+def gov_ppo_backward(mlp: "Mlp", K: int, storage: dict, M_total: int, perm_a: int, perm_c: int, row_begin: int,
+                     rows: int, hp: dict, workspace, grads, loss, stream=None):
+    """storage: torch tensors obs (bf16 rows), act (levels [M_total, K]), logp_old, val_old, adv, ret."""
+    if loss.numel() < PPO_LOSS_TERMS:
+        raise EconError(f"ej_gov_ppo_backward writes {PPO_LOSS_TERMS} loss terms; got {loss.numel()}")
+    b = EjPpoBatch(ptr(storage["obs"]), None, *(ptr(storage[k]) for k in ("act", "logp_old", "val_old", "adv", "ret")),
+                   M_total, perm_a, perm_c, row_begin, rows)
+    h = EjPpoHparams(hp["clip"], hp["vclip"], hp["vf_coef"], hp["ent_coef"])
+    check(lib().ej_gov_ppo_backward(C.byref(mlp.desc), K, ptr(mlp.params), ptr(mlp.work), C.byref(b), C.byref(h),
+                                    ptr(workspace), workspace.numel(), ptr(grads), ptr(loss), stream_ptr(stream)),
+          "ej_gov_ppo_backward")
+
+
+def sum_steps(x, t_begin: int, t_end: int, E: int, out, stream=None):
+    """out[e] = sum over t in [t_begin, t_end) of x[t, e] (ej_sum_steps)."""
+    check(lib().ej_sum_steps(ptr(x), t_begin, t_end, E, ptr(out), stream_ptr(stream)), "ej_sum_steps")

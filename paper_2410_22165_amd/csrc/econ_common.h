@@ -37,7 +37,14 @@ void set_last_hip_error(hipError_t e);
 // Philox4x64-10 (Salmon et al., SC'11), host and device.  Keys are
 // (seed, purpose); counters are four 64-bit words chosen per purpose.
 // ---------------------------------------------------------------------------
-enum : uint32_t { PURPOSE_SKILL = 1, PURPOSE_ENV = 2, PURPOSE_ACT = 3, PURPOSE_GOV = 4, PURPOSE_SAMPLE = 5 };
+enum : uint32_t {
+    PURPOSE_SKILL = 1,
+    PURPOSE_ENV = 2,
+    PURPOSE_ACT = 3,
+    PURPOSE_GOV = 4,
+    PURPOSE_SAMPLE = 5,
+    PURPOSE_GOV_SAMPLE = 6
+};
 
 struct u64x4 {
     uint64_t x, y, z, w;

@@ -768,6 +768,398 @@ static int launch_rows(const MlpDims& d, const float* params, const uint16_t* wo
     return EJ_OK;
 }
 
+
+// ===========================================================================
+// The government's policy (Sec. 3 "Government Agent", "Setting tax rates"):
+// the same two-hidden-layer network on the economy's government
+// observation, with K independent categorical heads of 21 tax levels (a
+// multi-discrete action, the logits of bracket k at columns 21 k .. 21 k +
+// 20) and the value at column 21 K.  log pi(levels) is the sum of the K heads'
+// log-probabilities and the entropy the sum of theirs.  One row per economy;
+// at most 12 brackets (21 K + 1 <= 256) and H <= 256.
+// ===========================================================================
+constexpr int GOV_LEVELS = EJ_GOV_LEVELS;
+constexpr int GOV_MAXK = 12;
+constexpr int GOV_A1P = 256;  // logits + value, padded (two 128-column chunks)
+constexpr int GOV_LS = GOV_A1P + 4;  // fp32 row stride of the full logit tile
+constexpr int GOV_YS = GOV_A1P + 8;  // bf16 row stride of the dY tile
+
+// government observation rows: fp32 features times their scale, rounded to
+// bf16, zero beyond D -> LDS tile [64][hs] (columns < K1P) and, when `out`
+// is given, the bf16 rows [rows][Ds] the learner stores
+__device__ inline void gov_load_obs(const float* __restrict__ gobs, const float* __restrict__ scale, int64_t row0,
+                                    int64_t E, int D, int Ds, uint16_t* hbuf, int hs, uint16_t* __restrict__ out)
+{
+    for (int p = threadIdx.x; p < 64 * K1P; p += blockDim.x) {
+        const int r = p / K1P, c = p - r * K1P;
+        const int64_t e = row0 + r;
+        uint16_t v = 0;
+        if (e < E && c < D) v = f32_to_bf16(gobs[e * D + c] * scale[c]);
+        hbuf[r * hs + c] = v;
+        if (out && e < E && c < Ds) out[e * Ds + c] = v;
+    }
+}
+
+// the K heads of one row: max, sum of exp(z - m) and sum of exp(z - m)(z - m)
+// over the 21 levels of head k (fp32, level order)
+__device__ inline void gov_head_stats(const float* z, float& m, float& S, float& T)
+{
+    m = z[0];
+#pragma unroll
+    for (int j = 1; j < GOV_LEVELS; ++j) m = fmaxf(m, z[j]);
+    S = 0.f;
+    T = 0.f;
+#pragma unroll
+    for (int j = 0; j < GOV_LEVELS; ++j) {
+        const float dz = z[j] - m;
+        const float e = __expf(dz);
+        S += e;
+        T += e * dz;
+    }
+}
+
+// Forward and sampling for 64 economies per workgroup: the network as in the
+// population policy (column-split bf16 MFMA layers), the full logit row in
+// LDS (fp32), then one thread per (economy, bracket): the head's softmax and
+// an inverse-CDF draw in level order with the uniform of word k % 4 of
+// Philox(GOV_SAMPLE; seed; economy, ctr, k / 4).
+template <int H>
+__global__ void __launch_bounds__(256)
+gov_forward_kernel(const MlpDims d, int K, const float* __restrict__ params, const uint16_t* __restrict__ work,
+                   const float* __restrict__ gobs, const float* __restrict__ scale, int64_t E, uint64_t seed,
+                   uint64_t ctr_arg, const uint64_t* __restrict__ ctr_base, int32_t* __restrict__ levels,
+                   float* __restrict__ logp, float* __restrict__ val, float* __restrict__ ent,
+                   uint16_t* __restrict__ obs_out, float* __restrict__ logits)
+{
+    constexpr int TILE = 64, TR = 4, HS = H + 8, CTW = H / 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* hbuf = (uint16_t*)smem;                  // [64][HS]
+    float* lbuf = (float*)(hbuf + TILE * HS);          // [64][GOV_LS]
+    float* hl = lbuf + TILE * GOV_LS;                  // [64][GOV_MAXK] log-probabilities of the draws
+    float* he = hl + TILE * GOV_MAXK;                  // [64][GOV_MAXK] head entropies
+    float* sb3 = he + TILE * GOV_MAXK;                 // [GOV_A1P]
+    const uint64_t ctr = ctr_arg + (ctr_base ? *ctr_base : 0ull);
+    const int wave = threadIdx.x >> 6, l = lane_id();
+    const int64_t row0 = (int64_t)blockIdx.x * TILE;
+    gov_load_obs(gobs, scale, row0, E, d.D, d.Ds, hbuf, HS, obs_out);
+    for (int p = threadIdx.x; p < GOV_A1P; p += 256) sb3[p] = p < d.A1 ? params[d.ob3 + p] : 0.f;
+    {
+        const int col0 = wave * (H / 4);
+        f32x4 acc[TR][CTW];
+        bias_init_t<TR, CTW>(acc, params + d.ob1, col0);
+        lds_barrier();
+        dense_cs<TR, CTW, 2, false, 2, false, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);
+        lds_barrier();
+        relu_store_t<TR, CTW>(acc, hbuf, HS, col0);
+        bias_init_t<TR, CTW>(acc, params + d.ob2, col0);
+        lds_barrier();
+        dense_cs<TR, CTW, H / 32, false, 2, false, true>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
+        lds_barrier();
+        relu_store_t<TR, CTW>(acc, hbuf, HS, col0);
+        lds_barrier();
+    }
+    for (int c = 0; c < d.NC; ++c) {
+        f32x4 acc3[TR][2];
+        dense_cs<TR, 2, H / 32, true, 2, false, true>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32,
+                                                      (int64_t)d.A1p * 32, 32 * wave);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int cc = c * 128 + 32 * wave + ct * 16 + 4 * (l >> 4);
+#pragma unroll
+            for (int rt = 0; rt < TR; ++rt)
+                *(float4*)(lbuf + (rt * 16 + (l & 15)) * GOV_LS + cc) =
+                    float4{acc3[rt][ct][0] + sb3[cc], acc3[rt][ct][1] + sb3[cc + 1], acc3[rt][ct][2] + sb3[cc + 2],
+                           acc3[rt][ct][3] + sb3[cc + 3]};
+        }
+    }
+    lds_barrier();
+    if (logits) {
+        const int A = d.A;
+        for (int p = threadIdx.x; p < TILE * A; p += 256) {
+            const int r = p / A, c = p - r * A;
+            if (row0 + r < E) logits[(row0 + r) * A + c] = lbuf[r * GOV_LS + c];
+        }
+    }
+    for (int idx = threadIdx.x; idx < TILE * K; idx += 256) {
+        const int r = idx / K, k = idx - r * K;
+        const int64_t e = row0 + r;
+        if (e >= E) continue;
+        const float* z = lbuf + r * GOV_LS + k * GOV_LEVELS;
+        float m, S, T;
+        gov_head_stats(z, m, S, T);
+        const u64x4 w = philox(seed, PURPOSE_GOV_SAMPLE, (uint64_t)e, ctr, (uint64_t)(k >> 2), 0);
+        const float u = unif24(word_of(w, k & 3));
+        const float target = u * S;
+        float cum = 0.f;
+        int j = GOV_LEVELS - 1;
+#pragma unroll
+        for (int q = 0; q < GOV_LEVELS; ++q) {
+            cum += __expf(z[q] - m);
+            if (cum > target) {
+                j = q;
+                break;
+            }
+        }
+        const float lS = __logf(S);
+        levels[e * K + k] = j;
+        hl[r * GOV_MAXK + k] = z[j] - m - lS;
+        he[r * GOV_MAXK + k] = lS - T / S;
+    }
+    lds_barrier();
+    if (threadIdx.x < TILE) {
+        const int r = threadIdx.x;
+        const int64_t e = row0 + r;
+        if (e < E) {
+            float a = 0.f, b = 0.f;
+            for (int k = 0; k < K; ++k) {  // bracket order
+                a += hl[r * GOV_MAXK + k];
+                b += he[r * GOV_MAXK + k];
+            }
+            logp[e] = a;
+            ent[e] = b;
+            val[e] = lbuf[r * GOV_LS + d.A];
+        }
+    }
+}
+
+// One fused pass over 64 minibatch rows of the government's PPO loss: the
+// forward recomputed (its bf16 products and ReLU patterns kept), the full
+// logit row in LDS, the K heads' softmax statistics, the per-row loss terms
+// (ratio of the summed log-probabilities), dY = dL/d[logits | value] with
+// dL/dz_kj = c_pg (1[j = a_k] - p_kj) + c_e/n p_kj (log p_kj + H_k), then
+// dh2 and dh1 as in the population's kernel; every GEMM operand of the
+// weight gradients leaves as bf16 m-blocks for dw_kernel.
+template <int H>
+__global__ void __launch_bounds__(256, 1)
+gov_rows_kernel(const MlpDims d, int K, const float* __restrict__ params, const uint16_t* __restrict__ work,
+                const PpoBatchDev B, const PpoHp hp, const float* __restrict__ stats, uint16_t* __restrict__ Tobs,
+                uint16_t* __restrict__ Th1, uint16_t* __restrict__ Th2, uint16_t* __restrict__ TdY,
+                uint16_t* __restrict__ Tdh2, uint16_t* __restrict__ Tdh1, float* __restrict__ loss_parts)
+{
+    constexpr int TILE = 64, TR = 4, HS = H + 8, CTW = H / 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* hbuf = (uint16_t*)smem;                      // [64][HS] obs -> h1 -> h2 -> dh2
+    uint16_t* ybuf = hbuf + TILE * HS;                     // [64][GOV_YS] dY (bf16)
+    float* lbuf = (float*)(ybuf + TILE * GOV_YS);          // [64][GOV_LS] logits
+    float* rinfo = lbuf + TILE * GOV_LS;                   // [5][64] logp_old, val_old, adv_hat, ret, valid
+    float* hm = rinfo + 5 * TILE;                          // [64][GOV_MAXK] head max
+    float* hls = hm + TILE * GOV_MAXK;                     // [64][GOV_MAXK] log sum exp(z - max)
+    float* hH = hls + TILE * GOV_MAXK;                     // [64][GOV_MAXK] head entropy
+    float* hlp = hH + TILE * GOV_MAXK;                     // [64][GOV_MAXK] log-probability of the taken level
+    int32_t* lvl = (int32_t*)(hlp + TILE * GOV_MAXK);      // [64][GOV_MAXK] taken levels
+    float* coef = (float*)(lvl + TILE * GOV_MAXK);         // [64][3] c_pg, dL/dV, entropy of the row
+    float* lred = coef + TILE * 3;                         // [4 waves][4]
+    float* sbias = lred + 64;                              // b1 [H], b2 [H], b3 [GOV_A1P]
+
+    const int wave = threadIdx.x >> 6, l = lane_id();
+    const int64_t tile_row0 = (int64_t)blockIdx.x * TILE;
+    const float inv_n = 1.0f / (float)B.rows;
+    const int col0 = wave * (H / 4);
+
+    for (int r = threadIdx.x; r < TILE; r += 256) {
+        const int64_t j = tile_row0 + r;
+        float lpo = 0.f, vo = 0.f, ah = 0.f, rt = 0.f, valid = 0.f;
+        if (j < B.rows) {
+            const int64_t sidx = sample_of(B, j);
+            lpo = B.logp_old[sidx];
+            vo = B.val_old[sidx];
+            ah = (B.adv[sidx] - stats[0]) * stats[1];
+            rt = B.ret[sidx];
+            valid = 1.f;
+        }
+        rinfo[0 * TILE + r] = lpo;
+        rinfo[1 * TILE + r] = vo;
+        rinfo[2 * TILE + r] = ah;
+        rinfo[3 * TILE + r] = rt;
+        rinfo[4 * TILE + r] = valid;
+    }
+    for (int p = threadIdx.x; p < TILE * K; p += 256) {
+        const int r = p / K, k = p - r * K;
+        const int64_t j = tile_row0 + r;
+        lvl[r * GOV_MAXK + k] = j < B.rows ? B.act[sample_of(B, j) * K + k] : 0;
+    }
+    for (int p = threadIdx.x; p < 2 * H + GOV_A1P; p += 256)
+        sbias[p] = p < H ? params[d.ob1 + p]
+                         : p < 2 * H ? params[d.ob2 + p - H] : (p - 2 * H < d.A1 ? params[d.ob3 + p - 2 * H] : 0.f);
+    for (int p = threadIdx.x; p < TILE * (K1P / 8); p += 256) {
+        const int r = p >> 3, cc = p & 7;
+        const int64_t j = tile_row0 + r;
+        const uint4 v = (j < B.rows && cc * 8 < d.Ds) ? *(const uint4*)(B.obs + sample_of(B, j) * d.Ds + cc * 8)
+                                                       : uint4{0u, 0u, 0u, 0u};
+        *(uint4*)(hbuf + r * HS + cc * 8) = v;
+    }
+    lds_barrier();
+    const int64_t mb0 = tile_row0 >> 5;
+    tile_to_mblocks(hbuf, HS, TILE, d.K1p, Tobs, mb0, d.K1p, 0);
+
+    f32x4 acc[TR][CTW];
+    uint32_t m1[TR], m2[TR];
+    dense_cs<TR, CTW, 2, true, 2, true, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);
+    lds_barrier();
+    ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias, hbuf, HS, col0, m1);
+    lds_barrier();
+    tile_to_mblocks(hbuf, HS, TILE, H, Th1, mb0, H, 0);
+    dense_cs<TR, CTW, H / 32, true, 3, true, true>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
+    lds_barrier();
+    ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias + H, hbuf, HS, col0, m2);
+    lds_barrier();
+    tile_to_mblocks(hbuf, HS, TILE, H, Th2, mb0, H, 0);
+
+    for (int c = 0; c < d.NC; ++c) {
+        f32x4 acc3[TR][2];
+        dense_cs<TR, 2, H / 32, true, 3, true, true>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32,
+                                                      (int64_t)d.A1p * 32, 32 * wave);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int cc = c * 128 + 32 * wave + ct * 16 + 4 * (l >> 4);
+            const float* b3 = sbias + 2 * H + cc;
+#pragma unroll
+            for (int rt = 0; rt < TR; ++rt)
+                *(float4*)(lbuf + (rt * 16 + (l & 15)) * GOV_LS + cc) =
+                    float4{acc3[rt][ct][0] + b3[0], acc3[rt][ct][1] + b3[1], acc3[rt][ct][2] + b3[2],
+                           acc3[rt][ct][3] + b3[3]};
+        }
+    }
+    lds_barrier();
+    // heads: softmax statistics and the taken level's log-probability
+    for (int idx = threadIdx.x; idx < TILE * K; idx += 256) {
+        const int r = idx / K, k = idx - r * K;
+        const float* z = lbuf + r * GOV_LS + k * GOV_LEVELS;
+        float m, S, T;
+        gov_head_stats(z, m, S, T);
+        const float lS = __logf(S);
+        int a = lvl[r * GOV_MAXK + k];
+        a = a < 0 ? 0 : (a >= GOV_LEVELS ? GOV_LEVELS - 1 : a);
+        hm[r * GOV_MAXK + k] = m;
+        hls[r * GOV_MAXK + k] = lS;
+        hH[r * GOV_MAXK + k] = lS - T / S;
+        hlp[r * GOV_MAXK + k] = z[a] - m - lS;
+    }
+    lds_barrier();
+    // rows: ratio, loss terms and the coefficients of dY
+    {
+        float part_pg = 0.f, part_vf = 0.f, part_ent = 0.f, part_clip = 0.f;
+        if (threadIdx.x < TILE) {
+            const int r = threadIdx.x;
+            const bool valid = rinfo[4 * TILE + r] != 0.f;
+            float lp = 0.f, H_ = 0.f;
+            for (int k = 0; k < K; ++k) {
+                lp += hlp[r * GOV_MAXK + k];
+                H_ += hH[r * GOV_MAXK + k];
+            }
+            const float ratio = __expf(lp - rinfo[0 * TILE + r]);
+            const float ah = rinfo[2 * TILE + r];
+            const float s1 = ratio * ah;
+            const float rc = fminf(fmaxf(ratio, 1.f - hp.clip), 1.f + hp.clip);
+            const float s2 = rc * ah;
+            const bool active = !(s1 > s2);
+            const float V = lbuf[r * GOV_LS + d.A], vo = rinfo[1 * TILE + r], R = rinfo[3 * TILE + r];
+            const float dvv = V - vo;
+            const float vc = vo + fminf(fmaxf(dvv, -hp.vclip), hp.vclip);
+            const float l1 = (V - R) * (V - R), l2 = (vc - R) * (vc - R);
+            const float gv = l1 >= l2 ? (V - R) : ((dvv >= -hp.vclip && dvv <= hp.vclip) ? (vc - R) : 0.f);
+            coef[r * 3 + 0] = valid ? (active ? -ah * ratio : 0.f) * inv_n : 0.f;
+            coef[r * 3 + 1] = valid ? hp.vf_coef * gv * inv_n : 0.f;
+            coef[r * 3 + 2] = valid ? 1.f : 0.f;
+            if (valid) {
+                part_pg = -fminf(s1, s2);
+                part_vf = 0.5f * fmaxf(l1, l2);
+                part_ent = H_;
+                part_clip = fabsf(ratio - 1.f) > hp.clip ? 1.f : 0.f;
+            }
+        }
+        part_pg = wave_sum(part_pg);
+        part_vf = wave_sum(part_vf);
+        part_ent = wave_sum(part_ent);
+        part_clip = wave_sum(part_clip);
+        if (l == 0) {
+            lred[wave * 4 + 0] = part_pg;
+            lred[wave * 4 + 1] = part_vf;
+            lred[wave * 4 + 2] = part_ent;
+            lred[wave * 4 + 3] = part_clip;
+        }
+    }
+    lds_barrier();
+    // dY (bf16): the heads' columns, the value column, zero padding
+    const float cent = hp.ent_coef * inv_n;
+    const int KL = K * GOV_LEVELS;
+    for (int p = threadIdx.x; p < TILE * (GOV_A1P / 2); p += 256) {
+        const int r = p / (GOV_A1P / 2), c0 = 2 * (p - r * (GOV_A1P / 2));
+        uint32_t pk = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int col = c0 + h;
+            float g = 0.f;
+            if (coef[r * 3 + 2] != 0.f) {
+                if (col < KL) {
+                    const int k = col / GOV_LEVELS, j = col - k * GOV_LEVELS;
+                    const float lp = lbuf[r * GOV_LS + col] - hm[r * GOV_MAXK + k] - hls[r * GOV_MAXK + k];
+                    const float pj = __expf(lp);
+                    const float taken = j == lvl[r * GOV_MAXK + k] ? 1.f : 0.f;
+                    g = coef[r * 3 + 0] * (taken - pj) + cent * pj * (lp + hH[r * GOV_MAXK + k]);
+                } else if (col == KL) {
+                    g = coef[r * 3 + 1];
+                }
+            }
+            pk |= (uint32_t)f32_to_bf16(g) << (16 * h);
+        }
+        *(uint32_t*)(ybuf + r * GOV_YS + c0) = pk;
+    }
+    lds_barrier();
+    tile_to_mblocks(ybuf, GOV_YS, TILE, d.A1p, TdY, mb0, d.A1p, 0);
+    // dh2 = (dY W3^T) * [h2 > 0], chunk by chunk of 128 logit columns
+    f32x4 dh[TR][CTW];
+    for (int c = 0; c < d.NC; ++c) {
+        if (c == 0)
+            dense_cs<TR, CTW, 4, true, 3, true, true>(dh, ybuf, GOV_YS, work + d.oW3b, (int64_t)H * 32, col0);
+        else
+            dense_cs<TR, CTW, 4, false, 3, true, true>(dh, ybuf + c * 128, GOV_YS, work + d.oW3b + (int64_t)c * 4 * H * 32,
+                                                       (int64_t)H * 32, col0);
+    }
+    lds_barrier();  // the activations h2 are no longer read
+    ppo_masked_grad_cs<TR, CTW>(dh, m2, hbuf, HS, col0);
+    lds_barrier();
+    tile_to_mblocks(hbuf, HS, TILE, H, Tdh2, mb0, H, 0);
+    dense_cs<TR, CTW, H / 32, true, 3, true, true>(dh, hbuf, HS, work + d.oW2b, (int64_t)H * 32, col0);
+    lds_barrier();
+    ppo_masked_grad_cs<TR, CTW>(dh, m1, hbuf, HS, col0);
+    lds_barrier();
+    tile_to_mblocks(hbuf, HS, TILE, H, Tdh1, mb0, H, 0);
+    if (threadIdx.x < 4) {
+        float sum = 0.f;
+        for (int w = 0; w < 4; ++w) sum += lred[w * 4 + threadIdx.x];
+        loss_parts[(int64_t)blockIdx.x * 4 + threadIdx.x] = sum;
+    }
+}
+
+template <int H>
+size_t gov_forward_lds_bytes()
+{
+    return (size_t)64 * (H + 8) * 2 + (size_t)64 * GOV_LS * 4 + 2 * (size_t)64 * GOV_MAXK * 4 + GOV_A1P * 4;
+}
+
+template <int H>
+size_t gov_rows_lds_bytes()
+{
+    return (size_t)64 * (H + 8) * 2 + (size_t)64 * GOV_YS * 2 + (size_t)64 * GOV_LS * 4 + 5 * 64 * 4 +
+           5 * (size_t)64 * GOV_MAXK * 4 + 64 * 3 * 4 + 64 * 4 + (size_t)(2 * H + GOV_A1P) * 4;
+}
+
+__global__ void sum_steps_kernel(const float* __restrict__ x, int t0, int t1, int64_t E, float* __restrict__ out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int t = t0; t < t1; ++t) s += x[(int64_t)t * E + e];
+        out[e] = s;
+    }
+}
+
+static int gov_dims(const ej_mlp_desc* m, int32_t K, MlpDims* d)
+{
+    if (!m || K < 1 || K > GOV_MAXK || m->A != K * GOV_LEVELS) return EJ_EINVAL;
+    if (m->H > 256) return EJ_EUNSUPPORTED;
+    return mlp_dims(m->D, m->D_stride, m->H, m->A, d);
+}
 }  // namespace econ
 
 using namespace econ;
@@ -798,6 +1190,9 @@ int ej_ppo_workspace_size(const ej_mlp_desc* m, int64_t rows, int64_t* bytes)
     *bytes = (int64_t)w.bytes;
     return EJ_OK;
 }
+
+static int ppo_weight_grads_and_loss(const MlpDims& d, const PpoWorkspace& w, unsigned char* ws, int64_t rows,
+                                     const ej_ppo_hparams& hp, float* d_grads, float* d_loss, hipStream_t st);
 
 static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work,
                              const ej_ppo_batch* b, const ej_ppo_hparams* hp, void* d_workspace,
@@ -843,6 +1238,18 @@ static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const 
     default: rc = launch_rows<512>(d, d_params, d_work, B, h, stats, W, T, lparts, w.ntiles, st); break;
     }
     if (rc != EJ_OK) return rc;
+    return ppo_weight_grads_and_loss(d, w, ws, b->rows, *hp, d_grads, d_loss, st);
+}
+
+// weight gradients from the m-blocks (dW GEMMs, fixed-order reduction) and
+// the minibatch means of the loss terms from the per-tile partial sums
+static int ppo_weight_grads_and_loss(const MlpDims& d, const PpoWorkspace& w, unsigned char* ws, int64_t rows,
+                                     const ej_ppo_hparams& hp, float* d_grads, float* d_loss, hipStream_t st)
+{
+    int rc = EJ_OK;
+    uint16_t* T[6] = {(uint16_t*)(ws + w.o_obs), (uint16_t*)(ws + w.o_h1), (uint16_t*)(ws + w.o_h2),
+                      (uint16_t*)(ws + w.o_dy), (uint16_t*)(ws + w.o_dh2), (uint16_t*)(ws + w.o_dh1)};
+    float* lparts = (float*)(ws + w.o_loss);
     float *p1 = (float*)(ws + w.o_p1), *p2 = (float*)(ws + w.o_p2), *p3 = (float*)(ws + w.o_p3);
     float *c1 = (float*)(ws + w.o_c1), *c2 = (float*)(ws + w.o_c2), *c3 = (float*)(ws + w.o_c3);
     const int G = (int)w.G;
@@ -863,9 +1270,111 @@ static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const 
     double* lslices = (double*)(ws + w.o_lslices);
     loss_slices_kernel<<<nslices, 256, 0, st>>>(lparts, (int)w.ntiles, nslices, lslices);
     EJ_LAUNCH_CHECK();
-    loss_final_kernel<<<1, 256, 0, st>>>(lslices, nslices, b->rows, hp->vf_coef, hp->ent_coef, d_loss);
+    loss_final_kernel<<<1, 256, 0, st>>>(lslices, nslices, rows, hp.vf_coef, hp.ent_coef, d_loss);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
+}
+
+int ej_gov_policy_forward(const ej_mlp_desc* m, int32_t K, const float* d_params, const uint16_t* d_work,
+                          const float* d_gov_obs, const float* d_scale, int64_t E, uint64_t seed, uint64_t ctr,
+                          const uint64_t* d_ctr_base, int32_t* d_levels, float* d_logp, float* d_val, float* d_ent,
+                          uint16_t* d_obs_bf16, float* d_logits, void* stream)
+{
+    MlpDims d;
+    int rc = gov_dims(m, K, &d);
+    if (rc != EJ_OK) return rc;
+    if (!d_params || !d_work || !d_gov_obs || !d_scale || !d_levels || !d_logp || !d_val || !d_ent || E < 0)
+        return EJ_EINVAL;
+    if (!aligned16(d_params) || !aligned16(d_work)) return EJ_EINVAL;
+    if (E == 0) return EJ_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned blocks = (unsigned)((E + 63) / 64);
+#define EJ_GOV_FWD(HH)                                                                                              \
+    gov_forward_kernel<HH><<<blocks, 256, gov_forward_lds_bytes<HH>(), st>>>(d, K, d_params, d_work, d_gov_obs,    \
+                                                                              d_scale, E, seed, ctr, d_ctr_base,    \
+                                                                              d_levels, d_logp, d_val, d_ent,       \
+                                                                              d_obs_bf16, d_logits)
+    switch (m->H) {
+    case 64: EJ_GOV_FWD(64); break;
+    case 128: EJ_GOV_FWD(128); break;
+    default: EJ_GOV_FWD(256); break;
+    }
+#undef EJ_GOV_FWD
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+int ej_sum_steps(const float* d_x, int32_t t_begin, int32_t t_end, int64_t E, float* d_out, void* stream)
+{
+    if (!d_x || !d_out || t_begin < 0 || t_end < t_begin || E < 0) return EJ_EINVAL;
+    if (E == 0) return EJ_OK;
+    int64_t blocks = (E + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    sum_steps_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(d_x, t_begin, t_end, E, d_out);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+int ej_gov_ppo_workspace_size(const ej_mlp_desc* m, int32_t K, int64_t rows, int64_t* bytes)
+{
+    MlpDims d;
+    int rc = gov_dims(m, K, &d);
+    if (rc != EJ_OK) return rc;
+    if (!bytes || rows <= 0) return EJ_EINVAL;
+    PpoWorkspace w;
+    ppo_workspace(d, rows, &w);
+    *bytes = (int64_t)w.bytes;
+    return EJ_OK;
+}
+
+int ej_gov_ppo_backward(const ej_mlp_desc* m, int32_t K, const float* d_params, const uint16_t* d_work,
+                        const ej_ppo_batch* b, const ej_ppo_hparams* hp, void* d_workspace, int64_t workspace_bytes,
+                        float* d_grads, float* d_loss, void* stream)
+{
+    MlpDims d;
+    int rc = gov_dims(m, K, &d);
+    if (rc != EJ_OK) return rc;
+    if (!d_params || !d_work || !b || !hp || !d_workspace || !d_grads || !d_loss) return EJ_EINVAL;
+    if (!b->obs || !b->act || !b->logp_old || !b->val_old || !b->adv || !b->ret) return EJ_EINVAL;
+    if (!aligned16(d_params) || !aligned16(d_work) || !aligned16(b->obs) || !aligned16(d_workspace) ||
+        !aligned16(d_grads))
+        return EJ_EINVAL;
+    if (b->M_total <= 0 || b->M_total > INT32_MAX || b->rows <= 0 || b->perm_a <= 0 || b->perm_c < 0 ||
+        b->row_begin < 0 || b->row_begin + b->rows > INT32_MAX)
+        return EJ_EINVAL;
+    PpoWorkspace w;
+    ppo_workspace(d, b->rows, &w);
+    if (workspace_bytes < (int64_t)w.bytes) return EJ_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char* ws = (unsigned char*)d_workspace;
+    const int64_t a = b->M_total == 1 ? 1 : b->perm_a % b->M_total;
+    if (a == 0) return EJ_EINVAL;
+    PpoBatchDev B{b->obs, nullptr, b->act, b->logp_old, b->val_old, b->adv, b->ret, b->M_total, a,
+                  b->perm_c % b->M_total, b->row_begin, b->rows, UINT64_MAX / (uint64_t)b->M_total};
+    PpoHp h{hp->clip, hp->vclip, hp->vf_coef, hp->ent_coef};
+    double* advp = (double*)(ws + w.o_adv);
+    float* stats = (float*)(ws + w.o_stats);
+    int nb = (int)((b->rows + 255) / 256);
+    if (nb > 1024) nb = 1024;
+    adv_stats_partial<<<nb, 256, 0, st>>>(B, advp);
+    EJ_LAUNCH_CHECK();
+    adv_stats_final<<<1, 256, 0, st>>>(advp, nb, b->rows, stats);
+    EJ_LAUNCH_CHECK();
+    uint16_t* T[6] = {(uint16_t*)(ws + w.o_obs), (uint16_t*)(ws + w.o_h1), (uint16_t*)(ws + w.o_h2),
+                      (uint16_t*)(ws + w.o_dy), (uint16_t*)(ws + w.o_dh2), (uint16_t*)(ws + w.o_dh1)};
+    float* lparts = (float*)(ws + w.o_loss);
+#define EJ_GOV_ROWS(HH)                                                                                              \
+    gov_rows_kernel<HH><<<(unsigned)w.ntiles, 256, gov_rows_lds_bytes<HH>(), st>>>(d, K, d_params, d_work, B, h,     \
+                                                                                    stats, T[0], T[1], T[2], T[3],   \
+                                                                                    T[4], T[5], lparts)
+    switch (m->H) {
+    case 64: EJ_GOV_ROWS(64); break;
+    case 128: EJ_GOV_ROWS(128); break;
+    default: EJ_GOV_ROWS(256); break;
+    }
+#undef EJ_GOV_ROWS
+    EJ_LAUNCH_CHECK();
+    return ppo_weight_grads_and_loss(d, w, ws, b->rows, *hp, d_grads, d_loss, st);
 }
 
 int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const ej_ppo_batch* b,

@@ -78,7 +78,7 @@ class PPOTrainer:
     def __init__(self, env_cfg: dict, scales: dict, hidden: int, rollout: int, epochs: int, minibatches: int,
                  gamma: float, lam: float, clip: float, vf_coef: float, vclip: float, ent_coef: float, lr: float,
                  seed: int = 0, weights: dict | None = None, n_per_env=None, total_updates: int = 1,
-                 groups: int = 1):
+                 groups: int = 1, gov_learning: bool = False, gov_hidden: int = 128):
         import workloads as W
         self.env = binding.Env(env_cfg, scales, n_per_env)
         e = self.env
@@ -106,12 +106,18 @@ class PPOTrainer:
         self.ctr_base = torch.zeros(1, dtype=torch.int64, device="cuda")
         self.updates = 0
         self.adam_step = 0
-        self.env.set_gov_draw(True, seed + 1)
+        self.gov = None
+        if gov_learning:
+            self.gov = GovLearner(self, env_cfg, gov_hidden, seed)
+            self.rollout = None
+        else:
+            self.env.set_gov_draw(True, seed + 1)
         self.env.observe(self.store.obs[0], self.store.mask[0])
-        # the whole rollout as one HIP graph captured by the library, the
-        # economies pipelined over `groups` streams
-        self.rollout = binding.Rollout(self.env, self.mlp, self.store.buffers(self.ctr_base), rollout, seed,
-                                       groups=groups, last_value=True, gamma=gamma, lam=lam)
+        if not gov_learning:
+            # the whole rollout as one HIP graph captured by the library, the
+            # economies pipelined over `groups` streams
+            self.rollout = binding.Rollout(self.env, self.mlp, self.store.buffers(self.ctr_base), rollout, seed,
+                                           groups=groups, last_value=True, gamma=gamma, lam=lam)
 
     # ---- rollout ----
     def collect(self, graph: bool = False):
@@ -120,7 +126,9 @@ class PPOTrainer:
         step, seed + 1), the last value and GAE.  graph=True replays the
         captured HIP graph; graph=False issues the same launches one by one
         (identical results)."""
-        if graph:
+        if self.gov is not None:
+            self.gov.collect()
+        elif graph:
             self.rollout.launch()
         else:
             self.rollout.launch_plain()
@@ -145,6 +153,8 @@ class PPOTrainer:
                 self.adam_step += 1
                 binding.adam(self.mlp.params, self.grads, self.adam_m, self.adam_v, self.adam_step, max(lr, 1e-12))
                 self.mlp.sync()
+        if self.gov is not None:
+            self.gov.update(lr, ent)
         self.updates += 1
         self.next_rollout()
 
@@ -154,5 +164,121 @@ class PPOTrainer:
         self.store.mask[0].copy_(self.store.mask[self.T])
 
     def close(self):
-        self.rollout.close()
+        if self.rollout is not None:
+            self.rollout.close()
         self.env.close()
+
+
+class GovLearner:
+    """The government agent trained at the same time as the population
+    (Sec. 3 "Government Agent", "Setting tax rates"; Sec. 4 "Experimental
+    details"): at the first step of every tax period its policy
+    (ej_gov_policy_forward) reads each economy's government observation and
+    sets the K bracket levels the economy step applies.  A decision's reward
+    is the sum of the per-step government rewards until the next decision
+    (ej_sum_steps, within the rollout); GAE runs over the decisions of the
+    rollout (ej_gae), bootstrapped with the value of the state after it, and
+    the update is the PPO loss of the K-head policy (ej_gov_ppo_backward) with
+    Adam.  The rollout is issued from the host, one launch per kernel."""
+
+    def __init__(self, tr: "PPOTrainer", env_cfg: dict, hidden: int, seed: int):
+        import workloads as W
+        e = tr.env
+        self.tr, self.K = tr, e.K
+        self.Dg = e.Dg
+        self.Dgs = (e.Dg + 7) // 8 * 8
+        self.E, self.P_tax, self.T_ep = e.E, env_cfg["P_tax"], env_cfg["T"]
+        self.seed = seed + 2
+        A = 21 * self.K
+        self.mlp = binding.Mlp(self.Dg, self.Dgs, hidden, A, W.policy_weights(self.Dg, hidden, A, seed=seed + 3))
+        self.scale = torch.from_numpy(W.gov_obs_scales(env_cfg)).cuda()
+        z = dict(device="cuda")
+        T = tr.T
+        self.Dmax = T // self.P_tax + 2  # decisions per rollout at most
+        D, E, K = self.Dmax, self.E, self.K
+        self.obs = torch.zeros((D, E, self.Dgs), dtype=torch.int16, **z)
+        self.lv = torch.zeros((D, E, K), dtype=torch.int32, **z)
+        self.logp = torch.zeros((D, E), **z)
+        self.val = torch.zeros((D, E), **z)
+        self.ent = torch.zeros((D, E), **z)
+        self.rew = torch.zeros((D, E), **z)
+        self.done = torch.zeros((D, E), dtype=torch.uint8, **z)
+        self.adv = torch.zeros((D, E), **z)
+        self.ret = torch.zeros((D, E), **z)
+        self.last_val = torch.zeros(E, **z)
+        self.gov_obs = torch.zeros((E, self.Dg), **z)
+        self.scratch_obs = torch.zeros((tr.M, tr.Ds), dtype=torch.int16, **z)
+        self.scratch_mask = torch.zeros((tr.M, tr.Wm), dtype=torch.int32, **z)
+        self.tmp_i = torch.zeros((E, K), dtype=torch.int32, **z)
+        self.tmp_f = torch.zeros((3, E), **z)
+        n = self.mlp.layout["n_params"]
+        self.grads = torch.zeros(n, **z)
+        self.adam_m = torch.zeros(n, **z)
+        self.adam_v = torch.zeros(n, **z)
+        self.adam_step = 0
+        self.loss_terms = torch.zeros(binding.PPO_LOSS_TERMS, **z)
+        self.t_env = int(e.get_state()["t"][0])  # every economy shares the episode clock
+        self.levels = torch.zeros(max(E * K, 1), dtype=torch.int32, **z)  # the levels in force
+        self.n_dec = 0
+        self.decisions = 0  # sampling counter
+
+    def _observe(self):
+        tr = self.tr
+        tr.env.observe(self.scratch_obs, self.scratch_mask, self.gov_obs)
+
+    def collect(self):
+        tr, s = self.tr, self.tr.store
+        starts = []
+        for t in range(tr.T):
+            if self.t_env % self.P_tax == 0:
+                d = len(starts)
+                self._observe()
+                binding.gov_policy_forward(self.mlp, self.K, self.gov_obs, self.scale, self.E, self.seed,
+                                           self.decisions, self.lv[d], self.logp[d], self.val[d], self.ent[d],
+                                           obs_bf16=self.obs[d])
+                self.levels.copy_(self.lv[d].reshape(-1))
+                self.decisions += 1
+                starts.append(t)
+            tr.mlp.forward(s.obs[t], s.mask[t], tr.M, tr.seed, t, s.act[t], s.logp[t], s.val[t], s.ent[t],
+                           ctr_base=tr.ctr_base)
+            tr.env.step(s.act[t], self.levels, s.rew[t], s.gov_rew[t], s.done[t], s.obs[t + 1], s.mask[t + 1])
+            self.t_env = (self.t_env + 1) % self.T_ep
+        tr.mlp.forward(s.obs[tr.T], s.mask[tr.T], tr.M, tr.seed, tr.T, s.tmp[2 * tr.M:].view(torch.int32),
+                       s.tmp[:tr.M], s.last_val, s.tmp[tr.M:2 * tr.M], ctr_base=tr.ctr_base)
+        binding.gae(s.rew, s.val, s.done, s.last_val, tr.T, tr.M, tr.gamma, tr.lam, s.adv, s.ret)
+        binding.counter_add(tr.ctr_base, tr.T + 1)
+        # decisions: rewards summed over their periods, episode ends, bootstrap value
+        self.n_dec = len(starts)
+        ends = starts[1:] + [tr.T]
+        done_host = s.done[:, 0].cpu().numpy()  # every economy ends its episode at the same step
+        for d, (a, b) in enumerate(zip(starts, ends)):
+            binding.sum_steps(s.gov_rew, a, b, self.E, self.rew[d])
+            self.done[d].fill_(1 if done_host[a:b].any() else 0)
+        if self.n_dec:
+            self._observe()
+            binding.gov_policy_forward(self.mlp, self.K, self.gov_obs, self.scale, self.E, self.seed, 0, self.tmp_i,
+                                       self.tmp_f[0], self.last_val, self.tmp_f[1])
+            binding.gae(self.rew, self.val, self.done, self.last_val, self.n_dec, self.E, self.tr.gamma,
+                        self.tr.lam, self.adv, self.ret)
+
+    def update(self, lr: float, ent: float):
+        import workloads as W
+        if self.n_dec == 0:
+            return
+        tr = self.tr
+        hp = dict(tr.hp, ent_coef=ent)
+        n = self.n_dec * self.E
+        flat = dict(obs=self.obs[:self.n_dec].reshape(n, -1), act=self.lv[:self.n_dec].reshape(n, -1),
+                    logp_old=self.logp[:self.n_dec].reshape(-1), val_old=self.val[:self.n_dec].reshape(-1),
+                    adv=self.adv[:self.n_dec].reshape(-1), ret=self.ret[:self.n_dec].reshape(-1))
+        mbs = max(1, min(tr.minibatches, n // 64))
+        rows = n // mbs
+        ws = torch.zeros(binding.gov_ppo_workspace_bytes(self.mlp, self.K, rows), dtype=torch.uint8, device="cuda")
+        for epoch in range(tr.epochs):
+            a, c = W.affine_permutation(n, tr.updates * tr.epochs + epoch, seed=self.seed)
+            for mb in range(mbs):
+                binding.gov_ppo_backward(self.mlp, self.K, flat, n, a, c, mb * rows, rows, hp, ws, self.grads,
+                                         self.loss_terms)
+                self.adam_step += 1
+                binding.adam(self.mlp.params, self.grads, self.adam_m, self.adam_v, self.adam_step, max(lr, 1e-12))
+                self.mlp.sync()

@@ -151,6 +151,22 @@ def affine_permutation(M: int, epoch: int, seed: int = 0):
     return a, c
 
 
+def gov_obs_scales(cfg) -> np.ndarray:
+    """Float32 scale of every government observation feature (the layout of
+    ej_env_observe: mean, std, median of coin, period income, labor and each
+    inventory; the K rates; the phase; best bid, best ask, #bids, #asks per
+    resource).  Inputs to both sides."""
+    R, K = cfg["R"], cfg["K"]
+    stats = [2.0 ** -7, 2.0 ** -6, 2.0 ** -11] + [2.0 ** -4] * R
+    s = []
+    for v in stats:
+        s += [v, v, v]
+    s += [1.0] * K + [1.0]
+    for _ in range(R):
+        s += [1.0 / cfg["prices"][cfg["P"] - 1]] * 2 + [1.0 / cfg["N"]] * 2
+    return np.asarray(s, np.float32)
+
+
 def synthetic_obs(M: int, D: int, Ds: int, seed: int = 0) -> np.ndarray:
     """Observation rows as bf16 bit patterns [M, Ds]: values k/16 with
     k in -40..40 (exact in bf16), zero padding beyond D."""
