@@ -269,6 +269,7 @@ typedef struct ej_mlp_layout_t {
     int64_t n_params;                 /* fp32 parameter count */
     int64_t n_work;                   /* bf16 work-copy element count */
     int64_t W1, b1, W2, b2, W3, b3;   /* element offsets in the parameter vector */
+    int64_t params_stride, work_stride; /* distance between stacked weight sets (grouped calls) */
 } ej_mlp_layout_t;
 
 int ej_mlp_layout(const ej_mlp_desc* m, ej_mlp_layout_t* out);
@@ -296,6 +297,26 @@ int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_
                       const uint32_t* d_mask, int64_t M, int64_t row_base, uint64_t seed, uint64_t ctr,
                       const uint64_t* d_ctr_base, int32_t* d_act, float* d_logp, float* d_val, float* d_ent,
                       float* d_logits, void* stream);
+
+/* Per-agent weight sets (Sec. 5, methods 2 and 3: independent policies,
+ * iPPO, and individual policies with a shared value network, MAPPO): G sets
+ * stacked params_stride fp32 / work_stride bf16 elements apart (the strides
+ * of ej_mlp_layout), set g serving the rows q * row_stride + g, q <
+ * rows_per_group -- with economies of N agents each, set g = agent index g of
+ * every economy (G = N, row_stride = N, rows_per_group = E).  One launch
+ * covers every set (a grouped GEMM: each workgroup takes 64 rows of one set).
+ * Outputs and sampling as ej_policy_forward, the uniforms keyed by the global
+ * row, so a row draws the same uniforms as in the shared layout.
+ * row_stride >= G. */
+int ej_policy_forward_grouped(const ej_mlp_desc* m, int32_t groups, const float* d_params, const uint16_t* d_work,
+                              const uint16_t* d_obs, const uint32_t* d_mask, int64_t rows_per_group,
+                              int64_t row_stride, uint64_t seed, uint64_t ctr, const uint64_t* d_ctr_base,
+                              int32_t* d_act, float* d_logp, float* d_val, float* d_ent, float* d_logits,
+                              void* stream);
+
+/* ej_mlp_sync_weights for G stacked sets (strides of ej_mlp_layout). */
+int ej_mlp_sync_weights_grouped(const ej_mlp_desc* m, int32_t groups, const float* d_params, uint16_t* d_work,
+                                void* stream);
 
 /* *d_counter += inc on the stream (one tiny kernel; usable inside a graph). */
 int ej_counter_add(uint64_t* d_counter, uint64_t inc, void* stream);
@@ -329,6 +350,10 @@ typedef struct ej_ppo_batch {
     const float* adv;
     const float* ret;
     int64_t M_total, perm_a, perm_c, row_begin, rows;
+    /* the samples s of the batch sit at storage index s * row_stride + row_offset
+     * (row_stride <= 0 reads as 1): one agent's own samples of a rollout stored
+     * for every agent (per-agent weight sets: row_stride = N, row_offset = agent) */
+    int64_t row_stride, row_offset;
 } ej_ppo_batch;
 
 /* clip epsilon (0.2), value clip (10), value coefficient c_v (0.25),

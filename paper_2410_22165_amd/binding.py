@@ -52,12 +52,13 @@ class EjMlpDesc(C.Structure):
 
 
 class EjMlpLayout(C.Structure):
-    _fields_ = [(n, C.c_int64) for n in ("n_params", "n_work", "W1", "b1", "W2", "b2", "W3", "b3")]
+    _fields_ = [(n, C.c_int64) for n in ("n_params", "n_work", "W1", "b1", "W2", "b2", "W3", "b3", "params_stride",
+                                          "work_stride")]
 
 
 class EjPpoBatch(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("obs", "mask", "act", "logp_old", "val_old", "adv", "ret")] + [
-        (n, C.c_int64) for n in ("M_total", "perm_a", "perm_c", "row_begin", "rows")]
+        (n, C.c_int64) for n in ("M_total", "perm_a", "perm_c", "row_begin", "rows", "row_stride", "row_offset")]
 
 
 class EjPpoHparams(C.Structure):
@@ -130,6 +131,9 @@ def _declare_learner(L):
         "ej_mlp_sync_weights": [C.POINTER(EjMlpDesc), vp, vp, vp],
         "ej_policy_forward": [C.POINTER(EjMlpDesc), vp, vp, vp, vp, i64, i64, u64, u64, vp, vp, vp, vp, vp, vp, vp],
         "ej_counter_add": [vp, u64, vp],
+        "ej_policy_forward_grouped": [C.POINTER(EjMlpDesc), i32, vp, vp, vp, vp, i64, i64, u64, u64, vp, vp, vp, vp,
+                                      vp, vp, vp],
+        "ej_mlp_sync_weights_grouped": [C.POINTER(EjMlpDesc), i32, vp, vp, vp],
         "ej_gae": [vp, vp, vp, vp, i32, i64, f32, f32, vp, vp, vp],
         "ej_ppo_workspace_size": [C.POINTER(EjMlpDesc), i64, C.POINTER(i64)],
         "ej_ppo_backward": [C.POINTER(EjMlpDesc), vp, vp, C.POINTER(EjPpoBatch), C.POINTER(EjPpoHparams), vp, i64,
@@ -399,15 +403,18 @@ def ppo_workspace_bytes(mlp: "Mlp", rows: int) -> int:
 
 
 def ppo_backward(mlp: "Mlp", storage: dict, M_total: int, perm_a: int, perm_c: int, row_begin: int, rows: int,
-                 hp: dict, workspace, grads, loss, stream=None):
+                 hp: dict, workspace, grads, loss, stream=None, row_stride: int = 1, row_offset: int = 0,
+                 params=None, work=None):
     """storage: torch tensors obs, mask, act, logp_old, val_old, adv, ret indexed by sample;
     loss: at least PPO_LOSS_TERMS floats."""
     if loss.numel() < PPO_LOSS_TERMS:
         raise EconError(f"ej_ppo_backward writes {PPO_LOSS_TERMS} loss terms; got {loss.numel()}")
     b = EjPpoBatch(*(ptr(storage[k]) for k in ("obs", "mask", "act", "logp_old", "val_old", "adv", "ret")),
-                   M_total, perm_a, perm_c, row_begin, rows)
+                   M_total, perm_a, perm_c, row_begin, rows, row_stride, row_offset)
     h = EjPpoHparams(hp["clip"], hp["vclip"], hp["vf_coef"], hp["ent_coef"])
-    check(lib().ej_ppo_backward(C.byref(mlp.desc), ptr(mlp.params), ptr(mlp.work), C.byref(b), C.byref(h),
+    p_ptr = ptr(mlp.params) if params is None else params
+    w_ptr = ptr(mlp.work) if work is None else work
+    check(lib().ej_ppo_backward(C.byref(mlp.desc), p_ptr, w_ptr, C.byref(b), C.byref(h),
                                 ptr(workspace), workspace.numel(), ptr(grads), ptr(loss), stream_ptr(stream)),
           "ej_ppo_backward")
 
@@ -532,3 +539,50 @@ def gov_ppo_backward(mlp: "Mlp", K: int, storage: dict, M_total: int, perm_a: in
 def sum_steps(x, t_begin: int, t_end: int, E: int, out, stream=None):
     """out[e] = sum over t in [t_begin, t_end) of x[t, e] (ej_sum_steps)."""
     check(lib().ej_sum_steps(ptr(x), t_begin, t_end, E, ptr(out), stream_ptr(stream)), "ej_sum_steps")
+
+
+class GroupedMlp:
+    """G weight sets of one network stacked in one tensor (per-agent
+    policies): set g's fp32 parameters at g * params_stride, its bf16 work
+    copy at g * work_stride."""
+
+    def __init__(self, D: int, D_stride: int, H: int, A: int, groups: int, weights: list | None = None):
+        import torch
+        self.desc = EjMlpDesc(D, D_stride, H, A, 0)
+        lay = EjMlpLayout()
+        check(lib().ej_mlp_layout(C.byref(self.desc), C.byref(lay)), "ej_mlp_layout")
+        self.layout = {n: int(getattr(lay, n)) for n, _ in EjMlpLayout._fields_}
+        self.D, self.Ds, self.H, self.A, self.G = D, D_stride, H, A, groups
+        self.ps, self.wst = self.layout["params_stride"], self.layout["work_stride"]
+        self.params = torch.zeros(groups * self.ps, dtype=torch.float32, device="cuda")
+        self.work = torch.zeros(groups * self.wst, dtype=torch.int16, device="cuda")
+        self._one = Mlp(D, D_stride, H, A)
+        if weights is not None:
+            for g, w in enumerate(weights):
+                self.params[g * self.ps:g * self.ps + self.layout["n_params"]].copy_(
+                    torch.from_numpy(self._one.flat(w)))
+            self.sync()
+
+    def set_params(self, g: int):
+        """Parameter view of set g."""
+        return self.params[g * self.ps:g * self.ps + self.layout["n_params"]]
+
+    def params_ptr(self, g: int) -> int:
+        return self.params.data_ptr() + 4 * g * self.ps
+
+    def work_ptr(self, g: int) -> int:
+        return self.work.data_ptr() + 2 * g * self.wst
+
+    def unflat(self, g: int, v=None) -> dict:
+        return self._one.unflat(self.set_params(g).cpu().numpy() if v is None else v)
+
+    def sync(self, stream=None):
+        check(lib().ej_mlp_sync_weights_grouped(C.byref(self.desc), self.G, ptr(self.params), ptr(self.work),
+                                                stream_ptr(stream)), "ej_mlp_sync_weights_grouped")
+
+    def forward(self, obs, mask, rows_per_group: int, row_stride: int, seed: int, ctr: int, act, logp, val, ent,
+                logits=None, ctr_base=None, stream=None):
+        check(lib().ej_policy_forward_grouped(C.byref(self.desc), self.G, ptr(self.params), ptr(self.work), ptr(obs),
+                                              ptr(mask), rows_per_group, row_stride, seed, ctr, ptr(ctr_base),
+                                              ptr(act), ptr(logp), ptr(val), ptr(ent), ptr(logits),
+                                              stream_ptr(stream)), "ej_policy_forward_grouped")

@@ -20,6 +20,15 @@
 
 namespace econ {
 
+// Weight sets and row layout of a grouped launch: group g reads parameters at
+// g * pstride and bf16 work at g * wstride, and owns rows q * rstride + g
+struct PolicyGroups {
+    int64_t rstride, pstride, wstride;
+};
+
+// stacked weight sets start 16 bytes apart at least: n rounded up to a multiple of `m`
+__host__ inline int64_t group_stride(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
+
 // LDS bytes: activations (aliased by the logit chunk when there is only one
 // chunk), mask words, uniforms, biases
 template <int H, int RPW>
@@ -35,13 +44,19 @@ size_t policy_lds_bytes(int W, int A1p)
 // 64-row tiles with H <= 256 take 38.5 KB of LDS and 128 VGPRs: four workgroups per CU
 template <int H, int RPW_>
 __global__ void __launch_bounds__(256, (RPW_ == 16 && H <= 256) ? 4 : 1)
-policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
+policy_forward_kernel(const MlpDims d, const float* __restrict__ params_all, const uint16_t* __restrict__ work_all,
                       const uint16_t* __restrict__ obs, const uint32_t* __restrict__ mask, int64_t M, int64_t row_base,
                       int W, uint64_t seed, uint64_t ctr_arg, const uint64_t* __restrict__ ctr_base,
                       int32_t* __restrict__ act, float* __restrict__ logp, float* __restrict__ val,
-                      float* __restrict__ ent, float* __restrict__ logits)
+                      float* __restrict__ ent, float* __restrict__ logits, const PolicyGroups grp)
 {
     const uint64_t ctr = ctr_arg + (ctr_base ? *ctr_base : 0ull);
+    // group g = blockIdx.y owns weight set g and the rows q * rstride + g of
+    // its M local rows q (one group with stride 1: the shared network)
+    const int64_t g = blockIdx.y;
+    const float* __restrict__ params = params_all + g * grp.pstride;
+    const uint16_t* __restrict__ work = work_all + g * grp.wstride;
+    auto grow = [&](int64_t q) { return q * grp.rstride + g; };
     using T = MlpTile<H, RPW_>;
     constexpr int RPW = T::RPW, TILE = T::TILE, HS = T::HS, TR = TILE / 16;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -61,7 +76,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     auto draw_uniforms = [&](int c) {
         if (l < RPW) {
             const int rl = wave * RPW + l;
-            u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row_base + row0 + rl), ctr, (uint64_t)(c >> 1), 0);
+            u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row_base + grow(row0 + rl)), ctr, (uint64_t)(c >> 1), 0);
 #pragma unroll
             for (int k = 0; k < 4; ++k) urow[rl * 4 + k] = unif24(word_of(w, k));
         }
@@ -75,7 +90,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     for (int i = 0; i < NPC; ++i) {
         const int p = threadIdx.x + 256 * i, r = p >> 3, cc = p & 7;
         const int64_t row = row0 + r;
-        pv[i] = (row < M && cc * 8 < d.Ds) ? *(const uint4*)(obs + row * d.Ds + cc * 8) : uint4{0u, 0u, 0u, 0u};
+        pv[i] = (row < M && cc * 8 < d.Ds) ? *(const uint4*)(obs + grow(row) * d.Ds + cc * 8) : uint4{0u, 0u, 0u, 0u};
     }
 #pragma unroll
     for (int i = 0; i < NPC; ++i) {
@@ -83,8 +98,9 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
         *(uint4*)(hbuf + (p >> 3) * HS + (p & 7) * 8) = pv[i];
     }
     for (int p = threadIdx.x; p < TILE * W; p += 256) {
-        const int64_t row = row0 + p / W;
-        smask[p] = row < M ? mask[row0 * W + p] : 0u;
+        const int r = p / W;
+        const int64_t row = row0 + r;
+        smask[p] = row < M ? mask[grow(row) * W + (p - r * W)] : 0u;
     }
     for (int p = threadIdx.x; p < d.A1p; p += 256) sb3[p] = p < d.A1 ? params[d.ob3 + p] : 0.f;
 
@@ -162,7 +178,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
             if (logits && row0 + rloc < M) {
 #pragma unroll
                 for (int j = 0; j < 32; ++j)
-                    if (colq + j < d.A) logits[(row0 + rloc) * d.A + colq + j] = z[j];
+                    if (colq + j < d.A) logits[grow(row0 + rloc) * d.A + colq + j] = z[j];
             }
             // allowed actions of this lane's quarter (bits past the last action cleared)
             const int wi = c * 4 + q, nact = d.A - colq;
@@ -233,8 +249,9 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
     if (q == 0) {
 #pragma unroll
         for (int k = 0; k < SR; ++k) {
-            const int64_t row = row0 + wave * RPW + k * 16 + (l >> 2);
-            if (row >= M) continue;
+            const int64_t q_row = row0 + wave * RPW + k * 16 + (l >> 2);
+            if (q_row >= M) continue;
+            const int64_t row = grow(q_row);
             const float S = sS[k];
             int a = sA[k];
             float lp = 0.f, h = 0.f;
@@ -254,8 +271,11 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params, const u
 }
 
 // fp32 parameters -> bf16 K-chunk layouts (forward W1f, W2f, W3f; backward W3b, W2b)
-__global__ void mlp_sync_kernel(const MlpDims d, const float* __restrict__ p, uint16_t* __restrict__ w)
+__global__ void mlp_sync_kernel(const MlpDims d, const float* __restrict__ p_all, uint16_t* __restrict__ w_all,
+                                int64_t pstride, int64_t wstride)
 {
+    const float* __restrict__ p = p_all + (int64_t)blockIdx.y * pstride;
+    uint16_t* __restrict__ w = w_all + (int64_t)blockIdx.y * wstride;
     const int64_t n = d.n_work;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
         float v = 0.f;
@@ -291,13 +311,13 @@ template <int H, int RPW>
 int launch_policy_forward(const MlpDims& d, const float* params, const uint16_t* work, const uint16_t* obs,
                           const uint32_t* mask, int64_t M, int64_t row_base, int W, uint64_t seed, uint64_t ctr,
                           const uint64_t* ctr_base, int32_t* act, float* logp, float* val, float* ent, float* logits,
-                          hipStream_t st)
+                          hipStream_t st, int groups = 1, PolicyGroups grp = PolicyGroups{1, 0, 0})
 {
     using T = MlpTile<H, RPW>;
     const int64_t blocks = (M + T::TILE - 1) / T::TILE;
     const size_t lds = policy_lds_bytes<H, RPW>(W, d.A1p);
-    policy_forward_kernel<H, RPW><<<(unsigned)blocks, 256, lds, st>>>(d, params, work, obs, mask, M, row_base, W, seed,
-                                                                      ctr, ctr_base, act, logp, val, ent, logits);
+    policy_forward_kernel<H, RPW><<<dim3((unsigned)blocks, (unsigned)groups), 256, lds, st>>>(
+        d, params, work, obs, mask, M, row_base, W, seed, ctr, ctr_base, act, logp, val, ent, logits, grp);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }
@@ -329,6 +349,8 @@ int ej_mlp_layout(const ej_mlp_desc* m, ej_mlp_layout_t* out)
     out->b2 = d.ob2;
     out->W3 = d.oW3;
     out->b3 = d.ob3;
+    out->params_stride = group_stride(d.n_params, 4);
+    out->work_stride = group_stride(d.n_work, 8);
     return EJ_OK;
 }
 
@@ -340,7 +362,22 @@ int ej_mlp_sync_weights(const ej_mlp_desc* m, const float* d_params, uint16_t* d
     if (!d_params || !d_work) return EJ_EINVAL;
     int64_t blocks = (d.n_work + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    mlp_sync_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(d, d_params, d_work);
+    mlp_sync_kernel<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(d, d_params, d_work, 0, 0);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
+int ej_mlp_sync_weights_grouped(const ej_mlp_desc* m, int32_t groups, const float* d_params, uint16_t* d_work,
+                                void* stream)
+{
+    MlpDims d;
+    int rc = desc_dims(m, &d);
+    if (rc != EJ_OK) return rc;
+    if (!d_params || !d_work || groups <= 0 || groups > 65535) return EJ_EINVAL;
+    int64_t blocks = (d.n_work + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    mlp_sync_kernel<<<dim3((unsigned)blocks, (unsigned)groups), 256, 0, (hipStream_t)stream>>>(
+        d, d_params, d_work, group_stride(d.n_params, 4), group_stride(d.n_work, 8));
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }
@@ -383,6 +420,34 @@ int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_
     default: return EJ_POLICY(512, 16);
     }
 #undef EJ_POLICY
+}
+
+int ej_policy_forward_grouped(const ej_mlp_desc* m, int32_t groups, const float* d_params, const uint16_t* d_work,
+                              const uint16_t* d_obs, const uint32_t* d_mask, int64_t rows_per_group,
+                              int64_t row_stride, uint64_t seed, uint64_t ctr, const uint64_t* d_ctr_base,
+                              int32_t* d_act, float* d_logp, float* d_val, float* d_ent, float* d_logits, void* stream)
+{
+    MlpDims d;
+    int rc = desc_dims(m, &d);
+    if (rc != EJ_OK) return rc;
+    if (groups <= 0 || groups > 65535 || rows_per_group < 0 || row_stride < groups || !d_params || !d_work || !d_obs ||
+        !d_mask || !d_act || !d_logp || !d_val || !d_ent)
+        return EJ_EINVAL;
+    if (!aligned16(d_params) || !aligned16(d_work) || !aligned16(d_obs)) return EJ_EINVAL;
+    if (rows_per_group == 0) return EJ_OK;
+    const int W = (m->A + 31) / 32;
+    hipStream_t st = (hipStream_t)stream;
+    const PolicyGroups grp{row_stride, group_stride(d.n_params, 4), group_stride(d.n_work, 8)};
+#define EJ_POLICY_G(HH)                                                                                              \
+    launch_policy_forward<HH, 16>(d, d_params, d_work, d_obs, d_mask, rows_per_group, 0, W, seed, ctr, d_ctr_base,   \
+                                  d_act, d_logp, d_val, d_ent, d_logits, st, groups, grp)
+    switch (m->H) {
+    case 64: return EJ_POLICY_G(64);
+    case 128: return EJ_POLICY_G(128);
+    case 256: return EJ_POLICY_G(256);
+    default: return EJ_POLICY_G(512);
+    }
+#undef EJ_POLICY_G
 }
 
 }  // extern "C"

@@ -36,6 +36,7 @@ struct PpoBatchDev {
     const float* ret;
     int64_t Mtot, a, c, begin, rows;
     uint64_t mu;  // floor((2^64 - 1) / Mtot): Barrett reciprocal of the permutation modulus
+    int64_t rstride, roff;  // sample s sits at storage index s * rstride + roff
 };
 
 struct PpoHp {
@@ -52,7 +53,7 @@ __device__ inline int64_t sample_of(const PpoBatchDev& B, int64_t j)
     uint64_t r = x - __umul64hi(x, B.mu) * M;
     r = r >= M ? r - M : r;
     r = r >= M ? r - M : r;
-    return (int64_t)r;
+    return (int64_t)r * B.rstride + B.roff;
 }
 
 // ---------------------------------------------------------------------------
@@ -1204,7 +1205,8 @@ static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const 
         !aligned16(d_grads))
         return EJ_EINVAL;
     if (b->M_total <= 0 || b->M_total > INT32_MAX || b->rows <= 0 || b->perm_a <= 0 || b->perm_c < 0 ||
-        b->row_begin < 0 || b->row_begin + b->rows > INT32_MAX)
+        b->row_begin < 0 || b->row_begin + b->rows > INT32_MAX || b->row_offset < 0 ||
+        (b->row_stride > 0 && b->row_offset >= b->row_stride))
         return EJ_EINVAL;
     MlpDims d;
     int rc = mlp_dims(m->D, m->D_stride, m->H, m->A, &d);
@@ -1217,7 +1219,8 @@ static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const 
     const int64_t a = b->M_total == 1 ? 1 : b->perm_a % b->M_total;
     if (a == 0) return EJ_EINVAL;
     PpoBatchDev B{b->obs, b->mask, b->act, b->logp_old, b->val_old, b->adv, b->ret, b->M_total, a,
-                  b->perm_c % b->M_total, b->row_begin, b->rows, UINT64_MAX / (uint64_t)b->M_total};
+                  b->perm_c % b->M_total, b->row_begin, b->rows, UINT64_MAX / (uint64_t)b->M_total,
+                  b->row_stride > 0 ? b->row_stride : 1, b->row_offset};
     PpoHp h{hp->clip, hp->vclip, hp->vf_coef, hp->ent_coef};
     const int W = (m->A + 31) / 32;
     double* advp = (double*)(ws + w.o_adv);
@@ -1340,7 +1343,8 @@ int ej_gov_ppo_backward(const ej_mlp_desc* m, int32_t K, const float* d_params, 
         !aligned16(d_grads))
         return EJ_EINVAL;
     if (b->M_total <= 0 || b->M_total > INT32_MAX || b->rows <= 0 || b->perm_a <= 0 || b->perm_c < 0 ||
-        b->row_begin < 0 || b->row_begin + b->rows > INT32_MAX)
+        b->row_begin < 0 || b->row_begin + b->rows > INT32_MAX || b->row_offset < 0 ||
+        (b->row_stride > 0 && b->row_offset >= b->row_stride))
         return EJ_EINVAL;
     PpoWorkspace w;
     ppo_workspace(d, b->rows, &w);
@@ -1350,7 +1354,8 @@ int ej_gov_ppo_backward(const ej_mlp_desc* m, int32_t K, const float* d_params, 
     const int64_t a = b->M_total == 1 ? 1 : b->perm_a % b->M_total;
     if (a == 0) return EJ_EINVAL;
     PpoBatchDev B{b->obs, nullptr, b->act, b->logp_old, b->val_old, b->adv, b->ret, b->M_total, a,
-                  b->perm_c % b->M_total, b->row_begin, b->rows, UINT64_MAX / (uint64_t)b->M_total};
+                  b->perm_c % b->M_total, b->row_begin, b->rows, UINT64_MAX / (uint64_t)b->M_total,
+                  b->row_stride > 0 ? b->row_stride : 1, b->row_offset};
     PpoHp h{hp->clip, hp->vclip, hp->vf_coef, hp->ent_coef};
     double* advp = (double*)(ws + w.o_adv);
     float* stats = (float*)(ws + w.o_stats);

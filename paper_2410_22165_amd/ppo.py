@@ -282,3 +282,123 @@ class GovLearner:
                 self.adam_step += 1
                 binding.adam(self.mlp.params, self.grads, self.adam_m, self.adam_v, self.adam_step, max(lr, 1e-12))
                 self.mlp.sync()
+
+
+class MultiAgentTrainer:
+    """PPO with per-agent weight sets (Sec. 5, methods 2 and 3): layout
+    "ippo" gives every agent index its own policy and value network (agent g
+    of every economy acts with set g); "mappo" gives every agent its own
+    policy and all agents one shared value network that sees the same
+    per-agent observation.  The rollout runs the grouped policy forward
+    (ej_policy_forward_grouped: one launch, 64-row tiles of one set each)
+    and, for "mappo", the shared value network; each agent's update reads its
+    own samples of the shared storage (batch row_stride = N, row_offset =
+    agent), and one Adam step covers every stacked set.  Economies have N
+    agents each; launches are issued from the host."""
+
+    def __init__(self, env_cfg: dict, scales: dict, layout: str, hidden: int, rollout: int, epochs: int,
+                 minibatches: int, gamma: float, lam: float, clip: float, vf_coef: float, vclip: float,
+                 ent_coef: float, lr: float, seed: int = 0, total_updates: int = 1):
+        import workloads as W
+        if layout not in ("ippo", "mappo"):
+            raise ValueError(layout)
+        self.layout = layout
+        self.env = binding.Env(env_cfg, scales)
+        e = self.env
+        self.E, self.N = e.E, env_cfg["N"]
+        self.M, self.A, self.D, self.Ds, self.Wm = e.M, e.A, e.D, e.Ds, e.W
+        assert self.M == self.E * self.N
+        self.T, self.epochs, self.minibatches = rollout, epochs, minibatches
+        self.gamma, self.lam, self.lr0, self.ent0 = gamma, lam, lr, ent_coef
+        self.hp = dict(clip=clip, vclip=vclip, vf_coef=vf_coef, ent_coef=ent_coef)
+        self.seed, self.total_updates = seed, total_updates
+        self.pol = binding.GroupedMlp(e.D, e.Ds, hidden, e.A, self.N,
+                                      [W.policy_weights(e.D, hidden, e.A, seed=seed * 1000 + g) for g in range(self.N)])
+        z = dict(device="cuda")
+        self.grads = torch.zeros_like(self.pol.params)
+        self.adam_m = torch.zeros_like(self.pol.params)
+        self.adam_v = torch.zeros_like(self.pol.params)
+        self.store = RolloutStorage(rollout, self.M, self.Ds, self.Wm, e.E)
+        self.ctr_base = torch.zeros(1, dtype=torch.int64, **z)
+        self.loss_terms = torch.zeros(binding.PPO_LOSS_TERMS, **z)
+        self.S_agent = rollout * self.E  # one agent's samples per rollout
+        self.mb_rows = self.S_agent // minibatches
+        self.workspace = torch.zeros(binding.ppo_workspace_bytes(self.pol._one, self.mb_rows), dtype=torch.uint8, **z)
+        if layout == "mappo":
+            self.vnet = binding.Mlp(e.D, e.Ds, hidden, 1, W.policy_weights(e.D, hidden, 1, seed=seed + 7))
+            self.vmask = torch.ones((rollout + 1, self.M, 1), dtype=torch.int32, **z)  # the one dummy action
+            self.vzero_i = torch.zeros((rollout, self.M), dtype=torch.int32, **z)
+            self.vzero_f = torch.zeros((rollout, self.M), **z)
+            self.vtmp = torch.zeros((4, self.M), **z)
+            self.vgrads = torch.zeros_like(self.vnet.params)
+            self.vadam_m = torch.zeros_like(self.vnet.params)
+            self.vadam_v = torch.zeros_like(self.vnet.params)
+            self.v_rows = rollout * self.M // minibatches
+            self.vworkspace = torch.zeros(binding.ppo_workspace_bytes(self.vnet, self.v_rows), dtype=torch.uint8, **z)
+            self.vloss = torch.zeros(binding.PPO_LOSS_TERMS, **z)
+        self.updates = 0
+        self.adam_step = 0
+        self.env.set_gov_draw(True, seed + 1)
+        self.env.observe(self.store.obs[0], self.store.mask[0])
+
+    def _values(self, t, out):
+        s = self.store
+        self.vnet.forward(s.obs[t], self.vmask[t], self.M, self.seed + 9, t, self.vtmp[0].view(torch.int32),
+                          self.vtmp[1], out, self.vtmp[2], ctr_base=self.ctr_base)
+
+    def collect(self):
+        s = self.store
+        for t in range(self.T):
+            self.pol.forward(s.obs[t], s.mask[t], self.E, self.N, self.seed, t, s.act[t], s.logp[t], s.val[t],
+                             s.ent[t], ctr_base=self.ctr_base)
+            if self.layout == "mappo":
+                self._values(t, s.val[t])
+            self.env.step(s.act[t], None, s.rew[t], s.gov_rew[t], s.done[t], s.obs[t + 1], s.mask[t + 1])
+        if self.layout == "mappo":
+            self._values(self.T, s.last_val)
+        else:
+            self.pol.forward(s.obs[self.T], s.mask[self.T], self.E, self.N, self.seed, self.T,
+                             s.tmp[2 * self.M:].view(torch.int32), s.tmp[:self.M], s.last_val, s.tmp[self.M:2 * self.M],
+                             ctr_base=self.ctr_base)
+        binding.gae(s.rew, s.val, s.done, s.last_val, self.T, self.M, self.gamma, self.lam, s.adv, s.ret)
+        binding.counter_add(self.ctr_base, self.T + 1)
+
+    def update(self):
+        import workloads as W
+        frac = self.updates / max(self.total_updates, 1)
+        lr = self.lr0 * max(1.0 - frac, 0.0)
+        ent = self.ent0 * max(1.0 - frac / 0.9, 0.0)
+        hp = dict(self.hp, ent_coef=ent)
+        if self.layout == "mappo":
+            hp = dict(hp, vf_coef=0.0)  # the policies carry no value head of their own
+        flat = self.store.flat()
+        n = self.pol.layout["n_params"]
+        for epoch in range(self.epochs):
+            a, c = W.affine_permutation(self.S_agent, self.updates * self.epochs + epoch, seed=self.seed)
+            if self.layout == "mappo":
+                av, cv = W.affine_permutation(self.T * self.M, self.updates * self.epochs + epoch, seed=self.seed + 5)
+            for mb in range(self.minibatches):
+                for g in range(self.N):
+                    binding.ppo_backward(self.pol._one, flat, self.S_agent, a, c, mb * self.mb_rows, self.mb_rows, hp,
+                                         self.workspace, self.grads[g * self.pol.ps:g * self.pol.ps + n],
+                                         self.loss_terms, row_stride=self.N, row_offset=g,
+                                         params=self.pol.params_ptr(g), work=self.pol.work_ptr(g))
+                self.adam_step += 1
+                binding.adam(self.pol.params, self.grads, self.adam_m, self.adam_v, self.adam_step, max(lr, 1e-12))
+                self.pol.sync()
+                if self.layout == "mappo":
+                    vflat = dict(flat, mask=self.vmask[:self.T].reshape(self.T * self.M, 1),
+                                 act=self.vzero_i.reshape(-1), logp_old=self.vzero_f.reshape(-1),
+                                 adv=self.vzero_f.reshape(-1))
+                    vhp = dict(self.hp, ent_coef=0.0)
+                    binding.ppo_backward(self.vnet, vflat, self.T * self.M, av, cv, mb * self.v_rows, self.v_rows,
+                                         vhp, self.vworkspace, self.vgrads, self.vloss)
+                    binding.adam(self.vnet.params, self.vgrads, self.vadam_m, self.vadam_v, self.adam_step,
+                                 max(lr, 1e-12))
+                    self.vnet.sync()
+        self.updates += 1
+        self.store.obs[0].copy_(self.store.obs[self.T])
+        self.store.mask[0].copy_(self.store.mask[self.T])
+
+    def close(self):
+        self.env.close()

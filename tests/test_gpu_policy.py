@@ -73,7 +73,7 @@ def test_policy_forward_parity(case):
     lp16p = np.concatenate([lp16, np.full((M, pad), -np.inf)], axis=1)
     a_o, margin = op.sample_chunked(lp16p, u1, u2)
     safe = margin > 1e-4
-    assert safe.mean() > 0.9
+    assert safe.mean() > 0.97, safe.mean()  # about 1 - 2e-4 per near-threshold candidate
     assert np.array_equal(g["act"][safe], a_o[safe]), np.flatnonzero(g["act"][safe] != a_o[safe])[:10]
 
 
@@ -264,5 +264,5 @@ def test_sparse_masks_single_actions_and_empty_chunks():
     lp16p = np.concatenate([lp16, np.full((M, NC * 128 - A), -np.inf)], axis=1)
     a_o, margin = op.sample_chunked(lp16p, u1, u2)
     safe = margin > 1e-4
-    assert safe.mean() > 0.9
+    assert safe.mean() > 0.97, safe.mean()  # about 1 - 2e-4 per near-threshold candidate
     assert np.array_equal(g["act"][safe], a_o[safe]), np.flatnonzero(g["act"][safe] != a_o[safe])[:10]
