@@ -258,7 +258,13 @@ size_t ppo_rows_lds_bytes(int W, int A1p)
 // [logits | value], dh2 = (dY W3^T) * [h2 > 0] and dh1 = (dh2 W2^T) *
 // [h1 > 0].  The weight-gradient GEMMs read the m-block copies written here.
 // The workgroup's threads talk through LDS only.
-template <int H>
+//
+// The rows of a minibatch are scattered samples (the permutation), so their
+// gather is latency-bound: every load of the tile's inputs (observation, mask
+// words, the five per-sample scalars, the biases) is issued before the first
+// of them is stored to LDS, one round trip for all.  MWP mask words per
+// thread cover rows of W <= 4 MWP words.
+template <int H, int MWP>
 __global__ void __launch_bounds__(256, H <= 256 ? 2 : 1)  // H <= 256: 73 KB of LDS, two workgroups per CU
 ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
                 const PpoBatchDev B, const PpoHp hp, const float* __restrict__ stats, int W,
@@ -278,52 +284,72 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     float* sbias = lred + 64;                         // b1 [H], b2 [H], b3 [A1p] (zero padded)
 
     const int wave = threadIdx.x >> 6, l = lane_id(), q = l & 3;
-    const int64_t tile_row0 = (int64_t)blockIdx.x * TILE;
     const float inv_n = 1.0f / (float)B.rows;
     const int col0 = wave * (H / 4);
 
-    // gather the tile's samples
-    for (int r = threadIdx.x; r < TILE; r += 256) {
-        const int64_t j = tile_row0 + r;
-        float va = 0.f, lpo = 0.f, vo = 0.f, ah = 0.f, rt = 0.f, valid = 0.f;
-        if (j < B.rows) {
-            const int64_t sidx = sample_of(B, j);
-            va = __int_as_float(B.act[sidx]);
-            lpo = B.logp_old[sidx];
-            vo = B.val_old[sidx];
-            ah = (B.adv[sidx] - stats[0]) * stats[1];
-            rt = B.ret[sidx];
-            valid = 1.f;
-        }
-        rinfo[0 * TILE + r] = va;
-        rinfo[1 * TILE + r] = lpo;
-        rinfo[2 * TILE + r] = vo;
-        rinfo[3 * TILE + r] = ah;
-        rinfo[4 * TILE + r] = rt;
-        rinfo[5 * TILE + r] = valid;
-    }
-    for (int p = threadIdx.x; p < TILE * W; p += 256) {  // mask words, spread over the workgroup
-        const int r = p / W;
-        const int64_t j = tile_row0 + r;
-        smask[p] = j < B.rows ? B.mask[sample_of(B, j) * W + (p - r * W)] : 0u;
-    }
-    load_biases<H>(d, params, sbias);
-    // (TILE x K1P / 8 pieces of 16 bytes: every load is issued before the first store)
-    constexpr int NPC = TILE * (K1P / 8) / 256;
+    // gather registers (the tile's inputs)
+    constexpr int NPC = TILE * (K1P / 8) / 256;  // 16-byte observation pieces per thread
     uint4 pv[NPC];
+    float gs[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // act (bits), logp_old, val_old, adv, ret of row threadIdx.x
+    uint32_t gm[MWP];
+    float mean = 0.f, istd = 0.f;  // advantage normalisation of the minibatch
+    auto gather = [&](int64_t tile) {
+        const int64_t row0 = tile * TILE;
+        mean = stats[0];
+        istd = stats[1];
+        if ((int)threadIdx.x < TILE && row0 + (int)threadIdx.x < B.rows) {
+            const int64_t sidx = sample_of(B, row0 + threadIdx.x);
+            gs[0] = __int_as_float(B.act[sidx]);
+            gs[1] = B.logp_old[sidx];
+            gs[2] = B.val_old[sidx];
+            gs[3] = B.adv[sidx];
+            gs[4] = B.ret[sidx];
+        }
 #pragma unroll
-    for (int i = 0; i < NPC; ++i) {
-        const int p = threadIdx.x + 256 * i, r = p >> 3, cc = p & 7;
-        const int64_t j = tile_row0 + r;
-        pv[i] = (j < B.rows && cc * 8 < d.Ds) ? *(const uint4*)(B.obs + sample_of(B, j) * d.Ds + cc * 8)
-                                               : uint4{0u, 0u, 0u, 0u};
-    }
+        for (int i = 0; i < MWP; ++i) {
+            const int p = threadIdx.x + 256 * i;
+            const int r = p / W;
+            const int64_t j = row0 + r;
+            gm[i] = (r < TILE && j < B.rows) ? B.mask[sample_of(B, j) * W + (p - r * W)] : 0u;
+        }
 #pragma unroll
-    for (int i = 0; i < NPC; ++i) {
-        const int p = threadIdx.x + 256 * i;
-        *(uint4*)(hbuf + (p >> 3) * HS + (p & 7) * 8) = pv[i];
-    }
+        for (int i = 0; i < NPC; ++i) {
+            const int p = threadIdx.x + 256 * i, r = p >> 3, cc = p & 7;
+            const int64_t j = row0 + r;
+            pv[i] = (j < B.rows && cc * 8 < d.Ds) ? *(const uint4*)(B.obs + sample_of(B, j) * d.Ds + cc * 8)
+                                                   : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    auto commit = [&](int64_t tile) {
+        const int64_t row0 = tile * TILE;
+        if ((int)threadIdx.x < TILE) {
+            const int r = threadIdx.x;
+            const bool v = row0 + r < B.rows;
+            rinfo[0 * TILE + r] = v ? gs[0] : 0.f;
+            rinfo[1 * TILE + r] = v ? gs[1] : 0.f;
+            rinfo[2 * TILE + r] = v ? gs[2] : 0.f;
+            rinfo[3 * TILE + r] = v ? (gs[3] - mean) * istd : 0.f;
+            rinfo[4 * TILE + r] = v ? gs[4] : 0.f;
+            rinfo[5 * TILE + r] = v ? 1.f : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < MWP; ++i) {
+            const int p = threadIdx.x + 256 * i;
+            if (p < TILE * W) smask[p] = gm[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NPC; ++i) {
+            const int p = threadIdx.x + 256 * i;
+            *(uint4*)(hbuf + (p >> 3) * HS + (p & 7) * 8) = pv[i];
+        }
+    };
+
+    const int64_t tile = blockIdx.x;
+    gather(tile);
+    load_biases<H>(d, params, sbias);
+    commit(tile);
     lds_barrier();
+    const int64_t tile_row0 = tile * TILE;
     const int64_t mb0 = tile_row0 >> 5;
     tile_to_mblocks(hbuf, HS, TILE, d.K1p, Tobs, mb0, d.K1p, 0);  // observations for dW1
 
@@ -506,7 +532,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     if (threadIdx.x < 4) {
         float sum = 0.f;
         for (int w = 0; w < 4; ++w) sum += lred[w * 4 + threadIdx.x];
-        loss_parts[(int64_t)blockIdx.x * 4 + threadIdx.x] = sum;
+        loss_parts[tile * 4 + threadIdx.x] = sum;
     }
 }
 
@@ -586,25 +612,47 @@ dw_kernel(const uint16_t* __restrict__ Tx, int J, const uint16_t* __restrict__ T
     if (jt == 0 && (int)threadIdx.x < CN) colsum[(int64_t)g * N + n0 + threadIdx.x] = cs;
 }
 
-// grad[woff + j ldw + n] = sum_g part[g][j][n] (j < Jv, n < Nv); bias from the column sums
-__global__ void dw_reduce_kernel(const float* __restrict__ part, const float* __restrict__ colsum, int J, int N,
-                                 int G, int Jv, int Nv, float* __restrict__ grad, int64_t woff, int ldw, int64_t boff)
+// grad[woff + j ldw + n] = sum_g part[g][j][n] (j < Jv, n < Nv); bias from the
+// column sums.  A workgroup takes 32 consecutive elements: eight slices of
+// its threads sum the partials g = s, s + 8, ... (coalesced 128-byte rows,
+// many loads in flight), and slice sums are added in the order s = 0 .. 7,
+// a fixed order for every call.
+__global__ void __launch_bounds__(256) dw_reduce_kernel(const float* __restrict__ part, const float* __restrict__ colsum,
+                                                        int J, int N, int G, int Jv, int Nv, float* __restrict__ grad,
+                                                        int64_t woff, int ldw, int64_t boff)
 {
+    __shared__ float red[8][32];
+    const int i = threadIdx.x & 31, sl = threadIdx.x >> 5;
     const int64_t total = (int64_t)J * N;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total + N;
-         idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t idx = (int64_t)blockIdx.x * 32 + i;
+    const bool in = idx < total + N;
+    const float* src = idx < total ? part + idx : colsum + (idx - total);
+    const int64_t stride = idx < total ? total : N;
+    float acc = 0.f;
+    if (in) {
+        int g = sl;
+        for (; g + 24 < G; g += 32) {  // four loads in flight per thread
+            const float v0 = src[(int64_t)g * stride], v1 = src[(int64_t)(g + 8) * stride];
+            const float v2 = src[(int64_t)(g + 16) * stride], v3 = src[(int64_t)(g + 24) * stride];
+            acc += v0;
+            acc += v1;
+            acc += v2;
+            acc += v3;
+        }
+        for (; g < G; g += 8) acc += src[(int64_t)g * stride];
+    }
+    red[sl][i] = acc;
+    __syncthreads();
+    if (sl == 0 && in) {
+        float sum = 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum += red[k][i];
         if (idx < total) {
             const int j = (int)(idx / N), n = (int)(idx % N);
-            if (j >= Jv || n >= Nv) continue;
-            float s = 0.f;
-            for (int g = 0; g < G; ++g) s += part[(int64_t)g * total + idx];
-            grad[woff + (int64_t)j * ldw + n] = s;
+            if (j < Jv && n < Nv) grad[woff + (int64_t)j * ldw + n] = sum;
         } else {
             const int n = (int)(idx - total);
-            if (n >= Nv) continue;
-            float s = 0.f;
-            for (int g = 0; g < G; ++g) s += colsum[(int64_t)g * N + n];
-            grad[boff + n] = s;
+            if (n < Nv) grad[boff + n] = sum;
         }
     }
 }
@@ -763,8 +811,13 @@ static int launch_rows(const MlpDims& d, const float* params, const uint16_t* wo
                        hipStream_t st)
 {
     const size_t lds = ppo_rows_lds_bytes<H>(W, d.A1p);
-    ppo_rows_kernel<H><<<(unsigned)ntiles, 256, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[1], T[2], T[3],
-                                                           T[4], T[5], loss_parts);
+    const unsigned grid = (unsigned)ntiles;
+    if (W <= 4)
+        ppo_rows_kernel<H, 1><<<grid, 256, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[1], T[2], T[3], T[4],
+                                                      T[5], loss_parts);
+    else
+        ppo_rows_kernel<H, 8><<<grid, 256, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[1], T[2], T[3], T[4],
+                                                      T[5], loss_parts);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }
@@ -1259,7 +1312,7 @@ static int ppo_weight_grads_and_loss(const MlpDims& d, const PpoWorkspace& w, un
     if ((rc = launch_dw(T[0], d.K1p, T[5], d.H, w.nmb, G, p1, c1, st)) != EJ_OK) return rc;
     if ((rc = launch_dw(T[1], d.H, T[4], d.H, w.nmb, G, p2, c2, st)) != EJ_OK) return rc;
     if ((rc = launch_dw(T[2], d.H, T[3], d.A1p, w.nmb, G, p3, c3, st)) != EJ_OK) return rc;
-    auto red_blocks = [](int64_t n) { int64_t bl = (n + 255) / 256; return (unsigned)(bl > 2048 ? 2048 : bl); };
+    auto red_blocks = [](int64_t n) { return (unsigned)((n + 31) / 32); };
     dw_reduce_kernel<<<red_blocks((int64_t)d.K1p * d.H + d.H), 256, 0, st>>>(p1, c1, d.K1p, d.H, G, d.D, d.H, d_grads,
                                                                             d.oW1, d.H, d.ob1);
     EJ_LAUNCH_CHECK();
