@@ -45,7 +45,7 @@ extern "C" {
 #define EJ_ESCRATCH (-5)     /* request larger than EJ_PPO_STATIC_SCRATCH_BYTES */
 
 #define EJ_MAX_N 1024 /* agents per economy */
-#define EJ_MAX_R 8    /* resource types */
+#define EJ_MAX_R 16   /* resource types */
 #define EJ_MAX_P 128  /* price levels */
 #define EJ_MAX_K 16   /* tax brackets */
 #define EJ_MAX_X 32   /* order lifetime in steps */
@@ -256,8 +256,8 @@ int ej_env_status(ej_env* env, int64_t* h_invalid_actions, int64_t* h_invalid_go
  * followed by its bias, for W1, b1, W2, b2, W3, b3; W3 has A + 1 columns,
  * the last one the value head).  The kernels read a bf16 "work" copy in
  * their own chunked layout, refreshed by ej_mlp_sync_weights.
- * Supported: D <= 64, D_stride a multiple of 8 in [D, 64], H in
- * {64, 128, 256, 512}, A + 1 <= 1024.
+ * Supported: D_stride a multiple of 8 in [D, 128] (above 64 only with
+ * H >= 128 and 64-row tiles), H in {64, 128, 256, 512}, A + 1 <= 1024.
  * ------------------------------------------------------------------------ */
 typedef struct ej_mlp_desc {
     int32_t D, D_stride, H, A;

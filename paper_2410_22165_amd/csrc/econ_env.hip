@@ -1624,7 +1624,7 @@ using namespace econ;
 
 struct ej_env {
     EnvParams P;
-    int E = 0, NT = 64, APT = 1, variant = 0;  // variant 0: R<=4, X<=16; 1: R<=8, X<=32
+    int E = 0, NT = 64, APT = 1, variant = 0;  // variant 0: R<=4, X<=16; 1: R<=8, X<=32; 2: R<=16, X<=32
     int64_t M = 0;
     std::vector<int32_t> n, off, row;
     int32_t* d_field = nullptr;
@@ -1672,7 +1672,7 @@ static int choose_step_shape(ej_env* h, int apw)
 {
     if (apw != 64 && apw != 32 && apw != 16) return EJ_EINVAL;
     const int waves = (h->P.N + apw - 1) / apw;
-    if (waves * 64 > 1024) return EJ_EUNSUPPORTED;
+    if (waves * 64 > (h->variant == 2 ? 256 : 1024)) return EJ_EUNSUPPORTED;
     h->P.apw = apw;
     h->step_NT = waves * 64;
     h->step_lds = lds_layout(h->P, waves * apw * h->APT, nullptr, nullptr);
@@ -1684,7 +1684,8 @@ static int choose_step_shape(ej_env* h, int apw)
 #define EJ_DISPATCH(h, KERNEL, ...)                                                                        \
     do {                                                                                                    \
         if ((h)->variant == 0) KERNEL<4, 16, 1><<<(h)->E, (h)->NT, (h)->lds, st>>>(__VA_ARGS__);           \
-        else KERNEL<8, 32, 1><<<(h)->E, (h)->NT, (h)->lds, st>>>(__VA_ARGS__);                             \
+        else if ((h)->variant == 1) KERNEL<8, 32, 1><<<(h)->E, (h)->NT, (h)->lds, st>>>(__VA_ARGS__);      \
+        else KERNEL<16, 32, 1><<<(h)->E, (h)->NT, (h)->lds, st>>>(__VA_ARGS__);                            \
     } while (0)
 
 extern "C" {
@@ -1756,7 +1757,7 @@ int ej_env_create(const ej_env_config* cfg, const int32_t* h_n_per_env, ej_env**
     std::memcpy(P.cutoffs, cfg->cutoffs, sizeof(P.cutoffs));
     P.sc = cfg->scales;
     h->E = cfg->E;
-    h->variant = (P.R <= 4 && P.X <= 16) ? 0 : 1;
+    h->variant = (P.R <= 4 && P.X <= 16) ? 0 : P.R <= 8 ? 1 : 2;
     h->n.resize(h->E);
     h->off.resize(h->E);
     h->row.resize(h->E + 1);
@@ -1781,6 +1782,7 @@ int ej_env_create(const ej_env_config* cfg, const int32_t* h_n_per_env, ej_env**
     h->M = rows;
     P.Ntot = slots;
     rc = choose_launch(h, 1);
+    if (rc == EJ_OK && h->variant == 2 && h->NT > 256) rc = EJ_EUNSUPPORTED;  // R > 8: populations of <= 256
     if (rc != EJ_OK) {
         delete h;
         return rc;
@@ -1907,11 +1909,14 @@ int ej_env_step_range(ej_env* h, int32_t e_begin, int32_t e_end, const int32_t* 
         else if (h->variant == 0)                                                                            \
             KERNEL<4, 16, 1, 1024><<<G, nt, lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs, \
                                                        d_mask, e_begin);                                     \
-        else if (small)                                                                                      \
+        else if (h->variant == 1 && small)                                                                   \
             KERNEL<8, 32, 1, 256><<<G, nt, lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs,  \
                                                       d_mask, e_begin);                                      \
-        else                                                                                                 \
+        else if (h->variant == 1)                                                                            \
             KERNEL<8, 32, 1, 1024><<<G, nt, lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs, \
+                                                       d_mask, e_begin);                                     \
+        else /* variant 2: at most 256 threads (creation and choose_step_shape) */                           \
+            KERNEL<16, 32, 1, 256><<<G, nt, lds, st>>>(h->P, S, d_act, d_gov, d_rew, d_gov_rew, d_done, d_obs, \
                                                        d_mask, e_begin);                                     \
     } while (0)
     if (h->mode == 1 && whole) {

@@ -25,19 +25,25 @@ struct MlpDims {
 
 __host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-constexpr int K1P = 64;  // first-layer input padded to 64 (one layout for every D <= 64)
+// First-layer input padded to K1p = 64 columns for rows of at most 64
+// features (D_stride <= 64), else to 128 (wide rows, H >= 128: the LDS row of
+// activations, H + 8 columns, must hold them).  The LDS tile and the K-chunk
+// layout of W1 take K1p columns; the product runs K1p / 32 k-steps.
+constexpr int K1P = 64;
+constexpr int K1P_WIDE = 128;
 
 __host__ inline int mlp_dims(int D, int Ds, int H, int A, MlpDims* d)
 {
-    if (D <= 0 || D > 64 || Ds < D || (Ds & 7) != 0 || Ds > 64) return EJ_EUNSUPPORTED;
+    if (D <= 0 || Ds < D || (Ds & 7) != 0 || Ds > K1P_WIDE) return EJ_EUNSUPPORTED;
     if (!(H == 64 || H == 128 || H == 256 || H == 512)) return EJ_EUNSUPPORTED;
+    if (Ds > K1P && H < 128) return EJ_EUNSUPPORTED;
     if (A <= 0 || A + 1 > 1024) return EJ_EUNSUPPORTED;
     d->D = D;
     d->Ds = Ds;
     d->H = H;
     d->A = A;
     d->A1 = A + 1;
-    d->K1p = K1P;
+    d->K1p = Ds <= K1P ? K1P : K1P_WIDE;
     d->A1p = round_up(A + 1, 128);
     d->NC = d->A1p / 128;
     int64_t o = 0;
@@ -125,6 +131,17 @@ __device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int
                 acc[rt][ct] = TRANS ? mfma16(bq[kt][ct], aq[kt][rt], acc[rt][ct])
                                     : mfma16(aq[kt][rt], bq[kt][ct], acc[rt][ct]);
     }
+}
+
+// The first layer: K1p = 64 or 128 input columns, two or four k-steps
+template <int TR, int CTW, bool ZERO, int PF, bool PIN, bool TRANS>
+__device__ inline void dense_first(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int as,
+                                   const uint16_t* __restrict__ wglob, int64_t kstride, int col0, int K1p)
+{
+    if (K1p == K1P)
+        dense_cs<TR, CTW, K1P / 32, ZERO, PF, PIN, TRANS>(acc, abuf, as, wglob, kstride, col0);
+    else
+        dense_cs<TR, CTW, K1P_WIDE / 32, ZERO, PF, PIN, TRANS>(acc, abuf, as, wglob, kstride, col0);
 }
 
 // Transposed accumulators (dense_cs with TRANS) started at the bias: lane

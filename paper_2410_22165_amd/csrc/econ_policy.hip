@@ -41,8 +41,9 @@ size_t policy_lds_bytes(int W, int A1p)
 }
 
 // The workgroup's threads talk through LDS only (its barriers order LDS).
-// 64-row tiles with H <= 256 take 38.5 KB of LDS and 128 VGPRs: four workgroups per CU
-template <int H, int RPW_>
+// 64-row tiles with H <= 256 take 38.5 KB of LDS and 128 VGPRs: four workgroups per CU.
+// K1: first-layer input columns (64, or 128 for wide observation rows).
+template <int H, int RPW_, int K1>
 __global__ void __launch_bounds__(256, (RPW_ == 16 && H <= 256) ? 4 : 1)
 policy_forward_kernel(const MlpDims d, const float* __restrict__ params_all, const uint16_t* __restrict__ work_all,
                       const uint16_t* __restrict__ obs, const uint32_t* __restrict__ mask, int64_t M, int64_t row_base,
@@ -82,20 +83,24 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params_all, con
         }
     };
     draw_uniforms(0);
-    // observation tile -> activation buffer columns [0, K1p); mask rows -> LDS
-    // (TILE x K1P / 8 pieces of 16 bytes: every load is issued before the first store)
+    // observation tile -> activation buffer columns [0, K1p), 64 columns at a
+    // time (TILE x 8 pieces of 16 bytes: every load of a half is issued before
+    // its first store); mask rows -> LDS
     constexpr int NPC = TILE * (K1P / 8) / 256;
-    uint4 pv[NPC];
+    for (int h = 0; h < K1 / K1P; ++h) {
+        uint4 pv[NPC];
 #pragma unroll
-    for (int i = 0; i < NPC; ++i) {
-        const int p = threadIdx.x + 256 * i, r = p >> 3, cc = p & 7;
-        const int64_t row = row0 + r;
-        pv[i] = (row < M && cc * 8 < d.Ds) ? *(const uint4*)(obs + grow(row) * d.Ds + cc * 8) : uint4{0u, 0u, 0u, 0u};
-    }
+        for (int i = 0; i < NPC; ++i) {
+            const int p = threadIdx.x + 256 * i, r = p >> 3, cc = h * 8 + (p & 7);
+            const int64_t row = row0 + r;
+            pv[i] = (row < M && cc * 8 < d.Ds) ? *(const uint4*)(obs + grow(row) * d.Ds + cc * 8)
+                                                : uint4{0u, 0u, 0u, 0u};
+        }
 #pragma unroll
-    for (int i = 0; i < NPC; ++i) {
-        const int p = threadIdx.x + 256 * i;
-        *(uint4*)(hbuf + (p >> 3) * HS + (p & 7) * 8) = pv[i];
+        for (int i = 0; i < NPC; ++i) {
+            const int p = threadIdx.x + 256 * i;
+            *(uint4*)(hbuf + (p >> 3) * HS + (h * 8 + (p & 7)) * 8) = pv[i];
+        }
     }
     for (int p = threadIdx.x; p < TILE * W; p += 256) {
         const int r = p / W;
@@ -115,7 +120,7 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params_all, con
         f32x4 acc[TR][CTW];
         bias_init_t<TR, CTW>(acc, params + d.ob1, col0);
         lds_barrier();  // observation tile in LDS
-        dense_cs<TR, CTW, 2, false, 2, false, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
+        dense_cs<TR, CTW, K1 / 32, false, 2, false, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);
         lds_barrier();  // every wave is done reading the observations
         relu_store_t<TR, CTW>(acc, hbuf, HS, col0);
         bias_init_t<TR, CTW>(acc, params + d.ob2, col0);
@@ -316,8 +321,19 @@ int launch_policy_forward(const MlpDims& d, const float* params, const uint16_t*
     using T = MlpTile<H, RPW>;
     const int64_t blocks = (M + T::TILE - 1) / T::TILE;
     const size_t lds = policy_lds_bytes<H, RPW>(W, d.A1p);
-    policy_forward_kernel<H, RPW><<<dim3((unsigned)blocks, (unsigned)groups), 256, lds, st>>>(
-        d, params, work, obs, mask, M, row_base, W, seed, ctr, ctr_base, act, logp, val, ent, logits, grp);
+    const dim3 grid((unsigned)blocks, (unsigned)groups);
+    if (d.K1p == K1P) {
+        policy_forward_kernel<H, RPW, K1P><<<grid, 256, lds, st>>>(d, params, work, obs, mask, M, row_base, W, seed, ctr,
+                                                                 ctr_base, act, logp, val, ent, logits, grp);
+    } else {
+        // wide rows (mlp_dims: H >= 128; desc_dims: 64-row tiles)
+        if constexpr (RPW == 16 && H >= 128)
+            policy_forward_kernel<H, RPW, K1P_WIDE><<<grid, 256, lds, st>>>(d, params, work, obs, mask, M, row_base, W,
+                                                                          seed, ctr, ctr_base, act, logp, val, ent,
+                                                                          logits, grp);
+        else
+            return EJ_EUNSUPPORTED;
+    }
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }
@@ -329,7 +345,8 @@ using namespace econ;
 static int desc_dims(const ej_mlp_desc* m, MlpDims* d)
 {
     if (!m) return EJ_EINVAL;
-    if (m->tile_rows != 0 && m->tile_rows != 64 && !(m->tile_rows == 128 && m->H <= 256)) return EJ_EUNSUPPORTED;
+    if (m->tile_rows != 0 && m->tile_rows != 64 && !(m->tile_rows == 128 && m->H <= 256 && m->D_stride <= K1P))
+        return EJ_EUNSUPPORTED;
     return mlp_dims(m->D, m->D_stride, m->H, m->A, d);
 }
 

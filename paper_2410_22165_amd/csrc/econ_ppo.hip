@@ -288,11 +288,28 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     const int col0 = wave * (H / 4);
 
     // gather registers (the tile's inputs)
-    constexpr int NPC = TILE * (K1P / 8) / 256;  // 16-byte observation pieces per thread
+    constexpr int NPC = TILE * (K1P / 8) / 256;  // 16-byte observation pieces per thread and 64 columns
     uint4 pv[NPC];
     float gs[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // act (bits), logp_old, val_old, adv, ret of row threadIdx.x
     uint32_t gm[MWP];
     float mean = 0.f, istd = 0.f;  // advantage normalisation of the minibatch
+    auto obs_half = [&](int64_t tile, int h) {  // observation columns [64 h, 64 h + 64)
+        const int64_t row0 = tile * TILE;
+#pragma unroll
+        for (int i = 0; i < NPC; ++i) {
+            const int p = threadIdx.x + 256 * i, r = p >> 3, cc = h * 8 + (p & 7);
+            const int64_t j = row0 + r;
+            pv[i] = (j < B.rows && cc * 8 < d.Ds) ? *(const uint4*)(B.obs + sample_of(B, j) * d.Ds + cc * 8)
+                                                   : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    auto store_half = [&](int h) {
+#pragma unroll
+        for (int i = 0; i < NPC; ++i) {
+            const int p = threadIdx.x + 256 * i;
+            *(uint4*)(hbuf + (p >> 3) * HS + (h * 8 + (p & 7)) * 8) = pv[i];
+        }
+    };
     auto gather = [&](int64_t tile) {
         const int64_t row0 = tile * TILE;
         mean = stats[0];
@@ -312,13 +329,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
             const int64_t j = row0 + r;
             gm[i] = (r < TILE && j < B.rows) ? B.mask[sample_of(B, j) * W + (p - r * W)] : 0u;
         }
-#pragma unroll
-        for (int i = 0; i < NPC; ++i) {
-            const int p = threadIdx.x + 256 * i, r = p >> 3, cc = p & 7;
-            const int64_t j = row0 + r;
-            pv[i] = (j < B.rows && cc * 8 < d.Ds) ? *(const uint4*)(B.obs + sample_of(B, j) * d.Ds + cc * 8)
-                                                   : uint4{0u, 0u, 0u, 0u};
-        }
+        obs_half(tile, 0);
     };
     auto commit = [&](int64_t tile) {
         const int64_t row0 = tile * TILE;
@@ -337,10 +348,10 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
             const int p = threadIdx.x + 256 * i;
             if (p < TILE * W) smask[p] = gm[i];
         }
-#pragma unroll
-        for (int i = 0; i < NPC; ++i) {
-            const int p = threadIdx.x + 256 * i;
-            *(uint4*)(hbuf + (p >> 3) * HS + (p & 7) * 8) = pv[i];
+        store_half(0);
+        if (d.K1p > K1P) {  // wide rows: the second 64 columns, one more round trip
+            obs_half(tile, 1);
+            store_half(1);
         }
     };
 
@@ -357,7 +368,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     // output also leaves as m-blocks for the weight gradients
     f32x4 acc[TR][CTW];
     uint32_t m1[TR], m2[TR];
-    dense_cs<TR, CTW, 2, true, 2, true, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0);  // K1p = 64
+    dense_first<TR, CTW, true, 2, true, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0, d.K1p);
     lds_barrier();  // every wave is done reading the observations
     ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias, hbuf, HS, col0, m1);
     lds_barrier();
@@ -1211,7 +1222,7 @@ __global__ void sum_steps_kernel(const float* __restrict__ x, int t0, int t1, in
 static int gov_dims(const ej_mlp_desc* m, int32_t K, MlpDims* d)
 {
     if (!m || K < 1 || K > GOV_MAXK || m->A != K * GOV_LEVELS) return EJ_EINVAL;
-    if (m->H > 256) return EJ_EUNSUPPORTED;
+    if (m->H > 256 || m->D_stride > K1P) return EJ_EUNSUPPORTED;  // (its kernels take 64 input columns)
     return mlp_dims(m->D, m->D_stride, m->H, m->A, d);
 }
 }  // namespace econ

@@ -55,3 +55,22 @@ def test_static_scratch_backward_rejects_oversize_on_the_host():
     rc = L.ej_ppo_backward_static(C.byref(desc), None, None, C.byref(b), C.byref(h), None, None, None)
     assert rc == binding.EJ_ESCRATCH
     assert L.ej_ppo_backward_static(None, None, None, C.byref(b), C.byref(h), None, None, None) == -1
+
+
+def test_mlp_layout_limits_on_the_host():
+    """ej_mlp_layout (host only): rows of up to 64 features take a 64-column
+    first layer, wider rows (up to 128, H >= 128) a 128-column one; the
+    12-resource multi-agent economy gives 7 + 7 * 12 = 91 features."""
+    import ctypes as C
+    from paper_2410_22165_amd import binding
+    L = binding.lib()
+    out = binding.EjMlpLayout()
+    for D, Ds, H, ok in ((35, 40, 256, True), (64, 64, 64, True), (91, 96, 256, True), (128, 128, 512, True),
+                         (91, 96, 64, False), (129, 136, 256, False), (40, 36, 256, False)):
+        rc = L.ej_mlp_layout(C.byref(binding.EjMlpDesc(D, Ds, H, 86, 0)), C.byref(out))
+        assert (rc == 0) == ok, (D, Ds, H, rc)
+        if ok:
+            k1 = 64 if Ds <= 64 else 128
+            assert out.W1 == 0 and out.b1 == D * H and out.n_work == k1 * H + H * H + H * 128 + 128 * H + H * H
+    # 128-row tiles take rows of at most 64 features
+    assert L.ej_mlp_layout(C.byref(binding.EjMlpDesc(91, 96, 256, 86, 128)), C.byref(out)) != 0

@@ -262,8 +262,8 @@ def test_determinism_and_checkpoint_resume():
 def test_create_rejects_bad_configs():
     from paper_2410_22165_amd import binding
     base = W.env_config(E=2, N=4)
-    bad = [dict(N=2000), dict(R=9), dict(X=33), dict(K=17), dict(prices=[4, 2] + [6] * 8), dict(E=0),
-           dict(P=128, X=32, R=8)]
+    bad = [dict(N=2000), dict(R=17), dict(X=33), dict(K=17), dict(prices=[4, 2] + [6] * 8), dict(E=0),
+           dict(P=128, X=32, R=8), dict(R=12, N=300)]  # (more than 8 resources: populations of <= 256)
     for kv in bad:
         cfg = dict(base)
         cfg.update(kv)
@@ -357,7 +357,7 @@ def test_episode_metrics_match_oracle(variant):
     env.close()
 
 
-@pytest.mark.parametrize("R", [4, 8])
+@pytest.mark.parametrize("R", [4, 8, 12])
 def test_parity_multi_agent_variant_lockstep(R):
     """The multi-agent variant (Sec. 5): skills near 1 with spread 1 that
     grow with every gather and craft, taxes off, prices 3, 6, 9, R_d from R;
@@ -368,8 +368,10 @@ def test_parity_multi_agent_variant_lockstep(R):
 
 
 @pytest.mark.slow
-def test_parity_multi_agent_variant_sampled():
-    """64 economies of 100 agents with 4 resources (30 actions), order
-    lifetime 30, 1100 steps (an episode end at 1000), 2 sampled economies."""
-    cfg = W.variant_config(R=4, N=100, E=64, seed=2)
+@pytest.mark.parametrize("R", [4, 12])
+def test_parity_multi_agent_variant_sampled(R):
+    """64 economies of 100 agents with 4 or 12 resources (30 or 86 actions),
+    order lifetime 30, 1100 steps (an episode end at 1000), 2 sampled
+    economies."""
+    cfg = W.variant_config(R=R, N=100, E=64, seed=2)
     _sampled_parity(cfg, 1100, sample=[0, 41])

@@ -20,7 +20,9 @@ CASES = [  # (D, Ds, H, A, M)
     (49, 56, 512, 507, 333),       # 1000-agent economy: 5 resources, 50 prices
     (64, 64, 128, 300, 129),
     (35, 40, 256, 125, 1),
-    (64, 64, 256, 1000, 200),      # widest input (64 features) and 8 action chunks
+    (64, 64, 256, 1000, 200),      # 64 features and 8 action chunks
+    (91, 96, 256, 86, 500),        # 12-resource multi-agent economy: a 128-column first layer
+    (128, 128, 512, 300, 129),     # widest input (128 features)
 ]
 
 

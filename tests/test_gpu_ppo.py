@@ -196,7 +196,8 @@ def assert_elementwise(got, want, B, rtol=1e-2, floor=2.0 ** -7, where=""):
 
 @pytest.mark.parametrize("case", [(35, 40, 256, 125, 3000, 1000, 10.0), (11, 16, 64, 9, 500, 77, 10.0),
                                   (49, 56, 512, 507, 1200, 300, 10.0), (64, 64, 128, 300, 700, 700, 10.0),
-                                  (35, 40, 256, 125, 3000, 1000, 0.2), (49, 56, 512, 507, 1200, 300, 0.2)])
+                                  (35, 40, 256, 125, 3000, 1000, 0.2), (49, 56, 512, 507, 1200, 300, 0.2),
+                                  (91, 96, 256, 86, 2000, 700, 10.0)])
 def test_ppo_backward_matches_reference_autograd(case):
     """Every gradient element against the float64 reference autograd at
     1e-2 relative plus the bf16 floor 2^-7 B (reference_with_bounds), on
@@ -303,6 +304,12 @@ def test_ppo_backward_finite_differences_large_action_space():
     50-price workload, on one minibatch of one economy's rows (1000-agent
     economies; 2000 generated, the kink-free ones kept)."""
     _fd_check(49, 56, 512, 507, 2000, seed=12, n_pick=6)
+
+
+def test_ppo_backward_finite_differences_wide_rows():
+    """The 91 -> 256 -> 256 -> 86 + 1 network of the 12-resource multi-agent
+    economy (a 128-column first layer)."""
+    _fd_check(91, 96, 256, 86, 300, seed=13)
 
 
 def test_ppo_backward_deterministic():
