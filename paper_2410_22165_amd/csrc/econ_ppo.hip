@@ -8,17 +8,20 @@
 //
 // Backward data flow for a minibatch of `rows` samples (row j of the epoch
 // maps to sample (a j + c) mod M):
-//   ppo_rows_kernel  per 128-row tile: gathers the samples, recomputes
+//   ppo_rows_kernel  per 64-row tile: gathers the samples, recomputes
 //     h1, h2 and the logits (never stored per rollout: activations are
 //     recomputed here), forms the loss gradient dY = dL/d[logits | value]
 //     from the row statistics of the masked softmax, and back-propagates
 //     dh2 = (dY W3^T) * [h2 > 0] and dh1 = (dh2 W2^T) * [h1 > 0].  The GEMM
-//     operands of the weight gradients (obs, h1, h2, dY, dh2, dh1) are
-//     written in bf16 "m-block" layout [rows / 32][column][32 rows].
+//     operands of the weight gradients h2, dY, dh2, dh1 are written in bf16
+//     "m-block" layout [rows / 32][column][32 rows]; the gathered
+//     observations leave as plain rows [rows][K1p].
 //   dw_kernel        dW = X^T Y as bf16 MFMA with the 32-row m-block as the
 //     k-step; every workgroup owns a C tile and a contiguous range of
 //     m-blocks and writes an fp32 partial; column sums of Y give the bias
-//     gradients.
+//     gradients.  dW1 transposes the observation rows into its LDS tile; dW2
+//     recomputes h1 from them (a quarter of dW2's products), so neither the
+//     observations' m-blocks nor h1 pass through HBM.
 //   dw_reduce_kernel sums the partials in a fixed order (deterministic).
 #include "econ_mlp.h"
 
@@ -256,8 +259,9 @@ size_t ppo_rows_lds_bytes(int W, int A1p)
 // One fused pass over a tile of minibatch rows: recompute the forward (bf16
 // MFMA), the masked-softmax statistics and the loss terms, then dY = dL/d
 // [logits | value], dh2 = (dY W3^T) * [h2 > 0] and dh1 = (dh2 W2^T) *
-// [h1 > 0].  The weight-gradient GEMMs read the m-block copies written here.
-// The workgroup's threads talk through LDS only.
+// [h1 > 0].  The weight-gradient GEMMs read the m-block copies and the
+// observation rows written here.  The workgroup's threads talk through LDS
+// only.
 //
 // The rows of a minibatch are scattered samples (the permutation), so their
 // gather is latency-bound: every load of the tile's inputs (observation, mask
@@ -268,9 +272,8 @@ template <int H, int MWP>
 __global__ void __launch_bounds__(256, H <= 256 ? 2 : 1)  // H <= 256: 73 KB of LDS, two workgroups per CU
 ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
                 const PpoBatchDev B, const PpoHp hp, const float* __restrict__ stats, int W,
-                uint16_t* __restrict__ Tobs, uint16_t* __restrict__ Th1, uint16_t* __restrict__ Th2,
-                uint16_t* __restrict__ TdY, uint16_t* __restrict__ Tdh2, uint16_t* __restrict__ Tdh1,
-                float* __restrict__ loss_parts)
+                uint16_t* __restrict__ Orows, uint16_t* __restrict__ Th2, uint16_t* __restrict__ TdY,
+                uint16_t* __restrict__ Tdh2, uint16_t* __restrict__ Tdh1, float* __restrict__ loss_parts)
 {
     using P = PpoTile<H>;
     constexpr int TILE = P::TILE, TR = P::TR, HS = P::HS, CTW = P::CTW, YS = P::YS;
@@ -303,11 +306,12 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
                                                    : uint4{0u, 0u, 0u, 0u};
         }
     };
-    auto store_half = [&](int h) {
+    auto store_half = [&](int64_t tile, int h) {  // -> the LDS tile and the minibatch's observation rows
 #pragma unroll
         for (int i = 0; i < NPC; ++i) {
-            const int p = threadIdx.x + 256 * i;
-            *(uint4*)(hbuf + (p >> 3) * HS + (h * 8 + (p & 7)) * 8) = pv[i];
+            const int p = threadIdx.x + 256 * i, cc = h * 8 + (p & 7);
+            *(uint4*)(hbuf + (p >> 3) * HS + cc * 8) = pv[i];
+            *(uint4*)(Orows + (tile * TILE + (p >> 3)) * d.K1p + cc * 8) = pv[i];
         }
     };
     auto gather = [&](int64_t tile) {
@@ -348,10 +352,10 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
             const int p = threadIdx.x + 256 * i;
             if (p < TILE * W) smask[p] = gm[i];
         }
-        store_half(0);
+        store_half(tile, 0);
         if (d.K1p > K1P) {  // wide rows: the second 64 columns, one more round trip
             obs_half(tile, 1);
-            store_half(1);
+            store_half(tile, 1);
         }
     };
 
@@ -362,7 +366,6 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     lds_barrier();
     const int64_t tile_row0 = tile * TILE;
     const int64_t mb0 = tile_row0 >> 5;
-    tile_to_mblocks(hbuf, HS, TILE, d.K1p, Tobs, mb0, d.K1p, 0);  // observations for dW1
 
     // ---- forward of the hidden layers (column split); every layer's bf16
     // output also leaves as m-blocks for the weight gradients
@@ -372,7 +375,6 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     lds_barrier();  // every wave is done reading the observations
     ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias, hbuf, HS, col0, m1);
     lds_barrier();
-    tile_to_mblocks(hbuf, HS, TILE, H, Th1, mb0, H, 0);
     dense_cs<TR, CTW, H / 32, true, 3, true, true>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
     lds_barrier();
     ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias + H, hbuf, HS, col0, m2);
@@ -550,14 +552,32 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
 // ---------------------------------------------------------------------------
 // weight gradients: C[j][n] = sum_m X[m][j] Y[m][n] over m-blocks
 // ---------------------------------------------------------------------------
-template <int WJ, int WN, int TJ, int TN>
+// Where X comes from.  XM_BLOCKS: X's own m-blocks.  XM_OBS: X is the
+// observation tile, read as minibatch rows [rows][K1p] and transposed into
+// the LDS tile (dW1).  XM_H1: X = h1 = relu(obs W1 + b1), recomputed for the
+// tile's columns from the observation rows with the same bf16 MFMA products
+// and rounding as the row kernel (dW2), so that h1 never passes through HBM.
+enum { XM_BLOCKS = 0, XM_OBS = 1, XM_H1 = 2 };
+
+struct DwX {
+    const uint16_t* obs;  // [rows][K1p] bf16 observation rows, minibatch order (XM_OBS, XM_H1)
+    const uint16_t* w1f;  // W1 K-chunks [K1p / 32][H][32] (XM_H1)
+    const float* b1;      // [H] (XM_H1)
+    int K1p;
+};
+
+template <int WJ, int WN, int TJ, int TN, int XM, int NK1 = 2>
 __global__ void __launch_bounds__(WJ* WN * 64)
 dw_kernel(const uint16_t* __restrict__ Tx, int J, const uint16_t* __restrict__ Ty, int N, int64_t nmb, int G,
-          float* __restrict__ part, float* __restrict__ colsum)
+          float* __restrict__ part, float* __restrict__ colsum, const DwX xsrc)
 {
-    constexpr int CJ = WJ * TJ * 16, CN = WN * TN * 16, NTH = WJ * WN * 64;
-    __shared__ __align__(16) uint16_t xs[CJ * WSTRIDE];
-    __shared__ __align__(16) uint16_t ys[CN * WSTRIDE];
+    constexpr int CJ = WJ * TJ * 16, CN = WN * TN * 16, NTH = WJ * WN * 64, NW = NTH / 64;
+    // two LDS stages of [X tile | Y tile]: the products of an m-block read one
+    // stage while the next m-block is written to the other (one barrier per
+    // m-block)
+    extern __shared__ __align__(16) unsigned char dw_smem[];
+    constexpr int STAGE = (CJ + CN) * WSTRIDE;  // bf16 elements per stage
+    uint16_t* const lds0 = (uint16_t*)dw_smem;
     const int njt = J / CJ;
     const int jt = blockIdx.x % njt, nt = blockIdx.x / njt;
     const int j0 = jt * CJ, n0 = nt * CN;
@@ -573,26 +593,98 @@ dw_kernel(const uint16_t* __restrict__ Tx, int J, const uint16_t* __restrict__ T
     float cs = 0.f;
     constexpr int PX = CJ * 4, PY = CN * 4;  // 16-byte pieces per tile (at most two per thread)
     static_assert(PX <= 2 * NTH && PY <= 2 * NTH, "two prefetch registers per operand");
-    uint4 rx0, rx1, ry0, ry1;  // plain scalars: an array here lands in scratch memory
+
+    // XM_H1: the X tile is CJ / 16 column tiles x 2 row tiles of 16 x 16; wave
+    // w computes XT of them (tiles t = w XT + i: column tile t / 2, row tile
+    // t % 2) from its W1 fragments (held for the whole launch) and the
+    // observation fragments of the m-block
+    constexpr int XT = XM == XM_H1 ? CJ / 8 / NW : 1;
+    constexpr int XJ = XT >= 2 ? XT / 2 : 1;  // distinct column tiles per wave
+    constexpr int XR = XT >= 2 ? 2 : 1;       // row tiles per wave
+    static_assert(XM != XM_H1 || (XT >= 1 && (XT == 1 || XT % 2 == 0)), "X tiles per wave");
+    bf16x8 w1q[XM == XM_H1 ? XJ : 1][NK1];
+    float b1v[XM == XM_H1 ? XJ : 1];
+    const int xt0 = wave * XT;
+    if constexpr (XM == XM_H1) {
+#pragma unroll
+        for (int a = 0; a < XJ; ++a) {
+            const int j = j0 + ((xt0 >> 1) + a) * 16 + (l & 15);
+            b1v[a] = xsrc.b1[j];
+#pragma unroll
+            for (int kt = 0; kt < NK1; ++kt)  // (X = h1 has J = H columns: W1f is [K1p / 32][J][32])
+                w1q[a][kt] = *(const bf16x8*)(xsrc.w1f + ((int64_t)kt * J + j) * 32 + 8 * (l >> 4));
+        }
+    }
+
+    // the next m-block's global data (plain scalars: arrays indexed at run
+    // time would land in scratch memory)
+    uint4 rx0, rx1, ry0, ry1;
+    bf16x8 oq[XM == XM_H1 ? XR : 1][NK1];
     auto load = [&](int64_t mb) {
         const int p0 = threadIdx.x, p1 = threadIdx.x + NTH;
-        if (p0 < PX) rx0 = *(const uint4*)(Tx + (mb * J + j0 + (p0 >> 2)) * 32 + (p0 & 3) * 8);
-        if (p1 < PX) rx1 = *(const uint4*)(Tx + (mb * J + j0 + (p1 >> 2)) * 32 + (p1 & 3) * 8);
+        if constexpr (XM == XM_BLOCKS) {
+            if (p0 < PX) rx0 = *(const uint4*)(Tx + (mb * J + j0 + (p0 >> 2)) * 32 + (p0 & 3) * 8);
+            if (p1 < PX) rx1 = *(const uint4*)(Tx + (mb * J + j0 + (p1 >> 2)) * 32 + (p1 & 3) * 8);
+        } else if constexpr (XM == XM_OBS) {  // piece p: row p / (CJ / 8), columns 8 (p % (CJ / 8)) .. + 7
+            constexpr int PR = CJ / 8;
+            if (p0 < PX) rx0 = *(const uint4*)(xsrc.obs + (mb * 32 + p0 / PR) * xsrc.K1p + j0 + (p0 % PR) * 8);
+            if (p1 < PX) rx1 = *(const uint4*)(xsrc.obs + (mb * 32 + p1 / PR) * xsrc.K1p + j0 + (p1 % PR) * 8);
+        } else {  // A operand of obs W1: row m = 16 mt + lane % 16, k = 32 kt + 8 (lane / 16) .. + 7
+#pragma unroll
+            for (int r = 0; r < XR; ++r) {
+                const int mt = XT >= 2 ? r : (xt0 & 1);
+#pragma unroll
+                for (int kt = 0; kt < NK1; ++kt)
+                    oq[r][kt] = *(const bf16x8*)(xsrc.obs + (mb * 32 + mt * 16 + (l & 15)) * xsrc.K1p + kt * 32 +
+                                                   8 * (l >> 4));
+            }
+        }
         if (p0 < PY) ry0 = *(const uint4*)(Ty + (mb * N + n0 + (p0 >> 2)) * 32 + (p0 & 3) * 8);
         if (p1 < PY) ry1 = *(const uint4*)(Ty + (mb * N + n0 + (p1 >> 2)) * 32 + (p1 & 3) * 8);
     };
-    if (mb0 < mb1) load(mb0);
-    for (int64_t mb = mb0; mb < mb1; ++mb) {
-        __syncthreads();
-        {
-            const int p0 = threadIdx.x, p1 = threadIdx.x + NTH;
+    // observation piece -> eight transposed bf16 entries of the X tile
+    auto put_obs = [&](uint16_t* xs, int p, const uint4& v) {
+        constexpr int PR = CJ / 8;
+        const int m = p / PR, jj = (p % PR) * 8;
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xs[(jj + i) * WSTRIDE + m] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+    };
+    // registers -> LDS stage s (the X tile computed in XM_H1)
+    auto produce = [&](int s) {
+        uint16_t* xs = lds0 + s * STAGE;
+        uint16_t* ys = xs + CJ * WSTRIDE;
+        const int p0 = threadIdx.x, p1 = threadIdx.x + NTH;
+        if constexpr (XM == XM_BLOCKS) {
             if (p0 < PX) *(uint4*)(xs + (p0 >> 2) * WSTRIDE + (p0 & 3) * 8) = rx0;
             if (p1 < PX) *(uint4*)(xs + (p1 >> 2) * WSTRIDE + (p1 & 3) * 8) = rx1;
-            if (p0 < PY) *(uint4*)(ys + (p0 >> 2) * WSTRIDE + (p0 & 3) * 8) = ry0;
-            if (p1 < PY) *(uint4*)(ys + (p1 >> 2) * WSTRIDE + (p1 & 3) * 8) = ry1;
+        } else if constexpr (XM == XM_OBS) {
+            if (p0 < PX) put_obs(xs, p0, rx0);
+            if (p1 < PX) put_obs(xs, p1, rx1);
+        } else {  // h1 = relu(obs W1 + b1) -> bf16, lane: column j, rows 4 (lane / 16) .. + 3
+#pragma unroll
+            for (int i = 0; i < XT; ++i) {
+                const int t = xt0 + i, a = XT >= 2 ? i >> 1 : 0, r = XT >= 2 ? (i & 1) : 0;
+                f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kt = 0; kt < NK1; ++kt) h = mfma16(oq[r][kt], w1q[a][kt], h);
+                uint32_t hb[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float x = h[e] + b1v[a];
+                    hb[e] = f32_to_bf16(x > 0.f ? x : 0.f);
+                }
+                *(uint2*)(xs + ((t >> 1) * 16 + (l & 15)) * WSTRIDE + (t & 1) * 16 + 4 * (l >> 4)) =
+                    uint2{hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16)};
+            }
         }
-        __syncthreads();
-        if (mb + 1 < mb1) load(mb + 1);
+        if (p0 < PY) *(uint4*)(ys + (p0 >> 2) * WSTRIDE + (p0 & 3) * 8) = ry0;
+        if (p1 < PY) *(uint4*)(ys + (p1 >> 2) * WSTRIDE + (p1 & 3) * 8) = ry1;
+    };
+    // the products of the m-block in LDS stage s
+    auto consume = [&](int s) {
+        const uint16_t* xs = lds0 + s * STAGE;
+        const uint16_t* ys = xs + CJ * WSTRIDE;
         bf16x8 af[TJ];
 #pragma unroll
         for (int a = 0; a < TJ; ++a) af[a] = lds_frag(xs + (wj * TJ * 16 + a * 16 + (l & 15)) * WSTRIDE + 8 * (l >> 4));
@@ -607,6 +699,22 @@ dw_kernel(const uint16_t* __restrict__ Tx, int J, const uint16_t* __restrict__ T
 #pragma unroll
             for (int m = 0; m < 32; ++m) cs += bf16_to_f32(yrow[m]);
         }
+    };
+    // m-block mb sits in stage s and the registers hold m-block mb + 1: run
+    // the products of mb, write mb + 1 to the other stage, load mb + 2 (a
+    // whole m-block of products ahead of its use), one barrier
+    if (mb0 < mb1) {
+        load(mb0);
+        produce(0);
+        if (mb0 + 1 < mb1) load(mb0 + 1);
+        __syncthreads();
+    }
+    for (int64_t mb = mb0; mb < mb1; ++mb) {
+        const int s = (int)((mb - mb0) & 1);
+        consume(s);
+        if (mb + 1 < mb1) produce(s ^ 1);
+        if (mb + 2 < mb1) load(mb + 2);
+        __syncthreads();
     }
     float* out = part + (int64_t)g * J * N;
 #pragma unroll
@@ -718,8 +826,13 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// rows_mode (the population's row kernel): o_obs holds the observation rows
+// [rows][K1p] (the same bytes as their m-blocks) and there is no h1 buffer.
+// G1 row splits for dW1 (a narrow tile: two workgroups per CU), G for dW2
+// and dW3.
 struct PpoWorkspace {
-    int64_t nmb, ntiles, G;
+    int64_t nmb, ntiles, G, G1;
+    bool rows_mode;
     size_t o_obs, o_h1, o_h2, o_dy, o_dh2, o_dh1, o_p1, o_p2, o_p3, o_c1, o_c2, o_c3, o_adv, o_stats, o_loss, o_lslices,
         bytes;
 };
@@ -728,25 +841,28 @@ static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int ppo_tile_rows(int) { return 64; }
 
-static int ppo_workspace(const MlpDims& d, int64_t rows, PpoWorkspace* w)
+static int ppo_workspace(const MlpDims& d, int64_t rows, PpoWorkspace* w, bool rows_mode = true)
 {
     const int TILE = ppo_tile_rows(d.H);
+    w->rows_mode = rows_mode;
     w->ntiles = (rows + TILE - 1) / TILE;
     w->nmb = w->ntiles * TILE / 32;
     w->G = w->nmb < 256 ? w->nmb : 256;
     if (w->G < 1) w->G = 1;
+    w->G1 = w->nmb < 512 ? w->nmb : 512;
+    if (w->G1 < 1) w->G1 = 1;
     size_t o = 0;
     const size_t mbrow = (size_t)w->nmb * 32 * 2;  // bytes per column of an m-block buffer
     w->o_obs = o; o = al256(o + mbrow * d.K1p);
-    w->o_h1 = o; o = al256(o + mbrow * d.H);
+    w->o_h1 = o; o = al256(o + (rows_mode ? 0 : mbrow * d.H));
     w->o_h2 = o; o = al256(o + mbrow * d.H);
     w->o_dy = o; o = al256(o + mbrow * d.A1p);
     w->o_dh2 = o; o = al256(o + mbrow * d.H);
     w->o_dh1 = o; o = al256(o + mbrow * d.H);
-    w->o_p1 = o; o = al256(o + (size_t)w->G * d.K1p * d.H * 4);
+    w->o_p1 = o; o = al256(o + (size_t)w->G1 * d.K1p * d.H * 4);
     w->o_p2 = o; o = al256(o + (size_t)w->G * d.H * d.H * 4);
     w->o_p3 = o; o = al256(o + (size_t)w->G * d.H * d.A1p * 4);
-    w->o_c1 = o; o = al256(o + (size_t)w->G * d.H * 4);
+    w->o_c1 = o; o = al256(o + (size_t)w->G1 * d.H * 4);
     w->o_c2 = o; o = al256(o + (size_t)w->G * d.H * 4);
     w->o_c3 = o; o = al256(o + (size_t)w->G * d.A1p * 4);
     w->o_adv = o; o = al256(o + 2 * 1024 * 8);
@@ -793,25 +909,30 @@ static int static_scratch_address(void** out)
     return EJ_OK;
 }
 
+template <int XM, int NK1 = 2>
 static int launch_dw(const uint16_t* Tx, int J, const uint16_t* Ty, int N, int64_t nmb, int G, float* part,
-                     float* colsum, hipStream_t st)
+                     float* colsum, const DwX& xs, hipStream_t st)
 {
     auto grid = [&](int CJ, int CN) { return dim3((unsigned)((J / CJ) * (N / CN)), (unsigned)G); };
-    if (J % 256 == 0 && N % 256 == 0) {
-        dw_kernel<4, 2, 4, 8><<<grid(256, 256), 512, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
-    } else if (J % 256 == 0 && N % 128 == 0) {
-        dw_kernel<4, 2, 4, 4><<<grid(256, 128), 512, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
-    } else if (J % 128 == 0 && N % 128 == 0) {
-        dw_kernel<2, 2, 4, 4><<<grid(128, 128), 256, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
-    } else if (J % 64 == 0 && N % 256 == 0) {
-        dw_kernel<1, 8, 4, 2><<<grid(64, 256), 512, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
-    } else if (J % 64 == 0 && N % 128 == 0) {
-        dw_kernel<1, 4, 4, 2><<<grid(64, 128), 256, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
-    } else if (J % 64 == 0 && N % 64 == 0) {
-        dw_kernel<1, 4, 4, 1><<<grid(64, 64), 256, 0, st>>>(Tx, J, Ty, N, nmb, G, part, colsum);
-    } else {
+#define EJ_DW(WJ, WN, TJ, TN)                                                                                   \
+    dw_kernel<WJ, WN, TJ, TN, XM, NK1><<<grid(WJ * TJ * 16, WN * TN * 16), WJ * WN * 64,                        \
+                                         (size_t)2 * (WJ * TJ * 16 + WN * TN * 16) * WSTRIDE * 2, st>>>(            \
+        Tx, J, Ty, N, nmb, G, part, colsum, xs)
+    if (J % 256 == 0 && N % 256 == 0)
+        EJ_DW(4, 2, 4, 8);
+    else if (J % 256 == 0 && N % 128 == 0)
+        EJ_DW(4, 2, 4, 4);
+    else if (J % 128 == 0 && N % 128 == 0)
+        EJ_DW(2, 2, 4, 4);
+    else if (J % 64 == 0 && N % 256 == 0)
+        EJ_DW(1, 8, 4, 2);
+    else if (J % 64 == 0 && N % 128 == 0)
+        EJ_DW(1, 4, 4, 2);
+    else if (J % 64 == 0 && N % 64 == 0)
+        EJ_DW(1, 4, 4, 1);
+    else
         return EJ_EUNSUPPORTED;
-    }
+#undef EJ_DW
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }
@@ -824,11 +945,11 @@ static int launch_rows(const MlpDims& d, const float* params, const uint16_t* wo
     const size_t lds = ppo_rows_lds_bytes<H>(W, d.A1p);
     const unsigned grid = (unsigned)ntiles;
     if (W <= 4)
-        ppo_rows_kernel<H, 1><<<grid, 256, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[1], T[2], T[3], T[4],
-                                                      T[5], loss_parts);
+        ppo_rows_kernel<H, 1><<<grid, 256, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[2], T[3], T[4], T[5],
+                                                      loss_parts);
     else
-        ppo_rows_kernel<H, 8><<<grid, 256, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[1], T[2], T[3], T[4],
-                                                      T[5], loss_parts);
+        ppo_rows_kernel<H, 8><<<grid, 256, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[2], T[3], T[4], T[5],
+                                                      loss_parts);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
 }
@@ -1257,7 +1378,8 @@ int ej_ppo_workspace_size(const ej_mlp_desc* m, int64_t rows, int64_t* bytes)
 }
 
 static int ppo_weight_grads_and_loss(const MlpDims& d, const PpoWorkspace& w, unsigned char* ws, int64_t rows,
-                                     const ej_ppo_hparams& hp, float* d_grads, float* d_loss, hipStream_t st);
+                                     const ej_ppo_hparams& hp, const float* d_params, const uint16_t* d_work,
+                                     float* d_grads, float* d_loss, hipStream_t st);
 
 static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work,
                              const ej_ppo_batch* b, const ej_ppo_hparams* hp, void* d_workspace,
@@ -1305,13 +1427,14 @@ static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const 
     default: rc = launch_rows<512>(d, d_params, d_work, B, h, stats, W, T, lparts, w.ntiles, st); break;
     }
     if (rc != EJ_OK) return rc;
-    return ppo_weight_grads_and_loss(d, w, ws, b->rows, *hp, d_grads, d_loss, st);
+    return ppo_weight_grads_and_loss(d, w, ws, b->rows, *hp, d_params, d_work, d_grads, d_loss, st);
 }
 
 // weight gradients from the m-blocks (dW GEMMs, fixed-order reduction) and
 // the minibatch means of the loss terms from the per-tile partial sums
 static int ppo_weight_grads_and_loss(const MlpDims& d, const PpoWorkspace& w, unsigned char* ws, int64_t rows,
-                                     const ej_ppo_hparams& hp, float* d_grads, float* d_loss, hipStream_t st)
+                                     const ej_ppo_hparams& hp, const float* d_params, const uint16_t* d_work,
+                                     float* d_grads, float* d_loss, hipStream_t st)
 {
     int rc = EJ_OK;
     uint16_t* T[6] = {(uint16_t*)(ws + w.o_obs), (uint16_t*)(ws + w.o_h1), (uint16_t*)(ws + w.o_h2),
@@ -1319,12 +1442,20 @@ static int ppo_weight_grads_and_loss(const MlpDims& d, const PpoWorkspace& w, un
     float* lparts = (float*)(ws + w.o_loss);
     float *p1 = (float*)(ws + w.o_p1), *p2 = (float*)(ws + w.o_p2), *p3 = (float*)(ws + w.o_p3);
     float *c1 = (float*)(ws + w.o_c1), *c2 = (float*)(ws + w.o_c2), *c3 = (float*)(ws + w.o_c3);
-    const int G = (int)w.G;
-    if ((rc = launch_dw(T[0], d.K1p, T[5], d.H, w.nmb, G, p1, c1, st)) != EJ_OK) return rc;
-    if ((rc = launch_dw(T[1], d.H, T[4], d.H, w.nmb, G, p2, c2, st)) != EJ_OK) return rc;
-    if ((rc = launch_dw(T[2], d.H, T[3], d.A1p, w.nmb, G, p3, c3, st)) != EJ_OK) return rc;
+    const int G = (int)w.G, G1 = (int)w.G1;
+    const DwX xs{T[0], d_work + d.oW1f, d_params + d.ob1, d.K1p};
+    if (w.rows_mode) {  // dW1 from the observation rows, dW2 with h1 recomputed from them
+        if ((rc = launch_dw<XM_OBS>(nullptr, d.K1p, T[5], d.H, w.nmb, G1, p1, c1, xs, st)) != EJ_OK) return rc;
+        rc = d.K1p == K1P ? launch_dw<XM_H1, K1P / 32>(nullptr, d.H, T[4], d.H, w.nmb, G, p2, c2, xs, st)
+                          : launch_dw<XM_H1, K1P_WIDE / 32>(nullptr, d.H, T[4], d.H, w.nmb, G, p2, c2, xs, st);
+        if (rc != EJ_OK) return rc;
+    } else {
+        if ((rc = launch_dw<XM_BLOCKS>(T[0], d.K1p, T[5], d.H, w.nmb, G1, p1, c1, xs, st)) != EJ_OK) return rc;
+        if ((rc = launch_dw<XM_BLOCKS>(T[1], d.H, T[4], d.H, w.nmb, G, p2, c2, xs, st)) != EJ_OK) return rc;
+    }
+    if ((rc = launch_dw<XM_BLOCKS>(T[2], d.H, T[3], d.A1p, w.nmb, G, p3, c3, xs, st)) != EJ_OK) return rc;
     auto red_blocks = [](int64_t n) { return (unsigned)((n + 31) / 32); };
-    dw_reduce_kernel<<<red_blocks((int64_t)d.K1p * d.H + d.H), 256, 0, st>>>(p1, c1, d.K1p, d.H, G, d.D, d.H, d_grads,
+    dw_reduce_kernel<<<red_blocks((int64_t)d.K1p * d.H + d.H), 256, 0, st>>>(p1, c1, d.K1p, d.H, G1, d.D, d.H, d_grads,
                                                                             d.oW1, d.H, d.ob1);
     EJ_LAUNCH_CHECK();
     dw_reduce_kernel<<<red_blocks((int64_t)d.H * d.H + d.H), 256, 0, st>>>(p2, c2, d.H, d.H, G, d.H, d.H, d_grads,
@@ -1389,7 +1520,7 @@ int ej_gov_ppo_workspace_size(const ej_mlp_desc* m, int32_t K, int64_t rows, int
     if (rc != EJ_OK) return rc;
     if (!bytes || rows <= 0) return EJ_EINVAL;
     PpoWorkspace w;
-    ppo_workspace(d, rows, &w);
+    ppo_workspace(d, rows, &w, false);  // the government's rows kernel writes every operand as m-blocks
     *bytes = (int64_t)w.bytes;
     return EJ_OK;
 }
@@ -1411,7 +1542,7 @@ int ej_gov_ppo_backward(const ej_mlp_desc* m, int32_t K, const float* d_params, 
         (b->row_stride > 0 && b->row_offset >= b->row_stride))
         return EJ_EINVAL;
     PpoWorkspace w;
-    ppo_workspace(d, b->rows, &w);
+    ppo_workspace(d, b->rows, &w, false);
     if (workspace_bytes < (int64_t)w.bytes) return EJ_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     unsigned char* ws = (unsigned char*)d_workspace;
@@ -1443,7 +1574,7 @@ int ej_gov_ppo_backward(const ej_mlp_desc* m, int32_t K, const float* d_params, 
     }
 #undef EJ_GOV_ROWS
     EJ_LAUNCH_CHECK();
-    return ppo_weight_grads_and_loss(d, w, ws, b->rows, *hp, d_grads, d_loss, st);
+    return ppo_weight_grads_and_loss(d, w, ws, b->rows, *hp, d_params, d_work, d_grads, d_loss, st);
 }
 
 int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const ej_ppo_batch* b,
