@@ -354,6 +354,13 @@ typedef struct ej_ppo_batch {
      * (row_stride <= 0 reads as 1): one agent's own samples of a rollout stored
      * for every agent (per-agent weight sets: row_stride = N, row_offset = agent) */
     int64_t row_stride, row_offset;
+    /* nullable: the batch's samples packed by ej_ppo_pack (record s = sample
+     * s).  When given, ej_ppo_backward reads each minibatch row's observation,
+     * mask words and five scalars from its record, one cache-line-aligned
+     * block, instead of from the seven arrays (which it still needs for the
+     * advantage statistics); the results are identical.  Population backward
+     * only: the government's ignores it. */
+    const void* records;
 } ej_ppo_batch;
 
 /* clip epsilon (0.2), value clip (10), value coefficient c_v (0.25),
@@ -364,6 +371,20 @@ typedef struct ej_ppo_hparams {
 
 /* Bytes of device scratch ej_ppo_backward needs for a minibatch of `rows`. */
 int ej_ppo_workspace_size(const ej_mlp_desc* m, int64_t rows, int64_t* bytes);
+
+/* Per-sample records of an update's samples (Table 2: every update runs
+ * several epochs of minibatches over one rollout, each row a scattered
+ * sample).  ej_ppo_record_bytes gives the record size for the network m (a
+ * multiple of 128 bytes: the observation row, padded to 16 bytes, the mask
+ * words, then action, old log-probability, old value, advantage and return,
+ * 4 bytes each).  ej_ppo_pack writes record s for every sample s in
+ * [0, b->M_total) of the batch (storage index s * row_stride + row_offset of
+ * each array; perm_*, row_begin, rows and records are ignored) to d_records
+ * [M_total * record_bytes] (16-byte aligned, caller-owned).  Pack once after
+ * the advantages are computed and pass the records in ej_ppo_batch for every
+ * minibatch of the update. */
+int ej_ppo_record_bytes(const ej_mlp_desc* m, int64_t* bytes);
+int ej_ppo_pack(const ej_mlp_desc* m, const ej_ppo_batch* b, void* d_records, void* stream);
 
 /* Loss and gradient of one PPO minibatch with respect to every parameter:
  *   L = mean(-min(rho A, clip(rho, 1 - eps, 1 + eps) A))

@@ -58,7 +58,8 @@ class EjMlpLayout(C.Structure):
 
 class EjPpoBatch(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("obs", "mask", "act", "logp_old", "val_old", "adv", "ret")] + [
-        (n, C.c_int64) for n in ("M_total", "perm_a", "perm_c", "row_begin", "rows", "row_stride", "row_offset")]
+        (n, C.c_int64) for n in ("M_total", "perm_a", "perm_c", "row_begin", "rows", "row_stride", "row_offset")] + [
+        ("records", C.c_void_p)]
 
 
 class EjPpoHparams(C.Structure):
@@ -136,6 +137,8 @@ def _declare_learner(L):
         "ej_mlp_sync_weights_grouped": [C.POINTER(EjMlpDesc), i32, vp, vp, vp],
         "ej_gae": [vp, vp, vp, vp, i32, i64, f32, f32, vp, vp, vp],
         "ej_ppo_workspace_size": [C.POINTER(EjMlpDesc), i64, C.POINTER(i64)],
+        "ej_ppo_record_bytes": [C.POINTER(EjMlpDesc), C.POINTER(i64)],
+        "ej_ppo_pack": [C.POINTER(EjMlpDesc), C.POINTER(EjPpoBatch), vp, vp],
         "ej_ppo_backward": [C.POINTER(EjMlpDesc), vp, vp, C.POINTER(EjPpoBatch), C.POINTER(EjPpoHparams), vp, i64,
                             vp, vp, vp],
         "ej_ppo_backward_static": [C.POINTER(EjMlpDesc), vp, vp, C.POINTER(EjPpoBatch), C.POINTER(EjPpoHparams),
@@ -402,15 +405,32 @@ def ppo_workspace_bytes(mlp: "Mlp", rows: int) -> int:
     return int(out.value)
 
 
+def ppo_record_bytes(mlp: "Mlp") -> int:
+    out = C.c_int64()
+    check(lib().ej_ppo_record_bytes(C.byref(mlp.desc), C.byref(out)), "ej_ppo_record_bytes")
+    return int(out.value)
+
+
+def ppo_pack(mlp: "Mlp", storage: dict, M_total: int, records, stream=None, row_stride: int = 1,
+             row_offset: int = 0):
+    """ej_ppo_pack: record s of `records` (uint8, M_total * ppo_record_bytes)
+    <- sample s of the storage arrays."""
+    if records.numel() < M_total * ppo_record_bytes(mlp):
+        raise EconError("records buffer too small")
+    b = EjPpoBatch(*(ptr(storage[k]) for k in ("obs", "mask", "act", "logp_old", "val_old", "adv", "ret")),
+                   M_total, 1, 0, 0, 0, row_stride, row_offset, None)
+    check(lib().ej_ppo_pack(C.byref(mlp.desc), C.byref(b), ptr(records), stream_ptr(stream)), "ej_ppo_pack")
+
+
 def ppo_backward(mlp: "Mlp", storage: dict, M_total: int, perm_a: int, perm_c: int, row_begin: int, rows: int,
                  hp: dict, workspace, grads, loss, stream=None, row_stride: int = 1, row_offset: int = 0,
-                 params=None, work=None):
+                 params=None, work=None, records=None):
     """storage: torch tensors obs, mask, act, logp_old, val_old, adv, ret indexed by sample;
-    loss: at least PPO_LOSS_TERMS floats."""
+    loss: at least PPO_LOSS_TERMS floats; records: optional ppo_pack output of the same storage."""
     if loss.numel() < PPO_LOSS_TERMS:
         raise EconError(f"ej_ppo_backward writes {PPO_LOSS_TERMS} loss terms; got {loss.numel()}")
     b = EjPpoBatch(*(ptr(storage[k]) for k in ("obs", "mask", "act", "logp_old", "val_old", "adv", "ret")),
-                   M_total, perm_a, perm_c, row_begin, rows, row_stride, row_offset)
+                   M_total, perm_a, perm_c, row_begin, rows, row_stride, row_offset, ptr(records))
     h = EjPpoHparams(hp["clip"], hp["vclip"], hp["vf_coef"], hp["ent_coef"])
     p_ptr = ptr(mlp.params) if params is None else params
     w_ptr = ptr(mlp.work) if work is None else work

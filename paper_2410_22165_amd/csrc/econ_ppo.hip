@@ -40,7 +40,20 @@ struct PpoBatchDev {
     int64_t Mtot, a, c, begin, rows;
     uint64_t mu;  // floor((2^64 - 1) / Mtot): Barrett reciprocal of the permutation modulus
     int64_t rstride, roff;  // sample s sits at storage index s * rstride + roff
+    const unsigned char* rec;  // nullable: packed records (record s = sample s)
+    int64_t rb;                // record bytes
+    int rmask, rsc;            // byte offsets of the mask words and of the five scalars in a record
 };
+
+// Record of one sample (ej_ppo_pack): the observation row (Ds bf16, padded to
+// 16 bytes), the W mask words, then act, logp_old, val_old, adv, ret; the
+// whole rounded up to 128 bytes
+__host__ __device__ inline void record_layout(int Ds, int W, int* rmask, int* rsc, int64_t* rb)
+{
+    *rmask = (2 * Ds + 15) / 16 * 16;
+    *rsc = *rmask + 4 * W;
+    *rb = (int64_t)(*rsc + 20 + 127) / 128 * 128;
+}
 
 struct PpoHp {
     float clip, vclip, vf_coef, ent_coef;
@@ -49,15 +62,18 @@ struct PpoHp {
 // sample behind minibatch row j: (a (begin + j) + c) mod Mtot.  With a, c,
 // begin + j < Mtot <= 2^31 - 1 the argument is below 2^63, and the Barrett
 // quotient umulhi(x, mu) undershoots floor(x / Mtot) by at most 2.
-__device__ inline int64_t sample_of(const PpoBatchDev& B, int64_t j)
+__device__ inline int64_t perm_of(const PpoBatchDev& B, int64_t j)
 {
     const uint64_t M = (uint64_t)B.Mtot;
     const uint64_t x = (uint64_t)B.a * (uint64_t)(B.begin + j) + (uint64_t)B.c;
     uint64_t r = x - __umul64hi(x, B.mu) * M;
     r = r >= M ? r - M : r;
     r = r >= M ? r - M : r;
-    return (int64_t)r * B.rstride + B.roff;
+    return (int64_t)r;
 }
+
+// its storage index in the arrays
+__device__ inline int64_t sample_of(const PpoBatchDev& B, int64_t j) { return perm_of(B, j) * B.rstride + B.roff; }
 
 // ---------------------------------------------------------------------------
 // GAE: one thread per row, reverse over time; coalesced over rows
@@ -302,8 +318,8 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         for (int i = 0; i < NPC; ++i) {
             const int p = threadIdx.x + 256 * i, r = p >> 3, cc = h * 8 + (p & 7);
             const int64_t j = row0 + r;
-            pv[i] = (j < B.rows && cc * 8 < d.Ds) ? *(const uint4*)(B.obs + sample_of(B, j) * d.Ds + cc * 8)
-                                                   : uint4{0u, 0u, 0u, 0u};
+            const uint16_t* src = B.rec ? (const uint16_t*)(B.rec + perm_of(B, j) * B.rb) : B.obs + sample_of(B, j) * d.Ds;
+            pv[i] = (j < B.rows && cc * 8 < d.Ds) ? *(const uint4*)(src + cc * 8) : uint4{0u, 0u, 0u, 0u};
         }
     };
     auto store_half = [&](int64_t tile, int h) {  // -> the LDS tile and the minibatch's observation rows
@@ -319,19 +335,27 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         mean = stats[0];
         istd = stats[1];
         if ((int)threadIdx.x < TILE && row0 + (int)threadIdx.x < B.rows) {
-            const int64_t sidx = sample_of(B, row0 + threadIdx.x);
-            gs[0] = __int_as_float(B.act[sidx]);
-            gs[1] = B.logp_old[sidx];
-            gs[2] = B.val_old[sidx];
-            gs[3] = B.adv[sidx];
-            gs[4] = B.ret[sidx];
+            if (B.rec) {  // one record: five consecutive words
+                const float* sc = (const float*)(B.rec + perm_of(B, row0 + threadIdx.x) * B.rb + B.rsc);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) gs[k] = sc[k];
+            } else {
+                const int64_t sidx = sample_of(B, row0 + threadIdx.x);
+                gs[0] = __int_as_float(B.act[sidx]);
+                gs[1] = B.logp_old[sidx];
+                gs[2] = B.val_old[sidx];
+                gs[3] = B.adv[sidx];
+                gs[4] = B.ret[sidx];
+            }
         }
 #pragma unroll
         for (int i = 0; i < MWP; ++i) {
             const int p = threadIdx.x + 256 * i;
             const int r = p / W;
             const int64_t j = row0 + r;
-            gm[i] = (r < TILE && j < B.rows) ? B.mask[sample_of(B, j) * W + (p - r * W)] : 0u;
+            const uint32_t* src = B.rec ? (const uint32_t*)(B.rec + perm_of(B, j) * B.rb + B.rmask)
+                                        : B.mask + sample_of(B, j) * W;
+            gm[i] = (r < TILE && j < B.rows) ? src[p - r * W] : 0u;
         }
         obs_half(tile, 0);
     };
@@ -955,6 +979,32 @@ static int launch_rows(const MlpDims& d, const float* params, const uint16_t* wo
 }
 
 
+// record s <- sample s of the batch (storage index s * rstride + roff): the
+// threads of a block row (threadIdx.y) write one record, one 4-byte word each
+// (coalesced reads of the arrays, coalesced writes of the records)
+__global__ void ppo_pack_kernel(const PpoBatchDev B, int Ds, int W, uint32_t* __restrict__ rec)
+{
+    const int wpr = (int)(B.rb / 4), w = threadIdx.x, byte = 4 * w;
+    for (int64_t sm = (int64_t)blockIdx.x * blockDim.y + threadIdx.y; sm < B.Mtot; sm += (int64_t)gridDim.x * blockDim.y) {
+        const int64_t g = sm * B.rstride + B.roff;
+        uint32_t v = 0u;
+        if (byte < 2 * Ds) {
+            v = ((const uint32_t*)(B.obs + g * Ds))[w];
+        } else if (byte >= B.rmask && byte < B.rsc) {
+            v = B.mask[g * W + (byte - B.rmask) / 4];
+        } else if (byte >= B.rsc && byte < B.rsc + 20) {
+            switch ((byte - B.rsc) / 4) {
+            case 0: v = (uint32_t)B.act[g]; break;
+            case 1: v = __float_as_uint(B.logp_old[g]); break;
+            case 2: v = __float_as_uint(B.val_old[g]); break;
+            case 3: v = __float_as_uint(B.adv[g]); break;
+            default: v = __float_as_uint(B.ret[g]); break;
+            }
+        }
+        rec[sm * wpr + w] = v;
+    }
+}
+
 // ===========================================================================
 // The government's policy (Sec. 3 "Government Agent", "Setting tax rates"):
 // the same two-hidden-layer network on the economy's government
@@ -1377,6 +1427,42 @@ int ej_ppo_workspace_size(const ej_mlp_desc* m, int64_t rows, int64_t* bytes)
     return EJ_OK;
 }
 
+int ej_ppo_record_bytes(const ej_mlp_desc* m, int64_t* bytes)
+{
+    if (!m || !bytes) return EJ_EINVAL;
+    MlpDims d;
+    int rc = mlp_dims(m->D, m->D_stride, m->H, m->A, &d);
+    if (rc != EJ_OK) return rc;
+    int rmask = 0, rsc = 0;
+    record_layout(d.Ds, (d.A + 31) / 32, &rmask, &rsc, bytes);
+    return EJ_OK;
+}
+
+int ej_ppo_pack(const ej_mlp_desc* m, const ej_ppo_batch* b, void* d_records, void* stream)
+{
+    if (!m || !b || !d_records) return EJ_EINVAL;
+    if (!b->obs || !b->mask || !b->act || !b->logp_old || !b->val_old || !b->adv || !b->ret) return EJ_EINVAL;
+    if (!aligned16(b->obs) || !aligned16(d_records)) return EJ_EINVAL;
+    if (b->M_total <= 0 || b->M_total > INT32_MAX || b->row_offset < 0 ||
+        (b->row_stride > 0 && b->row_offset >= b->row_stride))
+        return EJ_EINVAL;
+    MlpDims d;
+    int rc = mlp_dims(m->D, m->D_stride, m->H, m->A, &d);
+    if (rc != EJ_OK) return rc;
+    const int W = (d.A + 31) / 32;
+    PpoBatchDev B{b->obs, b->mask, b->act, b->logp_old, b->val_old, b->adv, b->ret, b->M_total, 1, 0, 0, 0, 0,
+                  b->row_stride > 0 ? b->row_stride : 1, b->row_offset, nullptr, 0, 0, 0};
+    record_layout(d.Ds, W, &B.rmask, &B.rsc, &B.rb);
+    const int wpr = (int)(B.rb / 4);  // 32 .. 128 words (Ds <= 128, W <= 32)
+    const int spb = wpr >= 256 ? 1 : 256 / wpr;
+    int64_t blocks = (b->M_total + spb - 1) / spb;
+    if (blocks > 65536) blocks = 65536;
+    ppo_pack_kernel<<<(unsigned)blocks, dim3((unsigned)wpr, (unsigned)spb), 0, (hipStream_t)stream>>>(B, d.Ds, W,
+                                                                                                     (uint32_t*)d_records);
+    EJ_LAUNCH_CHECK();
+    return EJ_OK;
+}
+
 static int ppo_weight_grads_and_loss(const MlpDims& d, const PpoWorkspace& w, unsigned char* ws, int64_t rows,
                                      const ej_ppo_hparams& hp, const float* d_params, const uint16_t* d_work,
                                      float* d_grads, float* d_loss, hipStream_t st);
@@ -1388,7 +1474,7 @@ static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const 
     if (!m || !d_params || !d_work || !b || !hp || !d_workspace || !d_grads || !d_loss) return EJ_EINVAL;
     if (!b->obs || !b->mask || !b->act || !b->logp_old || !b->val_old || !b->adv || !b->ret) return EJ_EINVAL;
     if (!aligned16(d_params) || !aligned16(d_work) || !aligned16(b->obs) || !aligned16(d_workspace) ||
-        !aligned16(d_grads))
+        !aligned16(d_grads) || !aligned16(b->records))
         return EJ_EINVAL;
     if (b->M_total <= 0 || b->M_total > INT32_MAX || b->rows <= 0 || b->perm_a <= 0 || b->perm_c < 0 ||
         b->row_begin < 0 || b->row_begin + b->rows > INT32_MAX || b->row_offset < 0 ||
@@ -1406,7 +1492,8 @@ static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const 
     if (a == 0) return EJ_EINVAL;
     PpoBatchDev B{b->obs, b->mask, b->act, b->logp_old, b->val_old, b->adv, b->ret, b->M_total, a,
                   b->perm_c % b->M_total, b->row_begin, b->rows, UINT64_MAX / (uint64_t)b->M_total,
-                  b->row_stride > 0 ? b->row_stride : 1, b->row_offset};
+                  b->row_stride > 0 ? b->row_stride : 1, b->row_offset, (const unsigned char*)b->records, 0, 0, 0};
+    if (B.rec) record_layout(m->D_stride, (m->A + 31) / 32, &B.rmask, &B.rsc, &B.rb);
     PpoHp h{hp->clip, hp->vclip, hp->vf_coef, hp->ent_coef};
     const int W = (m->A + 31) / 32;
     double* advp = (double*)(ws + w.o_adv);
@@ -1550,7 +1637,7 @@ int ej_gov_ppo_backward(const ej_mlp_desc* m, int32_t K, const float* d_params, 
     if (a == 0) return EJ_EINVAL;
     PpoBatchDev B{b->obs, nullptr, b->act, b->logp_old, b->val_old, b->adv, b->ret, b->M_total, a,
                   b->perm_c % b->M_total, b->row_begin, b->rows, UINT64_MAX / (uint64_t)b->M_total,
-                  b->row_stride > 0 ? b->row_stride : 1, b->row_offset};
+                  b->row_stride > 0 ? b->row_stride : 1, b->row_offset, nullptr, 0, 0, 0};
     PpoHp h{hp->clip, hp->vclip, hp->vf_coef, hp->ent_coef};
     double* advp = (double*)(ws + w.o_adv);
     float* stats = (float*)(ws + w.o_stats);

@@ -101,6 +101,10 @@ class PPOTrainer:
         self.mb_rows = self.M_total // minibatches
         self.workspace = torch.zeros(binding.ppo_workspace_bytes(self.mlp, self.mb_rows), dtype=torch.uint8,
                                      device="cuda")
+        # every sample of a rollout packed into one record (ej_ppo_pack), so that a
+        # minibatch row's gather touches one cache-line-aligned block
+        self.records = torch.empty(self.M_total * binding.ppo_record_bytes(self.mlp), dtype=torch.uint8,
+                                   device="cuda")
         # sampling counter on the device: a step's uniforms use (base + t); the
         # base moves by T + 1 after each rollout, so a replayed graph draws fresh ones
         self.ctr_base = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -145,11 +149,12 @@ class PPOTrainer:
         lr, ent = self.schedules()
         hp = dict(self.hp, ent_coef=ent)
         flat = self.store.flat()
+        binding.ppo_pack(self.mlp, flat, self.M_total, self.records)
         for epoch in range(self.epochs):
             a, c = W.affine_permutation(self.M_total, self.updates * self.epochs + epoch, seed=self.seed)
             for mb in range(self.minibatches):
                 binding.ppo_backward(self.mlp, flat, self.M_total, a, c, mb * self.mb_rows, self.mb_rows, hp,
-                                     self.workspace, self.grads, self.loss_terms)
+                                     self.workspace, self.grads, self.loss_terms, records=self.records)
                 self.adam_step += 1
                 binding.adam(self.mlp.params, self.grads, self.adam_m, self.adam_v, self.adam_step, max(lr, 1e-12))
                 self.mlp.sync()

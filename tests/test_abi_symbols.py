@@ -74,3 +74,16 @@ def test_mlp_layout_limits_on_the_host():
             assert out.W1 == 0 and out.b1 == D * H and out.n_work == k1 * H + H * H + H * 128 + 128 * H + H * H
     # 128-row tiles take rows of at most 64 features
     assert L.ej_mlp_layout(C.byref(binding.EjMlpDesc(91, 96, 256, 86, 128)), C.byref(out)) != 0
+
+
+def test_ppo_record_bytes_on_the_host():
+    """Record size of ej_ppo_pack (host only): observation row padded to 16
+    bytes, mask words, five 4-byte scalars, rounded up to 128 bytes."""
+    import ctypes as C
+    from paper_2410_22165_amd import binding
+    L = binding.lib()
+    out = C.c_int64()
+    for (D, Ds, H, A), want in (((35, 40, 256, 125), 128), ((49, 56, 512, 507), 256), ((91, 96, 256, 86), 256),
+                                ((64, 64, 128, 1000), 384), ((11, 16, 64, 9), 128)):
+        assert L.ej_ppo_record_bytes(C.byref(binding.EjMlpDesc(D, Ds, H, A, 0)), C.byref(out)) == 0
+        assert out.value == want, (D, Ds, A, out.value)

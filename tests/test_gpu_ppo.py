@@ -351,3 +351,50 @@ def test_ppo_backward_rejects_misaligned_arrays():
     assert call(obs_off=8) == -1
     torch.cuda.synchronize()
     assert (grads.cpu() == 7.0).all()
+
+
+@pytest.mark.parametrize("case", [(35, 40, 256, 125, 30000, 1, 0), (35, 40, 256, 125, 24000, 3, 2),
+                                  (91, 96, 256, 86, 5000, 1, 0), (49, 56, 512, 507, 3000, 1, 0)])
+def test_ppo_records_equal_arrays(case):
+    """ej_ppo_pack writes each sample's observation row, mask words and five
+    scalars into one record (checked byte by byte against the arrays), and
+    the backward that gathers the records gives the gradient and loss of the
+    one that gathers the arrays, bit for bit: ragged minibatches, several
+    m-blocks per weight-gradient split, a strided (per-agent) batch, the
+    wide-row and 507-action networks."""
+    import torch
+    from paper_2410_22165_amd import binding
+    D, Ds, H, A, M_gen, stride, offset = case
+    print(f"[gpu] records D={D} H={H} A={A} M={M_gen} stride={stride}", flush=True)
+    w, st = make_storage(D, Ds, H, A, M_gen, seed=21)
+    mlp = binding.Mlp(D, Ds, H, A, w)
+    dev = {k: _t(v.view(np.int16) if k == "obs" else (v.view(np.int32) if k == "mask" else v)) for k, v in st.items()}
+    M = (M_gen - 1 - offset) // stride + 1
+    rb = binding.ppo_record_bytes(mlp)
+    Wm = (A + 31) // 32
+    rmask = (2 * Ds + 15) // 16 * 16
+    rsc = rmask + 4 * Wm
+    assert rb % 128 == 0 and rb >= rsc + 20
+    rec = torch.full((M * rb,), 0xAB, dtype=torch.uint8, device="cuda")
+    binding.ppo_pack(mlp, dev, M, rec, row_stride=stride, row_offset=offset)
+    torch.cuda.synchronize()
+    R = rec.view(M, rb).cpu().numpy()
+    idx = np.arange(M) * stride + offset
+    assert np.array_equal(R[:, :2 * Ds], st["obs"][idx].view(np.uint8).reshape(M, -1))
+    assert not R[:, 2 * Ds:rmask].any() and not R[:, rsc + 20:].any()
+    assert np.array_equal(R[:, rmask:rsc], st["mask"][idx].view(np.uint8).reshape(M, -1))
+    for k, name in enumerate(("act", "logp_old", "val_old", "adv", "ret")):
+        assert np.array_equal(R[:, rsc + 4 * k:rsc + 4 * k + 4], st[name][idx].view(np.uint8).reshape(M, 4)), name
+    rows_all = [(0, M // 3), (M // 3, M - M // 3 - 5)]
+    for epoch, (begin, rows) in enumerate(rows_all):
+        a, c = W.affine_permutation(M, epoch, seed=5)
+        out = []
+        for r in (None, rec):
+            ws = torch.zeros(binding.ppo_workspace_bytes(mlp, rows), dtype=torch.uint8, device="cuda")
+            grads = torch.zeros(mlp.layout["n_params"], device="cuda")
+            loss = torch.zeros(binding.PPO_LOSS_TERMS, device="cuda")
+            binding.ppo_backward(mlp, dev, M, a, c, begin, rows, HP, ws, grads, loss, row_stride=stride,
+                                 row_offset=offset, records=r)
+            torch.cuda.synchronize()
+            out.append((grads.cpu(), loss.cpu()))
+        assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1]), (case, begin, rows)
