@@ -224,6 +224,36 @@ __device__ inline void ppo_masked_grad_cs(const f32x4 (&dh)[TR][CTW], const uint
     }
 }
 
+// masked input gradient of a column-split layer in the plain accumulator
+// layout (dense_cs without TRANS: lane l holds column col0 + 16 ct + l % 16,
+// rows 16 rt + 4 (l / 16) .. + 3) -> its bf16 m-blocks directly: a lane's four
+// rows are 8 contiguous bytes of T[(mb0 + rt / 2) ncol + column][32].  The
+// ReLU pattern comes in the transposed layout (bits[rt] bit 4 ct + i: row
+// 16 rt + l % 16, column col0 + 16 ct + 4 (l / 16) + i); the bit of (row
+// 16 rt + 4 g + i, column col0 + 16 ct + c) sits in lane 4 g + i + 16 (c / 4),
+// bit 4 ct + c % 4.
+template <int TR, int CTW>
+__device__ inline void ppo_grad_to_mblocks(const f32x4 (&dh)[TR][CTW], const uint32_t (&bits)[TR], uint16_t* T,
+                                           int64_t mb0, int ncol, int col0)
+{
+    const int l = lane_id(), c = l & 15, g = l >> 4;
+#pragma unroll
+    for (int rt = 0; rt < TR; ++rt) {
+        uint32_t mk[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mk[i] = (uint32_t)__shfl((int)bits[rt], 4 * g + i + 16 * (c >> 2), 64);
+#pragma unroll
+        for (int ct = 0; ct < CTW; ++ct) {
+            const int sh = 4 * ct + (c & 3);
+            uint32_t h[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h[i] = f32_to_bf16(((mk[i] >> sh) & 1u) ? dh[rt][ct][i] : 0.f);
+            *(uint2*)(T + ((mb0 + (rt >> 1)) * ncol + col0 + 16 * ct + c) * 32 + 16 * (rt & 1) + 4 * g) =
+                uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+        }
+    }
+}
+
 // m-block copy of an LDS tile: rows [0, rows) x columns [0, ncol) of a bf16
 // tile (row stride hs, a multiple of 4) -> T[(mb0 + row / 32) ncol_total +
 // col_off + col][32].  A work item is (32-row block, group of four columns,
@@ -560,12 +590,11 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     ppo_masked_grad_cs<TR, CTW>(dh, m2, hbuf, HS, col0);
     lds_barrier();
     tile_to_mblocks(hbuf, HS, TILE, H, Tdh2, mb0, H, 0);
-    // ---- dh1 = (dh2 W2^T) * [h1 > 0] -> m-blocks
-    dense_cs<TR, CTW, H / 32, true, 3, true, true>(dh, hbuf, HS, work + d.oW2b, (int64_t)H * 32, col0);
-    lds_barrier();  // everyone is done reading dh2
-    ppo_masked_grad_cs<TR, CTW>(dh, m1, hbuf, HS, col0);
-    lds_barrier();
-    tile_to_mblocks(hbuf, HS, TILE, H, Tdh1, mb0, H, 0);
+    // ---- dh1 = (dh2 W2^T) * [h1 > 0] -> m-blocks, straight from the
+    // accumulators (plain layout: a lane's four rows of one column are 8
+    // contiguous bytes of the m-block)
+    dense_cs<TR, CTW, H / 32, true, 3, true, false>(dh, hbuf, HS, work + d.oW2b, (int64_t)H * 32, col0);
+    ppo_grad_to_mblocks<TR, CTW>(dh, m1, Tdh1, mb0, H, col0);
     if (threadIdx.x < 4) {
         float sum = 0.f;
         for (int w = 0; w < 4; ++w) sum += lred[w * 4 + threadIdx.x];
