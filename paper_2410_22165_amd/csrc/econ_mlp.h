@@ -192,24 +192,24 @@ constexpr int ZQ = 36, ZS = 4 * ZQ;
 __device__ inline int zsw(int row) { return (row >> 2) & 3; }
 __device__ inline int zcol(int row, int cc) { return (cc >> 5) * ZQ + ((((cc >> 2) & 7) ^ zsw(row)) << 2) + (cc & 3); }
 
-// b1 [H], b2 [H], b3 [A1p] (zero beyond A1) -> sbias, by a 256-thread
-// workgroup; all loads are issued before the first store (A1p <= 1024)
-template <int H>
+// b1 [H], b2 [H], b3 [A1p] (zero beyond A1) -> sbias, by a workgroup of NT
+// threads; all loads are issued before the first store (A1p <= 1024)
+template <int H, int NT = 256>
 __device__ inline void load_biases(const MlpDims& d, const float* __restrict__ params, float* sbias)
 {
-    constexpr int NI = (2 * H + 1024 + 255) / 256;
+    constexpr int NI = (2 * H + 1024 + NT - 1) / NT;
     const int n = 2 * H + d.A1p;
     float v[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        const int p = threadIdx.x + 256 * i;
+        const int p = threadIdx.x + NT * i;
         v[i] = p >= n ? 0.f
                       : p < H ? params[d.ob1 + p]
                               : p < 2 * H ? params[d.ob2 + p - H] : (p - 2 * H < d.A1 ? params[d.ob3 + p - 2 * H] : 0.f);
     }
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        const int p = threadIdx.x + 256 * i;
+        const int p = threadIdx.x + NT * i;
         if (p < n) sbias[p] = v[i];
     }
 }

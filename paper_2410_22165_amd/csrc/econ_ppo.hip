@@ -290,7 +290,11 @@ __device__ inline void tile_to_mblocks(const uint16_t* tile, int hs, int rows, i
 // split by columns (wave w: all rows x columns [w H / 4, (w + 1) H / 4)).
 template <int H>
 struct PpoTile {
-    static constexpr int TILE = 64, TR = 4, HS = H + 8, CTW = H / 64;
+    // H = 512: eight waves, so that a wave's share of every product (four
+    // 16-column tiles) fits its registers; below, four waves
+    static constexpr int NW = H >= 512 ? 8 : 4, NTH = 64 * NW;
+    static constexpr int TILE = 64, TR = 4, HS = H + 8, CTW = H / (16 * NW);
+    static constexpr int LCT = 128 / (16 * NW);  // 16-column tiles of a logit chunk per wave
     static constexpr int YS = 136;  // bf16 row stride of the dY chunk (aliases the logit chunk)
 };
 
@@ -315,29 +319,33 @@ size_t ppo_rows_lds_bytes(int W, int A1p)
 // of them is stored to LDS, one round trip for all.  MWP mask words per
 // thread cover rows of W <= 4 MWP words.
 template <int H, int MWP>
-__global__ void __launch_bounds__(256, H <= 256 ? 2 : 1)  // H <= 256: 73 KB of LDS, two workgroups per CU
+__global__ void __launch_bounds__(PpoTile<H>::NTH, H <= 256 ? 2 : 1)  // H <= 256: 73 KB of LDS, two workgroups per CU
 ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
                 const PpoBatchDev B, const PpoHp hp, const float* __restrict__ stats, int W,
                 uint16_t* __restrict__ Orows, uint16_t* __restrict__ Th2, uint16_t* __restrict__ TdY,
                 uint16_t* __restrict__ Tdh2, uint16_t* __restrict__ Tdh1, float* __restrict__ loss_parts)
 {
     using P = PpoTile<H>;
-    constexpr int TILE = P::TILE, TR = P::TR, HS = P::HS, CTW = P::CTW, YS = P::YS;
+    constexpr int TILE = P::TILE, TR = P::TR, HS = P::HS, CTW = P::CTW, YS = P::YS, NW = P::NW, NTH = P::NTH;
+    constexpr int LCT = P::LCT;
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* hbuf = (uint16_t*)smem;                 // [TILE][HS] obs -> h1 -> h2 -> dh2
     float* zbuf = (float*)(hbuf + TILE * HS);         // [TILE][ZS] logit chunk
     uint16_t* ybuf = (uint16_t*)zbuf;                 // [TILE][YS] dY chunk once the logits are consumed
     float* rinfo = zbuf + TILE * ZS;                  // [6][TILE]: act, logp_old, val_old, adv_hat, ret, valid
     uint32_t* smask = (uint32_t*)(rinfo + 6 * TILE);  // [TILE][W]
-    float* lred = (float*)(smask + TILE * W);         // [4 waves][4]
+    float* lred = (float*)(smask + TILE * W);         // [NW waves][4] (64 floats)
     float* sbias = lred + 64;                         // b1 [H], b2 [H], b3 [A1p] (zero padded)
 
     const int wave = threadIdx.x >> 6, l = lane_id(), q = l & 3;
     const float inv_n = 1.0f / (float)B.rows;
-    const int col0 = wave * (H / 4);
+    const int col0 = wave * (H / NW);
+    // the masked softmax works on rows: four waves own 16 rows each (eight
+    // waves: the last four only join the products)
+    const bool rowner = NW == 4 || wave < 4;
 
     // gather registers (the tile's inputs)
-    constexpr int NPC = TILE * (K1P / 8) / 256;  // 16-byte observation pieces per thread and 64 columns
+    constexpr int NPC = TILE * (K1P / 8) / NTH;  // 16-byte observation pieces per thread and 64 columns
     uint4 pv[NPC];
     float gs[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // act (bits), logp_old, val_old, adv, ret of row threadIdx.x
     uint32_t gm[MWP];
@@ -346,7 +354,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         const int64_t row0 = tile * TILE;
 #pragma unroll
         for (int i = 0; i < NPC; ++i) {
-            const int p = threadIdx.x + 256 * i, r = p >> 3, cc = h * 8 + (p & 7);
+            const int p = threadIdx.x + NTH * i, r = p >> 3, cc = h * 8 + (p & 7);
             const int64_t j = row0 + r;
             const uint16_t* src = B.rec ? (const uint16_t*)(B.rec + perm_of(B, j) * B.rb) : B.obs + sample_of(B, j) * d.Ds;
             pv[i] = (j < B.rows && cc * 8 < d.Ds) ? *(const uint4*)(src + cc * 8) : uint4{0u, 0u, 0u, 0u};
@@ -355,7 +363,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     auto store_half = [&](int64_t tile, int h) {  // -> the LDS tile and the minibatch's observation rows
 #pragma unroll
         for (int i = 0; i < NPC; ++i) {
-            const int p = threadIdx.x + 256 * i, cc = h * 8 + (p & 7);
+            const int p = threadIdx.x + NTH * i, cc = h * 8 + (p & 7);
             *(uint4*)(hbuf + (p >> 3) * HS + cc * 8) = pv[i];
             *(uint4*)(Orows + (tile * TILE + (p >> 3)) * d.K1p + cc * 8) = pv[i];
         }
@@ -380,7 +388,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         }
 #pragma unroll
         for (int i = 0; i < MWP; ++i) {
-            const int p = threadIdx.x + 256 * i;
+            const int p = threadIdx.x + NTH * i;
             const int r = p / W;
             const int64_t j = row0 + r;
             const uint32_t* src = B.rec ? (const uint32_t*)(B.rec + perm_of(B, j) * B.rb + B.rmask)
@@ -403,7 +411,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         }
 #pragma unroll
         for (int i = 0; i < MWP; ++i) {
-            const int p = threadIdx.x + 256 * i;
+            const int p = threadIdx.x + NTH * i;
             if (p < TILE * W) smask[p] = gm[i];
         }
         store_half(tile, 0);
@@ -415,7 +423,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
 
     const int64_t tile = blockIdx.x;
     gather(tile);
-    load_biases<H>(d, params, sbias);
+    load_biases<H, NTH>(d, params, sbias);
     commit(tile);
     lds_barrier();
     const int64_t tile_row0 = tile * TILE;
@@ -435,19 +443,19 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     lds_barrier();
     tile_to_mblocks(hbuf, HS, TILE, H, Th2, mb0, H, 0);
 
-    // Logit chunks: wave w computes columns [32 w, 32 w + 32) of the chunk for
-    // every row into LDS (fp32); then a quad of lanes owns a row (q = lane % 4
-    // takes the chunk's columns 32 q .. 32 q + 31).
+    // Logit chunks: wave w computes columns [16 LCT w, 16 LCT (w + 1)) of the
+    // chunk for every row into LDS (fp32); then a quad of lanes of a row-owning
+    // wave owns a row (q = lane % 4 takes the chunk's columns 32 q .. 32 q + 31).
     const float NEG = -__builtin_huge_valf();
-    const int srow = wave * 16 + (l >> 2);
+    const int srow = (wave & 3) * 16 + (l >> 2);
     const int a_taken = __float_as_int(rinfo[srow]);
     auto logit_chunk = [&](int c) {
-        f32x4 acc3[TR][2];
-        dense_cs<TR, 2, H / 32, true, 3, true, true>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32,
-                                                      (int64_t)d.A1p * 32, 32 * wave);
+        f32x4 acc3[TR][LCT];
+        dense_cs<TR, LCT, H / 32, true, 3, true, true>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32,
+                                                        (int64_t)d.A1p * 32, 16 * LCT * wave);
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-            const int cc = 32 * wave + ct * 16 + 4 * (l >> 4);  // 4 adjacent columns of row l % 16
+        for (int ct = 0; ct < LCT; ++ct) {
+            const int cc = 16 * LCT * wave + ct * 16 + 4 * (l >> 4);  // 4 adjacent columns of row l % 16
             const float4 b = *(const float4*)(sbias + 2 * H + c * 128 + cc);
 #pragma unroll
             for (int rt = 0; rt < TR; ++rt)
@@ -471,6 +479,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     for (int c = 0; c < d.NC; ++c) {
         logit_chunk(c);
         lds_barrier();
+        if (rowner) {
         float z[32];
         load_row(z);
         const int colq = c * 128 + 32 * q;
@@ -503,6 +512,7 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         sT = (sm == NEG ? 0.f : fo * (sT + (sm - mn) * sS)) + (any ? fc * (te + (zmax - mn) * se) : 0.f);
         sS = sS * fo + se * fc;
         sm = mn;
+        }  // rowner
         if (c + 1 < d.NC) lds_barrier();  // before the next chunk overwrites the logits
     }
 
@@ -552,12 +562,13 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
             logit_chunk(c);
             lds_barrier();
         }
+        uint32_t gp[16];
+        if (rowner) {
         float z[32];
         load_row(z);
         const int colq = c * 128 + 32 * q;
         const int wi = c * 4 + q;
         const uint32_t mw = wi < W ? smask[srow * W + wi] : 0u;
-        uint32_t gp[16];
 #pragma unroll
         for (int j = 0; j < 32; j += 2) {
             float g2[2];
@@ -572,10 +583,13 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
             }
             gp[j >> 1] = f32_to_bf16(g2[0]) | (f32_to_bf16(g2[1]) << 16);
         }
+        }  // rowner
         lds_barrier();  // every lane has read its logits: the chunk's space takes dY
-        uint4* yrow = (uint4*)(ybuf + srow * YS + 32 * q);  // 16-byte stores: no bank conflicts
+        if (rowner) {
+            uint4* yrow = (uint4*)(ybuf + srow * YS + 32 * q);  // 16-byte stores: no bank conflicts
 #pragma unroll
-        for (int j = 0; j < 4; ++j) yrow[j] = uint4{gp[4 * j], gp[4 * j + 1], gp[4 * j + 2], gp[4 * j + 3]};
+            for (int j = 0; j < 4; ++j) yrow[j] = uint4{gp[4 * j], gp[4 * j + 1], gp[4 * j + 2], gp[4 * j + 3]};
+        }
         lds_barrier();
         tile_to_mblocks(ybuf, YS, TILE, 128, TdY, mb0, d.A1p, c * 128);  // dY for dW3
         if (c == 0)
@@ -997,11 +1011,12 @@ static int launch_rows(const MlpDims& d, const float* params, const uint16_t* wo
 {
     const size_t lds = ppo_rows_lds_bytes<H>(W, d.A1p);
     const unsigned grid = (unsigned)ntiles;
-    if (W <= 4)
-        ppo_rows_kernel<H, 1><<<grid, 256, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[2], T[3], T[4], T[5],
+    constexpr int NTH = PpoTile<H>::NTH;
+    if (PpoTile<H>::TILE * W <= NTH)
+        ppo_rows_kernel<H, 1><<<grid, NTH, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[2], T[3], T[4], T[5],
                                                       loss_parts);
     else
-        ppo_rows_kernel<H, 8><<<grid, 256, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[2], T[3], T[4], T[5],
+        ppo_rows_kernel<H, 8><<<grid, NTH, lds, st>>>(d, params, work, B, hp, stats, W, T[0], T[2], T[3], T[4], T[5],
                                                       loss_parts);
     EJ_LAUNCH_CHECK();
     return EJ_OK;
