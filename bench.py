@@ -110,7 +110,7 @@ def cpu_baseline(cfg, weights, budget_s: float = 12.0):
     import multiprocessing as mp
 
     n1, dt1, steps1 = _oracle_worker((cfg, weights, range(4), budget_s / 2))
-    # the host cores this process may run on, at most the 16 a one-GPU machine grants
+    # the host cores this process may run on (its affinity mask), at most 16
     cores = min(len(os.sched_getaffinity(0)), 16)
     ctx = mp.get_context("spawn")
     with ctx.Pool(cores) as pool:
