@@ -316,8 +316,9 @@ size_t ppo_rows_lds_bytes(int W, int A1p)
 // The rows of a minibatch are scattered samples (the permutation), so their
 // gather is latency-bound: every load of the tile's inputs (observation, mask
 // words, the five per-sample scalars, the biases) is issued before the first
-// of them is stored to LDS, one round trip for all.  MWP mask words per
-// thread cover rows of W <= 4 MWP words.
+// of them is stored to LDS, one round trip for all; with packed records
+// (ej_ppo_pack) a row's inputs are one aligned block.  MWP mask words per
+// thread cover the tile's TILE x W words (TILE W <= NTH MWP).
 template <int H, int MWP>
 __global__ void __launch_bounds__(PpoTile<H>::NTH, H <= 256 ? 2 : 1)  // H <= 256: 73 KB of LDS, two workgroups per CU
 ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_t* __restrict__ work,
