@@ -388,3 +388,27 @@ def test_library_rollout_graph_with_carry_equals_host_loop():
     r.close()
     for e in envs:
         e.close()
+
+
+def test_trainer_on_the_twelve_resource_variant():
+    """The shared-network trainer on the 12-resource multi-agent economy (86
+    actions, 91-feature observations: 256-byte packed records and the
+    128-column first layer): two updates of graph-replayed rollouts, finite
+    losses and advantages, weights that move."""
+    import torch
+    from paper_2410_22165_amd import binding
+    from paper_2410_22165_amd.ppo import PPOTrainer
+    cfg = W.variant_config(R=12, N=10, E=12, X=6, T=30, seed=5)
+    print("[gpu] trainer R=12", flush=True)
+    tr = PPOTrainer(cfg, W.obs_scales(cfg), hidden=128, rollout=16, epochs=2, minibatches=2, gamma=0.99, lam=0.95,
+                    clip=0.2, vf_coef=0.25, vclip=10.0, ent_coef=0.01, lr=1e-3, seed=3, total_updates=4, groups=2)
+    assert tr.A == 86 and tr.D == 91 and binding.ppo_record_bytes(tr.mlp) == 256
+    p0 = tr.mlp.params.clone()
+    for _ in range(2):
+        tr.collect(graph=True)
+        tr.update()
+    torch.cuda.synchronize()
+    assert np.isfinite(tr.loss_terms.cpu().numpy()).all()
+    assert np.isfinite(tr.store.adv.cpu().numpy()).all()
+    assert not torch.equal(p0, tr.mlp.params)
+    tr.close()

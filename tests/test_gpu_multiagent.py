@@ -127,15 +127,18 @@ def test_strided_agent_backward_equals_gathered_and_matches_oracle():
             assert_elementwise(mlp.unflat(gs.cpu().numpy()), g_o, B, where=f"agent {g}")
 
 
-@pytest.mark.parametrize("layout", ["ippo", "mappo"])
-def test_multi_agent_trainers(layout):
-    """The variant economy with 4 resources (30 actions): two updates of each
-    layout; finite losses, every agent's policy moves away from the others'
-    (independent sets), the shared value network moves (MAPPO)."""
+@pytest.mark.parametrize("layout,R", [("ippo", 4), ("mappo", 4), ("ippo", 12), ("mappo", 12)])
+def test_multi_agent_trainers(layout, R):
+    """The variant economy with 4 resources (30 actions) and with 12 (86
+    actions, 91-feature observations: the 128-column first layer): two
+    updates of each layout; finite losses, every agent's policy moves away
+    from the others' (independent sets), the shared value network moves
+    (MAPPO)."""
     import torch
     from paper_2410_22165_amd.ppo import MultiAgentTrainer
-    cfg = W.variant_config(R=4, N=6, E=16, X=6, T=30, seed=1)
-    tr = MultiAgentTrainer(cfg, W.obs_scales(cfg), layout, hidden=64, rollout=12, epochs=2, minibatches=2, gamma=0.99,
+    cfg = W.variant_config(R=R, N=6, E=16, X=6, T=30, seed=1)
+    tr = MultiAgentTrainer(cfg, W.obs_scales(cfg), layout, hidden=64 if R <= 8 else 128, rollout=12, epochs=2,
+                           minibatches=2, gamma=0.99,
                            lam=0.95, clip=0.2, vf_coef=0.25, vclip=10.0, ent_coef=0.01, lr=3e-3, seed=2,
                            total_updates=4)
     p0 = tr.pol.params.clone()
