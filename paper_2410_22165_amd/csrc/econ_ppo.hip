@@ -128,6 +128,63 @@ __global__ void adv_stats_partial(const PpoBatchDev B, double* __restrict__ part
     }
 }
 
+// The same sums by one streaming pass over the whole batch, for minibatches
+// of at least 1/32 of it (a gathered row costs a whole cache line, a
+// streamed sample 4 bytes): sample s is epoch row j = ainv (s - c) mod Mtot
+// (ainv the inverse of a modulo Mtot) and belongs to the minibatch when
+// begin <= j < begin + rows.  Thread t visits s = t, t + T, ... (T threads
+// in the grid), so its row advances by the constant step = ainv T mod Mtot;
+// kc = ainv c mod Mtot.  Mtot < 2^31.  Fixed order per thread and per block.
+__global__ void adv_stats_stream(const PpoBatchDev B, uint32_t ainv, uint32_t kc, uint32_t step,
+                                 double* __restrict__ part)
+{
+    __shared__ double red[2][16];
+    const uint32_t M = (uint32_t)B.Mtot;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, T = gridDim.x * blockDim.x;
+    const uint32_t at = (uint32_t)(((uint64_t)t * ainv) % M);
+    uint32_t jr = at >= kc ? at - kc : at + (M - kc);
+    const uint32_t begin = (uint32_t)B.begin, rows = (uint32_t)B.rows;
+    double s1 = 0.0, s2 = 0.0;
+    // sixteen loads in flight per thread (1024 workgroups hold about 16 MB in
+    // flight); every sample is loaded: at 1/32 of the batch or more nearly
+    // every cache line holds a row of the minibatch
+    for (uint32_t base = t; base < M; base += 16 * T) {
+        float v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t sm = min(base + k * T, M - 1);  // clamped: the loads stay unconditional
+            v[k] = B.adv[(int64_t)sm * B.rstride + B.roff];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (jr - begin < rows && base + k * T < M) {
+                const double a = v[k];
+                s1 += a;
+                s2 += a * a;
+            }
+            jr += step;
+            jr = jr >= M ? jr - M : jr;
+        }
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        red[0][w] = s1;
+        red[1][w] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+            a += red[0][k];
+            b += red[1][k];
+        }
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
 // sums of n records of C doubles-or-floats by one 256-thread workgroup: thread
 // t takes records t, t + 256, ...; then a fixed wave and LDS tree (the same
 // order on every call, so the result is deterministic)
@@ -1512,6 +1569,44 @@ static int ppo_weight_grads_and_loss(const MlpDims& d, const PpoWorkspace& w, un
                                      const ej_ppo_hparams& hp, const float* d_params, const uint16_t* d_work,
                                      float* d_grads, float* d_loss, hipStream_t st);
 
+// a^-1 mod M by the extended Euclidean algorithm (0 < a < M); 0 when
+// gcd(a, M) > 1 (then j -> a j + c is no permutation and has no inverse)
+static uint64_t inverse_mod(int64_t a, int64_t M)
+{
+    int64_t r0 = M, r1 = a, t0 = 0, t1 = 1;
+    while (r1 != 0) {
+        const int64_t q = r0 / r1, r2 = r0 - q * r1, t2 = t0 - q * t1;
+        r0 = r1;
+        r1 = r2;
+        t0 = t1;
+        t1 = t2;
+    }
+    if (r0 != 1) return 0;
+    if (t0 < 0) t0 += M;
+    return (uint64_t)t0;
+}
+
+// the minibatch's advantage mean and 1 / (std + 1e-8) -> stats[0..1]:
+// gathered per row for small minibatches, streamed otherwise
+static void launch_adv_stats(const PpoBatchDev& B, double* part, float* stats, hipStream_t st)
+{
+    int nb;
+    const uint64_t ainv = B.Mtot > 1 ? inverse_mod(B.a, B.Mtot) : 0;
+    if (B.rows * 32 >= B.Mtot && ainv != 0 && B.Mtot < ((int64_t)1 << 31)) {
+        nb = (int)((B.Mtot + 4095) / 4096);
+        if (nb > 1024) nb = 1024;
+        const uint64_t M = (uint64_t)B.Mtot;
+        const uint32_t kc = (uint32_t)(ainv * (uint64_t)B.c % M);
+        const uint32_t step = (uint32_t)(ainv * ((uint64_t)nb * 256u) % M);
+        adv_stats_stream<<<nb, 256, 0, st>>>(B, (uint32_t)ainv, kc, step, part);
+    } else {
+        nb = (int)((B.rows + 255) / 256);
+        if (nb > 1024) nb = 1024;
+        adv_stats_partial<<<nb, 256, 0, st>>>(B, part);
+    }
+    adv_stats_final<<<1, 256, 0, st>>>(part, nb, B.rows, stats);
+}
+
 static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work,
                              const ej_ppo_batch* b, const ej_ppo_hparams* hp, void* d_workspace,
                              int64_t workspace_bytes, float* d_grads, float* d_loss, void* stream)
@@ -1543,11 +1638,7 @@ static int ppo_backward_impl(const ej_mlp_desc* m, const float* d_params, const 
     const int W = (m->A + 31) / 32;
     double* advp = (double*)(ws + w.o_adv);
     float* stats = (float*)(ws + w.o_stats);
-    int nb = (int)((b->rows + 255) / 256);
-    if (nb > 1024) nb = 1024;
-    adv_stats_partial<<<nb, 256, 0, st>>>(B, advp);
-    EJ_LAUNCH_CHECK();
-    adv_stats_final<<<1, 256, 0, st>>>(advp, nb, b->rows, stats);
+    launch_adv_stats(B, advp, stats, st);
     EJ_LAUNCH_CHECK();
     uint16_t* T[6] = {(uint16_t*)(ws + w.o_obs), (uint16_t*)(ws + w.o_h1), (uint16_t*)(ws + w.o_h2),
                       (uint16_t*)(ws + w.o_dy), (uint16_t*)(ws + w.o_dh2), (uint16_t*)(ws + w.o_dh1)};
@@ -1686,11 +1777,7 @@ int ej_gov_ppo_backward(const ej_mlp_desc* m, int32_t K, const float* d_params, 
     PpoHp h{hp->clip, hp->vclip, hp->vf_coef, hp->ent_coef};
     double* advp = (double*)(ws + w.o_adv);
     float* stats = (float*)(ws + w.o_stats);
-    int nb = (int)((b->rows + 255) / 256);
-    if (nb > 1024) nb = 1024;
-    adv_stats_partial<<<nb, 256, 0, st>>>(B, advp);
-    EJ_LAUNCH_CHECK();
-    adv_stats_final<<<1, 256, 0, st>>>(advp, nb, b->rows, stats);
+    launch_adv_stats(B, advp, stats, st);
     EJ_LAUNCH_CHECK();
     uint16_t* T[6] = {(uint16_t*)(ws + w.o_obs), (uint16_t*)(ws + w.o_h1), (uint16_t*)(ws + w.o_h2),
                       (uint16_t*)(ws + w.o_dy), (uint16_t*)(ws + w.o_dh2), (uint16_t*)(ws + w.o_dh1)};
