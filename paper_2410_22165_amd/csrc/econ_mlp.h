@@ -84,15 +84,34 @@ __device__ inline void zero_acc(f32x4 (&acc)[RT][CT])
         for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 }
 
+// Weight fragments are read through a buffer resource over the (uniform)
+// weight base: every lane keeps one 32-bit byte offset (its column l % 16
+// and k group l / 16) and the k-step and column-tile offsets are uniform
+// scalar offsets, so a fragment load costs no vector address arithmetic.
+// Raw buffer resource words for gfx9: no stride, 2^31 - 1 bytes of range,
+// 32-bit data format.
+__device__ inline __amdgpu_buffer_rsrc_t weight_rsrc(const uint16_t* base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7fffffff, 0x00020000);
+}
+
+__device__ inline bf16x8 buf_frag(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    typedef __attribute__((ext_vector_type(4))) unsigned int u32x4_t;
+    const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
 // One dense layer split by columns: the wave multiplies ALL TR x 16 rows of
 // `abuf` (row stride `as`) by its own CTW x 16 columns of the weights,
-// starting at column `col0`.  B fragments come straight from global memory
-// (L2-resident weights in the K-chunk layout: lane l reads the 16 bytes of
-// column l % 16, k = 8 (l / 16) .. + 7), PF k-steps ahead of the MFMAs;
-// A fragments come from LDS one k-step ahead.  Every A fragment feeds CTW
-// MFMAs and every B fragment TR, and no weight passes through LDS.  The
-// caller synchronises before (abuf complete) and after (before abuf is
-// overwritten).  ZERO = false accumulates onto acc.  TRANS swaps the MFMA
+// starting at column `col0` (the same on every lane of the wave).  B
+// fragments come straight from global memory (L2-resident weights in the
+// K-chunk layout: lane l reads the 16 bytes of column l % 16, k = 8 (l / 16)
+// .. + 7), PF k-steps ahead of the MFMAs; A fragments come from LDS one
+// k-step ahead.  Every A fragment feeds CTW MFMAs and every B fragment TR,
+// and no weight passes through LDS.  The caller synchronises before (abuf
+// complete) and after (before abuf is overwritten).  ZERO = false
+// accumulates onto acc, ZERO = true starts from zero.  TRANS swaps the MFMA
 // operands, which transposes each accumulator tile: lane l then holds row
 // l % 16 and the four adjacent columns 4 (l / 16) .. + 3 (instead of column
 // l % 16 of rows 4 (l / 16) .. + 3), so an epilogue stores 4 columns at once.
@@ -100,24 +119,25 @@ template <int TR, int CTW, int NK, bool ZERO = true, int PF = 2, bool PIN = fals
 __device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int as,
                                 const uint16_t* __restrict__ wglob, int64_t kstride, int col0)
 {
-    if constexpr (ZERO) zero_acc(acc);
     const int l = lane_id();
-    const uint16_t* bp = wglob + (int64_t)(col0 + (l & 15)) * 32 + 8 * (l >> 4);
+    const __amdgpu_buffer_rsrc_t wr = weight_rsrc(wglob);
+    const int voff = ((l & 15) * 32 + 8 * (l >> 4)) * 2;
+    const int c0 = __builtin_amdgcn_readfirstlane(col0), ks = (int)kstride;
+    auto soff = [&](int kt, int ct) { return (kt * ks + (c0 + ct * 16) * 32) * 2; };
     const uint16_t* ap = abuf + (l & 15) * as + 8 * (l >> 4);
     bf16x8 bq[NK][CTW];
     bf16x8 aq[NK][TR];
 #pragma unroll
     for (int p = 0; p < PF && p < NK; ++p)
 #pragma unroll
-        for (int ct = 0; ct < CTW; ++ct) bq[p][ct] = *(const bf16x8*)(bp + (int64_t)p * kstride + ct * 16 * 32);
+        for (int ct = 0; ct < CTW; ++ct) bq[p][ct] = buf_frag(wr, voff, soff(p, ct));
 #pragma unroll
     for (int rt = 0; rt < TR; ++rt) aq[0][rt] = lds_frag(ap + rt * 16 * as);
 #pragma unroll
     for (int kt = 0; kt < NK; ++kt) {
         if (kt + PF < NK)
 #pragma unroll
-            for (int ct = 0; ct < CTW; ++ct)
-                bq[kt + PF][ct] = *(const bf16x8*)(bp + (int64_t)(kt + PF) * kstride + ct * 16 * 32);
+            for (int ct = 0; ct < CTW; ++ct) bq[kt + PF][ct] = buf_frag(wr, voff, soff(kt + PF, ct));
         if (kt + 1 < NK)
 #pragma unroll
             for (int rt = 0; rt < TR; ++rt) aq[kt + 1][rt] = lds_frag(ap + rt * 16 * as + (kt + 1) * 32);
@@ -127,9 +147,10 @@ __device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int
 #pragma unroll
         for (int ct = 0; ct < CTW; ++ct)
 #pragma unroll
-            for (int rt = 0; rt < TR; ++rt)
-                acc[rt][ct] = TRANS ? mfma16(bq[kt][ct], aq[kt][rt], acc[rt][ct])
-                                    : mfma16(aq[kt][rt], bq[kt][ct], acc[rt][ct]);
+            for (int rt = 0; rt < TR; ++rt) {
+                const f32x4 c = (kt > 0 || !ZERO) ? acc[rt][ct] : f32x4{0.f, 0.f, 0.f, 0.f};
+                acc[rt][ct] = TRANS ? mfma16(bq[kt][ct], aq[kt][rt], c) : mfma16(aq[kt][rt], bq[kt][ct], c);
+            }
     }
 }
 
@@ -160,6 +181,20 @@ __device__ inline void bias_init_t(f32x4 (&acc)[TR][CTW], const float* __restric
     }
 }
 
+// ReLU of two fp32 values rounded to a packed bf16 pair: a bf16 with its sign
+// bit set is a negative 16-bit integer, so a signed 16-bit max with 0 clears
+// exactly the negative values (and -0).  Rounding keeps the sign, so this
+// equals rounding the ReLU of the fp32 values.
+__device__ inline uint32_t relu_bf16x2(float a, float b)
+{
+    typedef __attribute__((ext_vector_type(2))) float f32x2;
+    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+    typedef short __attribute__((ext_vector_type(2))) i16x2;
+    const bf16x2 r = __builtin_convertvector(f32x2{a, b}, bf16x2);  // one packed round-to-nearest-even
+    const i16x2 v = __builtin_elementwise_max(__builtin_bit_cast(i16x2, r), i16x2{0, 0});
+    return __builtin_bit_cast(uint32_t, v);
+}
+
 // ReLU of transposed accumulators (bias included), rounded to bf16: one
 // 8-byte store of 4 adjacent columns per tile
 template <int TR, int CTW>
@@ -171,11 +206,8 @@ __device__ inline void relu_store_t(const f32x4 (&acc)[TR][CTW], uint16_t* hbuf,
         const int col = col0 + ct * 16 + 4 * (l >> 4);
 #pragma unroll
         for (int rt = 0; rt < TR; ++rt) {
-            const float v0 = fmaxf(acc[rt][ct][0], 0.f), v1 = fmaxf(acc[rt][ct][1], 0.f);
-            const float v2 = fmaxf(acc[rt][ct][2], 0.f), v3 = fmaxf(acc[rt][ct][3], 0.f);
-            const uint2 pk = {(uint32_t)f32_to_bf16(v0) | ((uint32_t)f32_to_bf16(v1) << 16),
-                              (uint32_t)f32_to_bf16(v2) | ((uint32_t)f32_to_bf16(v3) << 16)};
-            *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) = pk;
+            *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) =
+                uint2{relu_bf16x2(acc[rt][ct][0], acc[rt][ct][1]), relu_bf16x2(acc[rt][ct][2], acc[rt][ct][3])};
         }
     }
 }

@@ -71,15 +71,20 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params_all, con
     const int wave = threadIdx.x >> 6, l = lane_id();
     const int64_t row0 = (int64_t)blockIdx.x * TILE;
 
-    // One Philox call gives the uniforms (u1, u2) of two chunks: lane j < RPW
-    // draws for the wave's row j.  The first pair is drawn here, under the
-    // latency of the tile loads.
+    // One Philox call gives the uniforms (u1, u2) of two chunks for one row.
+    // A single wave draws for the whole tile (lane j takes rows j, j + 64):
+    // the generator is ~450 vector instructions, whatever the number of
+    // active lanes.  The drawing wave rotates with the workgroup, so every
+    // SIMD gets its share.  The first pair is drawn here, under the latency
+    // of the tile loads; LDS barriers separate the draws from their readers.
+    const int draw_wave = (int)(blockIdx.x & 3);
     auto draw_uniforms = [&](int c) {
-        if (l < RPW) {
-            const int rl = wave * RPW + l;
-            u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row_base + grow(row0 + rl)), ctr, (uint64_t)(c >> 1), 0);
+        if (wave == draw_wave) {
+            for (int rl = l; rl < TILE; rl += 64) {
+                u64x4 w = philox(seed, PURPOSE_SAMPLE, (uint64_t)(row_base + grow(row0 + rl)), ctr, (uint64_t)(c >> 1), 0);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) urow[rl * 4 + k] = unif24(word_of(w, k));
+                for (int k = 0; k < 4; ++k) urow[rl * 4 + k] = unif24(word_of(w, k));
+            }
         }
     };
     draw_uniforms(0);
