@@ -195,23 +195,29 @@ policy_forward_kernel(const MlpDims d, const float* __restrict__ params_all, con
             uint32_t mw = wi < W ? smask[rloc * W + wi] : 0u;
             mw = nact >= 32 ? mw : (nact <= 0 ? 0u : mw & ((1u << nact) - 1u));
             const float u1 = urow[rloc * 4 + 2 * (c & 1)], u2 = urow[rloc * 4 + 2 * (c & 1) + 1];
-            // masked logits: -inf where not allowed
-            float zmax = NEG;
+            // masked logits -> MASKED, a finite stand-in for -inf (the
+            // network's logits are finite): exp(MASKED - ms) is exactly 0, and
+            // so is its product with MASKED - ms, so the weight and entropy
+            // sums below need no select.  Bit j of the mask word, spread to a
+            // whole word, picks the logit or MASKED (extract + bit insert).
+            constexpr float MASKED = -1e30f;
+            float zmax = MASKED;
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
-                z[j] = ((mw >> j) & 1u) ? z[j] : NEG;
+                const int keep = __builtin_amdgcn_sbfe((int)mw, j, 1);  // opaque to the select folding
+                z[j] = __int_as_float((__float_as_int(z[j]) & keep) | (__float_as_int(MASKED) & ~keep));
                 zmax = fmaxf(zmax, z[j]);
             }
             const float mc = quad_max(zmax);
-            const bool any = mc != NEG;
-            const float ms = any ? mc : 0.f;  // finite shift: exp(-inf - ms) = 0 for masked actions
+            const bool any = mc > MASKED;
+            const float ms = any ? mc : 0.f;
             // weights exp(z - mc), kept in z; their sum and sum of w (z - mc)
             float own = 0.f, tl = 0.f;
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
                 const float dz = z[j] - ms;
                 const float e = __expf(dz);
-                tl += e > 0.f ? e * dz : 0.f;
+                tl = __builtin_fmaf(e, dz, tl);
                 own += e;
                 z[j] = e;
             }
