@@ -246,17 +246,18 @@ __device__ inline void ppo_hidden_epilogue_cs(const f32x4 (&acc)[TR][CTW], const
         const float4 b = *(const float4*)(bias + col);
 #pragma unroll
         for (int rt = 0; rt < TR; ++rt) {
-            const float bb[4] = {b.x, b.y, b.z, b.w};
-            uint32_t h[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float x = acc[rt][ct][i] + bb[i];
-                bits[rt] |= (x > 0.f ? 1u : 0u) << (ct * 4 + i);
-                h[i] = f32_to_bf16(x > 0.f ? x : 0.f);
-            }
-            *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) = uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+            const float x0 = acc[rt][ct][0] + b.x, x1 = acc[rt][ct][1] + b.y;
+            const float x2 = acc[rt][ct][2] + b.z, x3 = acc[rt][ct][3] + b.w;
+            bits[rt] |= ((x0 > 0.f ? 1u : 0u) | (x1 > 0.f ? 2u : 0u) | (x2 > 0.f ? 4u : 0u) | (x3 > 0.f ? 8u : 0u))
+                        << (ct * 4);
+            *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) = uint2{relu_bf16x2(x0, x1), relu_bf16x2(x2, x3)};
         }
     }
+    // The words go through an identity lane move, which the compiler cannot
+    // see through: otherwise it keeps every comparison as a 64-bit lane mask
+    // in scalar registers until the backward's use and spills them.
+#pragma unroll
+    for (int rt = 0; rt < TR; ++rt) bits[rt] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits[rt], 0xE4, 0xF, 0xF, false);
 }
 
 // masked input gradient of a column-split layer (transposed accumulators, as
@@ -271,11 +272,13 @@ __device__ inline void ppo_masked_grad_cs(const f32x4 (&dh)[TR][CTW], const uint
         const int col = col0 + ct * 16 + 4 * (l >> 4);
 #pragma unroll
         for (int rt = 0; rt < TR; ++rt) {
-            const uint32_t m = bits[rt] >> (ct * 4);
-            const float v0 = (m & 1u) ? dh[rt][ct][0] : 0.f, v1 = (m & 2u) ? dh[rt][ct][1] : 0.f;
-            const float v2 = (m & 4u) ? dh[rt][ct][2] : 0.f, v3 = (m & 8u) ? dh[rt][ct][3] : 0.f;
-            const uint2 pk = {(uint32_t)f32_to_bf16(v0) | ((uint32_t)f32_to_bf16(v1) << 16),
-                              (uint32_t)f32_to_bf16(v2) | ((uint32_t)f32_to_bf16(v3) << 16)};
+            // bit 4 ct + i spread to a whole word keeps or clears the value
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                v[i] = __int_as_float(__float_as_int(dh[rt][ct][i]) & __builtin_amdgcn_sbfe((int)bits[rt], ct * 4 + i, 1));
+            const uint2 pk = {(uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16),
+                              (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16)};
             *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) = pk;
         }
     }
