@@ -181,17 +181,23 @@ __device__ inline void bias_init_t(f32x4 (&acc)[TR][CTW], const float* __restric
     }
 }
 
+// two fp32 values rounded to a packed bf16 pair (a in the low half) by one
+// packed round-to-nearest-even conversion
+__device__ inline uint32_t bf16x2_bits(float a, float b)
+{
+    typedef __attribute__((ext_vector_type(2))) float f32x2;
+    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
+
 // ReLU of two fp32 values rounded to a packed bf16 pair: a bf16 with its sign
 // bit set is a negative 16-bit integer, so a signed 16-bit max with 0 clears
 // exactly the negative values (and -0).  Rounding keeps the sign, so this
 // equals rounding the ReLU of the fp32 values.
 __device__ inline uint32_t relu_bf16x2(float a, float b)
 {
-    typedef __attribute__((ext_vector_type(2))) float f32x2;
-    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
     typedef short __attribute__((ext_vector_type(2))) i16x2;
-    const bf16x2 r = __builtin_convertvector(f32x2{a, b}, bf16x2);  // one packed round-to-nearest-even
-    const i16x2 v = __builtin_elementwise_max(__builtin_bit_cast(i16x2, r), i16x2{0, 0});
+    const i16x2 v = __builtin_elementwise_max(__builtin_bit_cast(i16x2, bf16x2_bits(a, b)), i16x2{0, 0});
     return __builtin_bit_cast(uint32_t, v);
 }
 

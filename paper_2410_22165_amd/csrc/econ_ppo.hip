@@ -277,9 +277,7 @@ __device__ inline void ppo_masked_grad_cs(const f32x4 (&dh)[TR][CTW], const uint
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 v[i] = __int_as_float(__float_as_int(dh[rt][ct][i]) & __builtin_amdgcn_sbfe((int)bits[rt], ct * 4 + i, 1));
-            const uint2 pk = {(uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16),
-                              (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16)};
-            *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) = pk;
+            *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) = uint2{bf16x2_bits(v[0], v[1]), bf16x2_bits(v[2], v[3])};
         }
     }
 }
@@ -305,11 +303,12 @@ __device__ inline void ppo_grad_to_mblocks(const f32x4 (&dh)[TR][CTW], const uin
 #pragma unroll
         for (int ct = 0; ct < CTW; ++ct) {
             const int sh = 4 * ct + (c & 3);
-            uint32_t h[4];
+            float v[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) h[i] = f32_to_bf16(((mk[i] >> sh) & 1u) ? dh[rt][ct][i] : 0.f);
+            for (int i = 0; i < 4; ++i)
+                v[i] = __int_as_float(__float_as_int(dh[rt][ct][i]) & __builtin_amdgcn_sbfe((int)mk[i], sh, 1));
             *(uint2*)(T + ((mb0 + (rt >> 1)) * ncol + col0 + 16 * ct + c) * 32 + 16 * (rt & 1) + 4 * g) =
-                uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+                uint2{bf16x2_bits(v[0], v[1]), bf16x2_bits(v[2], v[3])};
         }
     }
 }
@@ -510,6 +509,22 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
     const float NEG = -__builtin_huge_valf();
     const int srow = (wave & 3) * 16 + (l >> 2);
     const int a_taken = __float_as_int(rinfo[srow]);
+    // Masked logits become MASKED, a finite stand-in for -inf (the network's
+    // logits are finite): exp(MASKED - shift) is exactly 0 for any finite
+    // shift, and so is its product with any finite factor, so the sums and
+    // gradients below need no per-action select.  Bit j of the quarter's
+    // mask word, spread to a whole word, keeps the logit (extract + insert).
+    constexpr float MASKED = -1e30f;
+    auto mask_logit = [&](float zj, uint32_t mw, int j) {
+        const int keep = __builtin_amdgcn_sbfe((int)mw, j, 1);
+        return __int_as_float((__float_as_int(zj) & keep) | (__float_as_int(MASKED) & ~keep));
+    };
+    // allowed actions of this lane's quarter of chunk c (bits past the last action cleared)
+    auto quarter_mask = [&](int c) {
+        const int wi = c * 4 + q, nact = d.A - (c * 128 + 32 * q);
+        const uint32_t mw = wi < W ? smask[srow * W + wi] : 0u;
+        return nact >= 32 ? mw : (nact <= 0 ? 0u : mw & ((1u << nact) - 1u));
+    };
     auto logit_chunk = [&](int c) {
         f32x4 acc3[TR][LCT];
         dense_cs<TR, LCT, H / 32, true, 3, true, true>(acc3, hbuf, HS, work + d.oW3f + (int64_t)c * 128 * 32,
@@ -543,28 +558,28 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         if (rowner) {
         float z[32];
         load_row(z);
-        const int colq = c * 128 + 32 * q;
-        const int wi = c * 4 + q;
-        const uint32_t mw = wi < W ? smask[srow * W + wi] : 0u;
-        float zmax = NEG, zsel = 0.f, zval = 0.f;
+        const uint32_t mw = quarter_mask(c);
+        // the taken action's logit and the value head: one read each (the
+        // quad's four lanes read the same word)
+        const int ta = a_taken - c * 128, va = d.A - c * 128;
+        if (ta >= 0 && ta < 128) za += zbuf[srow * ZS + zcol(srow, ta)];
+        if (va >= 0 && va < 128) zv += zbuf[srow * ZS + zcol(srow, va)];
+        float zmax = MASKED;
 #pragma unroll
         for (int j = 0; j < 32; ++j) {
-            const bool ok = colq + j < d.A && ((mw >> j) & 1u);
-            zmax = ok ? fmaxf(zmax, z[j]) : zmax;
-            zsel = colq + j == a_taken ? z[j] : zsel;
-            zval = colq + j == d.A ? z[j] : zval;
+            z[j] = mask_logit(z[j], mw, j);
+            zmax = fmaxf(zmax, z[j]);
         }
         zmax = quad_max(zmax);
-        za += quad_sum(zsel);
-        zv += quad_sum(zval);
-        const bool any = zmax != NEG;
+        const bool any = zmax > MASKED;
+        const float zs = any ? zmax : 0.f;  // a finite shift: masked weights are exactly 0
         float se = 0.f, te = 0.f;
 #pragma unroll
         for (int j = 0; j < 32; ++j) {
-            const bool ok = colq + j < d.A && ((mw >> j) & 1u);
-            const float e = ok ? __expf(z[j] - zmax) : 0.f;
+            const float dz = z[j] - zs;
+            const float e = __expf(dz);
             se += e;
-            te += ok ? e * (z[j] - zmax) : 0.f;
+            te = __builtin_fmaf(e, dz, te);
         }
         se = quad_sum(se);
         te = quad_sum(te);
@@ -616,6 +631,13 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
 
     // ---- pass 2: dY = dL/d[logits | value] per chunk, dh2 += dY W3^T
     const float cent = hp.ent_coef * inv_n;
+    const float kq = cent * ent - cpg;
+    const float lse2 = valid ? lse : 0.f;  // rows without an allowed action: every weight exactly 0
+    // the taken action, when allowed: its gradient takes cpg more
+    const bool taken_ok = valid && a_taken >= 0 && a_taken < d.A &&
+                          ((smask[srow * W + (a_taken >> 5)] >> (a_taken & 31)) & 1u);
+    const float lp_taken = za - lse2;
+    const float g_taken = __expf(lp_taken) * __builtin_fmaf(cent, lp_taken, kq) + cpg;
     f32x4 dh[TR][CTW];
     for (int c = 0; c < d.NC; ++c) {
         if (d.NC > 1) {  // with one chunk its logits are still in LDS
@@ -627,22 +649,20 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
         if (rowner) {
         float z[32];
         load_row(z);
-        const int colq = c * 128 + 32 * q;
-        const int wi = c * 4 + q;
-        const uint32_t mw = wi < W ? smask[srow * W + wi] : 0u;
+        const uint32_t mw = quarter_mask(c);
+        // allowed action a: dL/dz_a = cpg ([a taken] - p_a) + cent p_a (lp_a + ent)
+        //                            = p_a (cent lp_a + kq) + cpg [a taken];
+        // the taken action's term and the value head are set below
 #pragma unroll
         for (int j = 0; j < 32; j += 2) {
             float g2[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int col = colq + j + h;
-                const bool ok = col < d.A && ((mw >> (j + h)) & 1u);
-                const float lp = z[j + h] - lse;
+                const float lp = mask_logit(z[j + h], mw, j + h) - lse2;
                 const float p = __expf(lp);
-                const float gg = cpg * ((col == a_taken ? 1.f : 0.f) - p) + cent * p * (lp + ent);
-                g2[h] = ok ? gg : (col == d.A ? dzv : 0.f);
+                g2[h] = p * __builtin_fmaf(cent, lp, kq);
             }
-            gp[j >> 1] = f32_to_bf16(g2[0]) | (f32_to_bf16(g2[1]) << 16);
+            gp[j >> 1] = bf16x2_bits(g2[0], g2[1]);
         }
         }  // rowner
         lds_barrier();  // every lane has read its logits: the chunk's space takes dY
@@ -650,6 +670,11 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
             uint4* yrow = (uint4*)(ybuf + srow * YS + 32 * q);  // 16-byte stores: no bank conflicts
 #pragma unroll
             for (int j = 0; j < 4; ++j) yrow[j] = uint4{gp[4 * j], gp[4 * j + 1], gp[4 * j + 2], gp[4 * j + 3]};
+            // after the row's stores (LDS keeps a wave's order): the taken
+            // action's gradient and the value head's
+            const int ta = a_taken - c * 128, va = d.A - c * 128;
+            if (q == 0 && taken_ok && ta >= 0 && ta < 128) ybuf[srow * YS + ta] = f32_to_bf16(g_taken);
+            if (q == 0 && va >= 0 && va < 128) ybuf[srow * YS + va] = f32_to_bf16(dzv);
         }
         lds_barrier();
         tile_to_mblocks(ybuf, YS, TILE, 128, TdY, mb0, d.A1p, c * 128);  // dY for dW3
