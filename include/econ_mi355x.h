@@ -292,7 +292,8 @@ int ej_mlp_sync_weights(const ej_mlp_desc* m, const float* d_params, uint16_t* d
  * uniforms after each ej_counter_add).  row_base >= 0 numbers the rows when
  * the pointers address a slice of a larger batch: slices drawn separately
  * give exactly the results of one call over the whole batch.  Logits are
- * never written to memory unless d_logits is given. */
+ * never written to memory unless d_logits is given.  A row whose mask allows
+ * no action gets action 0, log-probability 0 and entropy 0. */
 int ej_policy_forward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const uint16_t* d_obs,
                       const uint32_t* d_mask, int64_t M, int64_t row_base, uint64_t seed, uint64_t ctr,
                       const uint64_t* d_ctr_base, int32_t* d_act, float* d_logp, float* d_val, float* d_ent,
@@ -397,7 +398,10 @@ int ej_ppo_pack(const ej_mlp_desc* m, const ej_ppo_batch* b, void* d_records, vo
  * accumulated); d_loss [5] receives the mean surrogate, value and entropy
  * terms, the clipped fraction, and the minibatch loss L itself.  d_workspace: caller-owned device scratch of at
  * least ej_ppo_workspace_size bytes.  Deterministic: the weight gradients
- * are reduced over a fixed split in a fixed order. */
+ * are reduced over a fixed split in a fixed order.  The taken action must be
+ * allowed by its row's mask; a row whose mask allows no action adds nothing
+ * to L or the gradients (it still counts in the means and the advantage
+ * statistics). */
 int ej_ppo_backward(const ej_mlp_desc* m, const float* d_params, const uint16_t* d_work, const ej_ppo_batch* b,
                     const ej_ppo_hparams* hp, void* d_workspace, int64_t workspace_bytes, float* d_grads,
                     float* d_loss, void* stream);

@@ -268,3 +268,32 @@ def test_sparse_masks_single_actions_and_empty_chunks():
     safe = margin > 1e-4
     assert safe.mean() > 0.97, safe.mean()  # about 1 - 2e-4 per near-threshold candidate
     assert np.array_equal(g["act"][safe], a_o[safe]), np.flatnonzero(g["act"][safe] != a_o[safe])[:10]
+
+
+@pytest.mark.parametrize("A", [125, 507])
+def test_rows_without_allowed_actions(A):
+    """A row whose mask allows no action gets action 0, log-probability 0
+    and entropy 0 (its value head is still computed), and the other rows
+    are bit for bit those of the same call with that row's mask full."""
+    import torch
+    from paper_2410_22165_amd import binding
+    D, Ds, H, M = 35, 40, 256, 300
+    mlp = binding.Mlp(D, Ds, H, A, W.policy_weights(D, H, A, seed=4))
+    obs = torch.from_numpy(W.synthetic_obs(M, D, Ds, 4).view(np.int16)).cuda()
+    masks = W.synthetic_masks(M, A, 4)
+    empty = np.zeros(M, bool)
+    empty[[0, 63, 64, 130, 299]] = True
+    cut = masks.copy()
+    cut[empty] = 0
+    outs = []
+    for mk in (masks, cut):
+        o = [torch.zeros(M, dtype=torch.int32, device="cuda")] + [torch.zeros(M, device="cuda") for _ in range(3)]
+        mlp.forward(obs, torch.from_numpy(mk.view(np.int32)).cuda(), M, 9, 2, *o)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy() for t in o])
+    (act0, lp0, val0, ent0), (act1, lp1, val1, ent1) = outs
+    assert (act1[empty] == 0).all() and (lp1[empty] == 0).all() and (ent1[empty] == 0).all()
+    assert np.array_equal(val1, val0)
+    keep = ~empty
+    for x, y in ((act0, act1), (lp0, lp1), (ent0, ent1)):
+        assert np.array_equal(x[keep], y[keep])

@@ -235,6 +235,30 @@ def test_ppo_backward_matches_reference_autograd(case):
     assert abs(loss[4] - l_o) <= 1e-3 * max(1.0, abs(l_o))
 
 
+def test_rows_without_allowed_actions_contribute_nothing():
+    """Rows whose mask allows no action (policy and entropy undefined) add
+    nothing to the loss terms or the gradients, whatever their observation,
+    action, old log-probability, old value and return: two batches that differ
+    only there give bit-identical, finite results.  Their advantages stay (the
+    minibatch statistics count every row)."""
+    D, Ds, H, A, M = 35, 40, 256, 125, 3000
+    w, st = make_storage(D, Ds, H, A, M, seed=5)
+    empty = np.random.default_rng(7).random(M) < 0.1
+    st["mask"][empty] = 0
+    other = make_storage(D, Ds, H, A, M, seed=6)[1]
+    st2 = {k: v.copy() for k, v in st.items()}
+    for k in ("obs", "act", "logp_old", "val_old", "ret"):
+        st2[k][empty] = other[k][empty]
+    a, c = W.affine_permutation(M, epoch=0, seed=3)
+    rows = 1200
+    idx = (a * np.arange(rows) + c) % M
+    assert empty[idx].sum() > 50
+    _, g1, l1 = gpu_backward(w, st, D, Ds, H, A, M, a, c, 0, rows)
+    _, g2, l2 = gpu_backward(w, st2, D, Ds, H, A, M, a, c, 0, rows)
+    assert np.isfinite(g1).all() and np.isfinite(l1).all()
+    assert np.array_equal(g1, g2) and np.array_equal(l1, l2)
+
+
 @pytest.mark.parametrize("case", [(35, 40, 256, 125, 64000, 40000), (35, 40, 64, 125, 330000, 300000)])
 def test_ppo_backward_many_mblocks_per_split(case):
     """Minibatches large enough that every weight-gradient split accumulates
