@@ -821,14 +821,8 @@ dw_kernel(const uint16_t* __restrict__ Tx, int J, const uint16_t* __restrict__ T
                 f32x4 h = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kt = 0; kt < NK1; ++kt) h = mfma16(oq[r][kt], w1q[a][kt], h);
-                uint32_t hb[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float x = h[e] + b1v[a];
-                    hb[e] = f32_to_bf16(x > 0.f ? x : 0.f);
-                }
                 *(uint2*)(xs + ((t >> 1) * 16 + (l & 15)) * WSTRIDE + (t & 1) * 16 + 4 * (l >> 4)) =
-                    uint2{hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16)};
+                    uint2{relu_bf16x2(h[0] + b1v[a], h[1] + b1v[a]), relu_bf16x2(h[2] + b1v[a], h[3] + b1v[a])};
             }
         }
         if (p0 < PY) *(uint4*)(ys + (p0 >> 2) * WSTRIDE + (p0 & 3) * 8) = ry0;
@@ -847,10 +841,18 @@ dw_kernel(const uint16_t* __restrict__ Tx, int J, const uint16_t* __restrict__ T
 #pragma unroll
             for (int a = 0; a < TJ; ++a) acc[a][b] = mfma16(af[a], bf, acc[a][b]);
         }
-        if (jt == 0 && (int)threadIdx.x < CN) {
-            const uint16_t* yrow = ys + threadIdx.x * WSTRIDE;
+        if (jt == 0 && (int)threadIdx.x < CN) {  // column sums of Y (the bias gradient): 16-byte reads
+            const uint4* yrow = (const uint4*)(ys + threadIdx.x * WSTRIDE);
 #pragma unroll
-            for (int m = 0; m < 32; ++m) cs += bf16_to_f32(yrow[m]);
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const uint4 v = yrow[q4];
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    cs += __uint_as_float(w[e] << 16);
+                    cs += __uint_as_float(w[e] & 0xffff0000u);
+                }
+            }
         }
     };
     // m-block mb sits in stage s and the registers hold m-block mb + 1: run
