@@ -110,14 +110,15 @@ __device__ inline bf16x8 buf_frag(__amdgpu_buffer_rsrc_t r, int voff, int soff)
 // .. + 7), PF k-steps ahead of the MFMAs; A fragments come from LDS one
 // k-step ahead.  Every A fragment feeds CTW MFMAs and every B fragment TR,
 // and no weight passes through LDS.  The caller synchronises before (abuf
-// complete) and after (before abuf is overwritten).  ZERO = false
-// accumulates onto acc, ZERO = true starts from zero.  TRANS swaps the MFMA
+// complete) and after (before abuf is overwritten).  The first k-step's
+// accumulator input is, by CM: 0 acc itself (accumulate), 1 zero, 2 cb[ct]
+// (the same vector for every row tile: a bias).  TRANS swaps the MFMA
 // operands, which transposes each accumulator tile: lane l then holds row
 // l % 16 and the four adjacent columns 4 (l / 16) .. + 3 (instead of column
 // l % 16 of rows 4 (l / 16) .. + 3), so an epilogue stores 4 columns at once.
-template <int TR, int CTW, int NK, bool ZERO = true, int PF = 2, bool PIN = false, bool TRANS = false>
-__device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int as,
-                                const uint16_t* __restrict__ wglob, int64_t kstride, int col0)
+template <int TR, int CTW, int NK, int CM, int PF, bool PIN, bool TRANS>
+__device__ inline void dense_core(f32x4 (&acc)[TR][CTW], const f32x4* cb, const uint16_t* abuf, int as,
+                                  const uint16_t* __restrict__ wglob, int64_t kstride, int col0)
 {
     const int l = lane_id();
     const __amdgpu_buffer_rsrc_t wr = weight_rsrc(wglob);
@@ -148,10 +149,27 @@ __device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int
         for (int ct = 0; ct < CTW; ++ct)
 #pragma unroll
             for (int rt = 0; rt < TR; ++rt) {
-                const f32x4 c = (kt > 0 || !ZERO) ? acc[rt][ct] : f32x4{0.f, 0.f, 0.f, 0.f};
+                const f32x4 c = (kt > 0 || CM == 0) ? acc[rt][ct] : (CM == 1 ? f32x4{0.f, 0.f, 0.f, 0.f} : cb[ct]);
                 acc[rt][ct] = TRANS ? mfma16(bq[kt][ct], aq[kt][rt], c) : mfma16(aq[kt][rt], bq[kt][ct], c);
             }
     }
+}
+
+// ZERO = false accumulates onto acc, ZERO = true starts from zero
+template <int TR, int CTW, int NK, bool ZERO = true, int PF = 2, bool PIN = false, bool TRANS = false>
+__device__ inline void dense_cs(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int as,
+                                const uint16_t* __restrict__ wglob, int64_t kstride, int col0)
+{
+    dense_core<TR, CTW, NK, ZERO ? 1 : 0, PF, PIN, TRANS>(acc, nullptr, abuf, as, wglob, kstride, col0);
+}
+
+// started at the bias: cb[ct] is the accumulator input of the first k-step
+// (16 more live registers than dense_cs during that step)
+template <int TR, int CTW, int NK, int PF = 2, bool PIN = false, bool TRANS = false>
+__device__ inline void dense_cs_bias(f32x4 (&acc)[TR][CTW], const f32x4 (&cb)[CTW], const uint16_t* abuf, int as,
+                                     const uint16_t* __restrict__ wglob, int64_t kstride, int col0)
+{
+    dense_core<TR, CTW, NK, 2, PF, PIN, TRANS>(acc, cb, abuf, as, wglob, kstride, col0);
 }
 
 // The first layer: K1p = 64 or 128 input columns, two or four k-steps
@@ -163,6 +181,17 @@ __device__ inline void dense_first(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, 
         dense_cs<TR, CTW, K1P / 32, ZERO, PF, PIN, TRANS>(acc, abuf, as, wglob, kstride, col0);
     else
         dense_cs<TR, CTW, K1P_WIDE / 32, ZERO, PF, PIN, TRANS>(acc, abuf, as, wglob, kstride, col0);
+}
+
+// the first layer started at the bias (dense_cs_bias)
+template <int TR, int CTW, int PF, bool PIN, bool TRANS>
+__device__ inline void dense_first_bias(f32x4 (&acc)[TR][CTW], const f32x4 (&cb)[CTW], const uint16_t* abuf, int as,
+                                        const uint16_t* __restrict__ wglob, int64_t kstride, int col0, int K1p)
+{
+    if (K1p == K1P)
+        dense_cs_bias<TR, CTW, K1P / 32, PF, PIN, TRANS>(acc, cb, abuf, as, wglob, kstride, col0);
+    else
+        dense_cs_bias<TR, CTW, K1P_WIDE / 32, PF, PIN, TRANS>(acc, cb, abuf, as, wglob, kstride, col0);
 }
 
 // Transposed accumulators (dense_cs with TRANS) started at the bias: lane

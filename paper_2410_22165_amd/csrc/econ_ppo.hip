@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(256) adv_stats_final(const double* __restrict_
 // layer and source of the m-block copy), one 8-byte store per tile, and the
 // ReLU pattern of the lane's columns (bit 4 ct + i of bits[rt]) for the
 // backward, whose products use the same layout
-template <int TR, int CTW>
+template <int TR, int CTW, bool ADD_BIAS = true>
 __device__ inline void ppo_hidden_epilogue_cs(const f32x4 (&acc)[TR][CTW], const float* __restrict__ bias,
                                               uint16_t* hbuf, int hs, int col0, uint32_t (&bits)[TR])
 {
@@ -243,11 +243,13 @@ __device__ inline void ppo_hidden_epilogue_cs(const f32x4 (&acc)[TR][CTW], const
 #pragma unroll
     for (int ct = 0; ct < CTW; ++ct) {
         const int col = col0 + ct * 16 + 4 * (l >> 4);
-        const float4 b = *(const float4*)(bias + col);
+        const float4 b = ADD_BIAS ? *(const float4*)(bias + col) : float4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int rt = 0; rt < TR; ++rt) {
-            const float x0 = acc[rt][ct][0] + b.x, x1 = acc[rt][ct][1] + b.y;
-            const float x2 = acc[rt][ct][2] + b.z, x3 = acc[rt][ct][3] + b.w;
+            const float x0 = ADD_BIAS ? acc[rt][ct][0] + b.x : acc[rt][ct][0];
+            const float x1 = ADD_BIAS ? acc[rt][ct][1] + b.y : acc[rt][ct][1];
+            const float x2 = ADD_BIAS ? acc[rt][ct][2] + b.z : acc[rt][ct][2];
+            const float x3 = ADD_BIAS ? acc[rt][ct][3] + b.w : acc[rt][ct][3];
             bits[rt] |= ((x0 > 0.f ? 1u : 0u) | (x1 > 0.f ? 2u : 0u) | (x2 > 0.f ? 4u : 0u) | (x3 > 0.f ? 8u : 0u))
                         << (ct * 4);
             *(uint2*)(hbuf + (rt * 16 + (l & 15)) * hs + col) = uint2{relu_bf16x2(x0, x1), relu_bf16x2(x2, x3)};
@@ -491,15 +493,25 @@ ppo_rows_kernel(const MlpDims d, const float* __restrict__ params, const uint16_
 
     // ---- forward of the hidden layers (column split); every layer's bf16
     // output also leaves as m-blocks for the weight gradients
-    f32x4 acc[TR][CTW];
+    // (the first k-step of each layer takes the bias as its accumulator input)
+    f32x4 acc[TR][CTW], cb[CTW];
     uint32_t m1[TR], m2[TR];
-    dense_first<TR, CTW, true, 2, true, true>(acc, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0, d.K1p);
+    auto bias_frags = [&](const float* bias) {
+#pragma unroll
+        for (int ct = 0; ct < CTW; ++ct) {
+            const float4 b = *(const float4*)(bias + col0 + ct * 16 + 4 * (l >> 4));
+            cb[ct] = f32x4{b.x, b.y, b.z, b.w};
+        }
+    };
+    bias_frags(sbias);
+    dense_first_bias<TR, CTW, 2, true, true>(acc, cb, hbuf, HS, work + d.oW1f, (int64_t)H * 32, col0, d.K1p);
     lds_barrier();  // every wave is done reading the observations
-    ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias, hbuf, HS, col0, m1);
+    ppo_hidden_epilogue_cs<TR, CTW, false>(acc, nullptr, hbuf, HS, col0, m1);
+    bias_frags(sbias + H);
     lds_barrier();
-    dense_cs<TR, CTW, H / 32, true, 3, true, true>(acc, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
+    dense_cs_bias<TR, CTW, H / 32, 3, true, true>(acc, cb, hbuf, HS, work + d.oW2f, (int64_t)H * 32, col0);
     lds_barrier();
-    ppo_hidden_epilogue_cs<TR, CTW>(acc, sbias + H, hbuf, HS, col0, m2);
+    ppo_hidden_epilogue_cs<TR, CTW, false>(acc, nullptr, hbuf, HS, col0, m2);
     lds_barrier();
     tile_to_mblocks(hbuf, HS, TILE, H, Th2, mb0, H, 0);
 
