@@ -75,15 +75,6 @@ __device__ inline f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-template <int RT, int CT>
-__device__ inline void zero_acc(f32x4 (&acc)[RT][CT])
-{
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-}
-
 // Weight fragments are read through a buffer resource over the (uniform)
 // weight base: every lane keeps one 32-bit byte offset (its column l % 16
 // and k group l / 16) and the k-step and column-tile offsets are uniform
@@ -172,18 +163,8 @@ __device__ inline void dense_cs_bias(f32x4 (&acc)[TR][CTW], const f32x4 (&cb)[CT
     dense_core<TR, CTW, NK, 2, PF, PIN, TRANS>(acc, cb, abuf, as, wglob, kstride, col0);
 }
 
-// The first layer: K1p = 64 or 128 input columns, two or four k-steps
-template <int TR, int CTW, bool ZERO, int PF, bool PIN, bool TRANS>
-__device__ inline void dense_first(f32x4 (&acc)[TR][CTW], const uint16_t* abuf, int as,
-                                   const uint16_t* __restrict__ wglob, int64_t kstride, int col0, int K1p)
-{
-    if (K1p == K1P)
-        dense_cs<TR, CTW, K1P / 32, ZERO, PF, PIN, TRANS>(acc, abuf, as, wglob, kstride, col0);
-    else
-        dense_cs<TR, CTW, K1P_WIDE / 32, ZERO, PF, PIN, TRANS>(acc, abuf, as, wglob, kstride, col0);
-}
-
-// the first layer started at the bias (dense_cs_bias)
+// The first layer (K1p = 64 or 128 input columns: two or four k-steps),
+// started at the bias (dense_cs_bias)
 template <int TR, int CTW, int PF, bool PIN, bool TRANS>
 __device__ inline void dense_first_bias(f32x4 (&acc)[TR][CTW], const f32x4 (&cb)[CTW], const uint16_t* abuf, int as,
                                         const uint16_t* __restrict__ wglob, int64_t kstride, int col0, int K1p)
