@@ -297,3 +297,43 @@ def test_rows_without_allowed_actions(A):
     keep = ~empty
     for x, y in ((act0, act1), (lp0, lp1), (ent0, ent1)):
         assert np.array_equal(x[keep], y[keep])
+
+
+@pytest.mark.parametrize("A", [125, 507])
+def test_peaked_distributions(A):
+    """Head weights scaled by 300, so that the logits spread over hundreds of
+    units and every allowed weight but the largest underflows to 0 in fp32
+    (within the chunk and across the chunks' reservoir).  The draw is the
+    best allowed action wherever its margin over the runner-up exceeds the
+    bf16 rounding of the logits; with a margin above 30 its log-probability
+    and the entropy are 0 to within 1e-3; the value column is not scaled and
+    stays within 2e-2."""
+    import torch
+    from paper_2410_22165_amd import binding
+    D, Ds, H, M = 35, 40, 256, 400
+    print(f"[gpu] peaked policy A={A} M={M}", flush=True)
+    w = W.policy_weights(D, H, A, seed=9)
+    w["W3"] = w["W3"].copy()
+    w["W3"][:, :A] *= 300.0
+    mlp = binding.Mlp(D, Ds, H, A, w)
+    obs = W.synthetic_obs(M, D, Ds, seed=9)
+    mask = W.synthetic_masks(M, A, seed=9)
+    o = [torch.zeros(M, dtype=torch.int32, device="cuda")] + [torch.zeros(M, device="cuda") for _ in range(3)]
+    mlp.forward(torch.from_numpy(obs.view(np.int16)).cuda(), torch.from_numpy(mask.view(np.int32)).cuda(), M,
+                5, 1, *o)
+    torch.cuda.synchronize()
+    act, logp, val, ent = (t.cpu().numpy() for t in o)
+    x = oe.bf16_bits_to_f32(obs[:, :D]).astype(np.float64)
+    logits, value = op.mlp(x, op.bf16_weights(w), bf16_hidden=True)
+    allowed = op.unpack_mask(mask, A)
+    z = np.where(allowed, logits, -np.inf)
+    best = np.argmax(z, axis=1)
+    top2 = -np.sort(-z, axis=1)[:, :2]
+    gap = top2[:, 0] - top2[:, 1]
+    clear = gap > 0.01 * np.abs(z[np.isfinite(z)]).max() + 1.0
+    assert clear.mean() > 0.5
+    assert np.array_equal(act[clear], best[clear])
+    wide = gap > 30.0
+    assert wide.sum() > 20
+    assert np.abs(logp[wide]).max() <= 1e-3 and np.abs(ent[wide]).max() <= 1e-3
+    assert np.abs(val - value).max() <= 2e-2

@@ -259,6 +259,32 @@ def test_rows_without_allowed_actions_contribute_nothing():
     assert np.array_equal(g1, g2) and np.array_equal(l1, l2)
 
 
+@pytest.mark.parametrize("A", [125, 507])
+def test_peaked_policy_backward_is_finite(A):
+    """Head weights scaled by 300 (logits over hundreds of units: every
+    allowed weight but the largest underflows to 0 in fp32, in one chunk and
+    across four): gradients and loss terms stay finite, and the surrogate,
+    value and entropy terms equal the reference's (bf16 hidden activations,
+    as in the kernel)."""
+    D, Ds, H, M = 35, 40, 256, 3000
+    w, st = make_storage(D, Ds, H, A, M, seed=8)
+    w["W3"] = w["W3"].copy()
+    w["W3"][:, :A] *= 300.0
+    a, c = W.affine_permutation(M, epoch=0, seed=4)
+    rows = 1500
+    _, g, loss = gpu_backward(w, st, D, Ds, H, A, M, a, c, 0, rows)
+    assert np.isfinite(g).all() and np.isfinite(loss).all()
+    idx = (a * np.arange(rows) + c) % M
+    sub = {k: v[idx] for k, v in st.items()}
+    x = oe.bf16_bits_to_f32(sub["obs"][:, :D]).astype(np.float64)
+    _, terms, _ = op.ppo_grads(w, x, sub["mask"], sub["act"], sub["logp_old"], sub["val_old"], sub["adv"],
+                               sub["ret"], HP, bf16_hidden=True)
+    print("loss terms", loss[:3], terms["pg"], terms["vf"], terms["ent"], flush=True)
+    assert abs(loss[0] - terms["pg"]) <= 1e-3 * max(1.0, abs(terms["pg"]))
+    assert abs(loss[1] - terms["vf"]) <= 1e-3 * max(1.0, abs(terms["vf"]))
+    assert abs(loss[2] - terms["ent"]) <= 1e-3
+
+
 @pytest.mark.parametrize("case", [(35, 40, 256, 125, 64000, 40000), (35, 40, 64, 125, 330000, 300000)])
 def test_ppo_backward_many_mblocks_per_split(case):
     """Minibatches large enough that every weight-gradient split accumulates
