@@ -357,12 +357,13 @@ def test_episode_metrics_match_oracle(variant):
     env.close()
 
 
-@pytest.mark.parametrize("R", [4, 8, 12])
+@pytest.mark.parametrize("R", [4, 8, 12, 16])
 def test_parity_multi_agent_variant_lockstep(R):
     """The multi-agent variant (Sec. 5): skills near 1 with spread 1 that
     grow with every gather and craft, taxes off, prices 3, 6, 9, R_d from R;
     state (skills included), rewards, observations and masks against the
-    oracle after every step, over an episode end (new skills drawn)."""
+    oracle after every step, over an episode end (new skills drawn).  R = 16
+    is the largest resource count (114 actions, 122-feature observations)."""
     cfg = W.variant_config(R=R, N=23, E=3, X=7, T=35, seed=4)
     run_lockstep(cfg, 50, actions="masked", seed=R, n_per_env=[23, 9, 16])
 

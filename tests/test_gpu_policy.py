@@ -23,6 +23,7 @@ CASES = [  # (D, Ds, H, A, M)
     (64, 64, 256, 1000, 200),      # 64 features and 8 action chunks
     (91, 96, 256, 86, 500),        # 12-resource multi-agent economy: a 128-column first layer
     (128, 128, 512, 300, 129),     # widest input (128 features)
+    (122, 128, 256, 114, 300),     # 16-resource multi-agent economy (the largest resource count)
 ]
 
 
