@@ -197,7 +197,8 @@ def assert_elementwise(got, want, B, rtol=1e-2, floor=2.0 ** -7, where=""):
 @pytest.mark.parametrize("case", [(35, 40, 256, 125, 3000, 1000, 10.0), (11, 16, 64, 9, 500, 77, 10.0),
                                   (49, 56, 512, 507, 1200, 300, 10.0), (64, 64, 128, 300, 700, 700, 10.0),
                                   (35, 40, 256, 125, 3000, 1000, 0.2), (49, 56, 512, 507, 1200, 300, 0.2),
-                                  (91, 96, 256, 86, 2000, 700, 10.0), (35, 40, 256, 125, 8000, 120, 10.0)])
+                                  (91, 96, 256, 86, 2000, 700, 10.0), (122, 128, 256, 114, 2000, 700, 0.2),
+                                  (35, 40, 256, 125, 8000, 120, 10.0)])
 def test_ppo_backward_matches_reference_autograd(case):
     """Every gradient element against the float64 reference autograd at
     1e-2 relative plus the bf16 floor 2^-7 B (reference_with_bounds), on
@@ -205,7 +206,8 @@ def test_ppo_backward_matches_reference_autograd(case):
     bind on most rows; ratio noise puts a share of rows outside the
     surrogate clip.  The advantage statistics take the streaming pass for
     minibatches of at least 1/32 of the batch and the per-row gather below
-    (the last case)."""
+    (the last case).  The 122 -> 256 -> 256 -> 114 + 1 network is the
+    16-resource variant's."""
     D, Ds, H, A, M_gen, rows, vclip = case
     hp = dict(HP, vclip=vclip)
     w, st, ratio = kink_free_storage(D, Ds, H, A, M_gen, seed=rows, hp=hp)
