@@ -333,14 +333,19 @@ __device__ inline void tile_to_mblocks(const uint16_t* tile, int hs, int rows, i
 #pragma unroll
         for (int k = 0; k < 8; ++k) v[k] = *(const uint2*)(tile + (blk * 32 + qq * 8 + k) * hs + 4 * g);
         uint16_t* dst = T + ((mb0 + blk) * ncol_total + col_off + 4 * g) * 32 + qq * 8;
+        // column 4 g + j of rows 2 k, 2 k + 1: the (j & 1) half of word j / 2
+        // of each, packed by one byte permute (low halves 0x05040100, high
+        // halves 0x07060302; bytes 0-3 of the selection come from the second
+        // operand)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
+            const uint32_t sel = (j & 1) ? 0x07060302u : 0x05040100u;
             uint32_t w[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const uint32_t lo = (j < 2 ? v[2 * k].x : v[2 * k].y) >> (16 * (j & 1));
-                const uint32_t hi = (j < 2 ? v[2 * k + 1].x : v[2 * k + 1].y) >> (16 * (j & 1));
-                w[k] = (lo & 0xFFFFu) | (hi << 16);
+                const uint32_t lo = j < 2 ? v[2 * k].x : v[2 * k].y;
+                const uint32_t hi = j < 2 ? v[2 * k + 1].x : v[2 * k + 1].y;
+                w[k] = __builtin_amdgcn_perm(hi, lo, sel);
             }
             *(uint4*)(dst + j * 32) = uint4{w[0], w[1], w[2], w[3]};
         }
